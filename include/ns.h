@@ -1,0 +1,288 @@
+/*
+ * ns.h -- C ABI of libns.so, an MI355X (gfx950) implementation of the batched
+ * nested sampler of "Fast and efficient nested sampling with BEST"
+ * (arXiv 2608.28514).
+ *
+ * The problem (Sec. 1, Eq. (1)): compute the evidence Z = int_0^1 L(X) dX of a
+ * likelihood L under a uniform prior on a box [lo, hi], by keeping N live
+ * points and repeatedly replacing the worst ones with points of higher
+ * likelihood.  One call of ns_step_batch(m) replaces m live points at once
+ * (Sec. 3): the m worst are selected by sorting (Algorithm 1), m slice-sampling
+ * chains run under the hard constraints L > L_W[j] (Sec. 2.2) with directions
+ * whitened by the covariance of the seed's k-means cluster (Sec. 2.1), and the
+ * batch is corrected by batch sorting (Algorithm 1) or the history correction
+ * (Algorithm 2).  Dead points enter a single-point evidence integration in FP64.
+ *
+ * Conventions common to every call:
+ *  - Every call returns ns_status; a negative value is an error and leaves the
+ *    context as it was; ns_last_error(ctx) describes it until the next call.
+ *  - Host pointers (const double* lo, likelihood parameters, ...) are read
+ *    during the call and copied; the caller keeps ownership.
+ *  - Device pointers (arguments named d_*) must point to device memory of the
+ *    current HIP device, sized as stated; the library never frees them.
+ *  - All device work of a context runs on one HIP stream (the one given to
+ *    ns_init, or an own default-priority stream when NULL).  Only ns_logZ,
+ *    ns_sync and the ns_get_* getters synchronise that stream.
+ *  - Points are stored in unit-cube coordinates u in [0,1]^d, theta = lo +
+ *    (hi - lo) u.  Arrays of points are row major: point k occupies
+ *    [k*d, (k+1)*d).
+ *  - A context is not thread safe; distinct contexts are independent.
+ *  - Limits: 1 <= d <= 32, 2 <= N <= 8192, 1 <= m <= min(N-1, 1024),
+ *    tree_depth <= 6, hist_cap in [2, 64], lo < hi elementwise.
+ */
+#ifndef NS_H
+#define NS_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ns_ctx ns_ctx; /* opaque; created by ns_init, owned by the library */
+
+typedef enum {
+  NS_OK = 0,
+  NS_DONE = 1,        /* the stopping rule holds; further steps are no-ops        */
+  NS_EINVAL = -1,     /* invalid argument                                         */
+  NS_ENOMEM = -2,     /* device or host allocation failed                         */
+  NS_EDEVICE = -3,    /* a HIP call failed                                        */
+  NS_ESTATE = -4,     /* call not valid in the context's state                    */
+  NS_ENUMERIC = -5    /* non-finite value where none is allowed                   */
+} ns_status;
+
+/* NS_BF16: bfloat16 MFMA operands, FP32 accumulation.  NS_BF16X3: the same
+ * MFMA with each activation split into three bfloat16 terms (hi + mid + lo),
+ * which keeps ~24 significant bits of the activations. */
+typedef enum { NS_FP64 = 0, NS_FP32 = 1, NS_BF16 = 2, NS_BF16X3 = 3 } ns_prec;
+
+/* Batch corrections, Sec. 3 and Sec. 3.2 (i)-(v). */
+typedef enum {
+  NS_CORR_NONE = 0,           /* naive: the m worst die, chain j replaces W[j]            */
+  NS_CORR_BEST_OF_WORST = 1,  /* every chain uses the batch-best worst L_W[m-1]           */
+  NS_CORR_SORT = 2,           /* Algorithm 1: sort W u N, worst m die                     */
+  NS_CORR_HISTORY = 3         /* Algorithm 2: Algorithm 1 + history_iters relaxations     */
+} ns_corr;
+
+/* Likelihood families (all vectorised on the device). */
+typedef enum {
+  NS_LIK_MIXTURE = 0,    /* log sum_k exp(logw_k - q_k/2), q_k diagonal Mahalanobis:
+                            Gaussians, Eq. (2), Eq. (3), Eq. (5) and Gaussian mixtures   */
+  NS_LIK_ROSENBROCK = 1, /* -sum_i [b (x_{i+1} - x_i^2)^2 + (a - x_i)^2], Eq. (6)      */
+  NS_LIK_SHELL = 2,      /* -((|x| - r0)/w)^2 / 2, Eq. (4)                              */
+  NS_LIK_MLP = 3         /* emulator: tanh MLP, linear output, diagonal chi^2 (Sec. 5)  */
+} ns_lik_kind;
+
+typedef struct {
+  ns_lik_kind kind;
+  ns_prec prec;            /* arithmetic of the likelihood: FP64 or FP32 for analytic
+                              families; FP32, BF16 or BF16X3 for MLP (the first layer
+                              always runs in FP32 so theta is never rounded)          */
+  /* NS_LIK_MIXTURE: n_comp components; logw[K], mu[K*d], ivar[K*d] (host)             */
+  int n_comp;
+  const double* logw;
+  const double* mu;
+  const double* ivar;
+  /* NS_LIK_ROSENBROCK */
+  double ros_a, ros_b;
+  /* NS_LIK_SHELL */
+  double shell_r0, shell_w;
+  /* NS_LIK_MLP: n_layers weight matrices; widths[n_layers+1] with widths[0] == d;
+     weights = concatenated row-major W_l (widths[l] x widths[l+1]); biases
+     concatenated; data[widths[n_layers]] and sigma[widths[n_layers]] > 0.          */
+  int n_layers;
+  const int* widths;
+  const double* weights;
+  const double* biases;
+  const double* data;
+  const double* sigma;
+} ns_likelihood;
+
+typedef struct {
+  int slice_steps_per_dim; /* n: n*d slice iterations per chain (Sec. 2.2); default 5   */
+  double step_width;       /* bracket width w in units of the whitened direction; 1.0   */
+  int max_stepout;         /* stepping-out cap per side; 64                             */
+  int max_shrink;          /* shrink cap; 64                                            */
+  int tree_depth;          /* D: at most 2^D clusters (Sec. 2.1); 0 = one cluster       */
+  double split_vol_frac;   /* p: children kept if their volume is < (1-p) x parent; 0.3 */
+  int min_cluster_pts;     /* n_min: both children need more points; 0 = 2(d+1)        */
+  int recluster_every;     /* recluster after this many deaths (Sec. 2.1); 100          */
+  int kmeans_iters;        /* Lloyd iteration cap; 20                                   */
+  ns_corr correction;      /* default NS_CORR_HISTORY                                   */
+  int history_iters;       /* K of Algorithm 2; default 1 (Sec. 3.1)                    */
+  int hist_cap;            /* T: stored shrink proposals of the last iteration; 32      */
+  ns_prec state_prec;      /* sampler state precision: FP64 or FP32                     */
+  double stop_frac;        /* stop when X_i max(L_live) < stop_frac Z_i; 1e-3           */
+  double eig_floor;        /* covariance eigenvalue floor, relative to lambda_max; 1e-8 */
+  uint64_t seed;           /* Philox4x32-10 key                                         */
+  int batch_rounds;        /* 1: evaluate proposals in batched rounds (always the case
+                              for NS_LIK_MLP); 0: analytic families run one fused
+                              kernel per step                                           */
+  int stepout_spec;        /* batched rounds: stepping-out offsets per side per round; 4 */
+  int shrink_spec;         /* batched rounds: shrink proposals per round; 8             */
+} ns_config;
+
+typedef struct {
+  int64_t steps;           /* steps that did work                                       */
+  int64_t dead;            /* dead rows (live-point updates)                            */
+  int64_t evals;           /* true likelihood evaluations of in-box points (incl. init) */
+  int64_t oob;             /* proposals outside the prior box (not evaluated)           */
+  int64_t stepout_caps;    /* stepping-out sides that hit max_stepout                   */
+  int64_t shrink_caps;     /* slice iterations that hit max_shrink                      */
+  int64_t clusterings;     /* cluster-tree builds                                       */
+  int64_t nan_logL;        /* likelihood values that were NaN (counted as -inf)         */
+  int32_t done;            /* stopping rule reached                                     */
+  int32_t n_clusters;      /* clusters of the current tree                              */
+} ns_stats_t;
+
+/* Defaults listed above. */
+ns_status ns_config_default(ns_config* cfg);
+
+/* Create a sampler: N = n_live initial points drawn uniformly in [lo, hi]
+ * (Sec. 1), their likelihoods, and the first cluster tree (Sec. 2.1).
+ * lo, hi: host arrays of d doubles.  hip_stream: a hipStream_t or NULL.
+ * On success *out owns all device memory of the context (freed by ns_free). */
+ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n_live,
+                  const ns_config* cfg, const ns_likelihood* lik, void* hip_stream);
+
+/* One batched update of m live points (Sec. 3; Algorithms 1 and 2): select the
+ * m worst, run m constrained slice-sampling chains, correct, update the live
+ * set, append m dead rows and accumulate the evidence.  Enqueued without
+ * synchronising.  Returns NS_DONE once the stopping rule is known to hold
+ * (the device checks it after every step; steps after it are no-ops). */
+ns_status ns_step_batch(ns_ctx* c, int m);
+
+/* Repeat ns_step_batch(m) until the stopping rule holds or max_steps steps
+ * have been enqueued; *steps (may be NULL) = steps that did work.  Returns
+ * NS_DONE or NS_OK. */
+ns_status ns_run(ns_ctx* c, int m, int64_t max_steps, int64_t* steps);
+
+/* Wait for all enqueued work of the context. */
+ns_status ns_sync(ns_ctx* c);
+
+/* Evidence with the final live points added, each with prior volume X_end/N:
+ * logZ, sigma = sqrt(H/N) and the information H = sum_i p_i log L_i - log Z.
+ * Does not change the run; any output pointer may be NULL. */
+ns_status ns_logZ(ns_ctx* c, double* logZ, double* sigma, double* H);
+
+/* Dead rows in death order.  Two-phase: with u == logL == logX == logw == NULL
+ * only *n is set.  Otherwise arrays hold *n rows: u (n*d), logL, logX = -i/N,
+ * logw = log((X_{i-1} - X_i) L_i) (host arrays, any may be NULL). */
+ns_status ns_get_dead(ns_ctx* c, int64_t* n, double* u, double* logL, double* logX, double* logw);
+
+/* Live set: u (N*d), logL (N), label (N: cluster node of each point); host
+ * arrays, any may be NULL. */
+ns_status ns_get_live(ns_ctx* c, double* u, double* logL, int* label);
+
+/* Replace the live set (host arrays u N*d, logL N, label N; label may be NULL
+ * to keep the labels).  Points are rounded to the state precision. */
+ns_status ns_set_live(ns_ctx* c, const double* u, const double* logL, const int* label);
+
+/* Cluster tree (Sec. 2.1), heap indexed, n_nodes = 2^(D+1)-1.  Host arrays:
+ * count, accepted (1 = cluster of the pruned tree), split_ok (n_nodes ints),
+ * logV (n_nodes), centre (n_nodes*d), chol (n_nodes*d*d, lower triangle of the
+ * regularised covariance's Cholesky factor).  Any may be NULL. */
+ns_status ns_get_tree(ns_ctx* c, int* n_nodes, int* count, int* accepted, int* split_ok,
+                      double* logV, double* centre, double* chol);
+
+/* Inputs and outputs of the last enqueued step (for parity checks): *m = its
+ * batch size; seeds (m slots),
+ * tau (m thresholds), new_u (m*d) and new_logL (m) of the chains before the
+ * correction, chain_evals (m), hist_logL (T*m, row t = shrink proposal t of
+ * the last slice iteration, slot T-1 = the chain's final point), hist_u
+ * (m*T*d), hist_n (m recorded proposals).  Host arrays, any may be NULL. */
+ns_status ns_get_last_batch(ns_ctx* c, int* m, int* seeds, double* tau, double* new_u,
+                            double* new_logL, int64_t* chain_evals, double* hist_logL,
+                            double* hist_u, int* hist_n);
+
+/* Counters; synchronises. */
+ns_status ns_stats(ns_ctx* c, ns_stats_t* s);
+
+/* Evaluate the context's likelihood, as the sampler does, at n unit-cube
+ * points: d_u device array n*d doubles (rounded to the state precision first),
+ * d_out device array n doubles.  Enqueued on the context's stream. */
+ns_status ns_loglike_batch(ns_ctx* c, const double* d_u, int64_t n, double* d_out);
+
+/* Algorithm 1 "sorted": ascending order of (logL, slot) of N keys (NaN counts
+ * as -inf, -0 as +0).  d_logL: N doubles, d_order: N ints (device).  N <= 8192. */
+ns_status ns_select_order(const double* d_logL, int N, int* d_order, void* hip_stream);
+
+/* Algorithms 1 and 2 on explicit arrays (device): d_wlogL (m, ascending),
+ * d_nlogL (m), d_P (m thresholds), d_hist (T*m, row t, column = chain),
+ * d_hist_n (m).  Outputs (device, m each): accepted and rejected entries as
+ * codes (< m: worst point, >= m: chain code-m), history slot (-1: the chain's
+ * final point) and logL, each ascending.  m <= 1024. */
+ns_status ns_correct_batch(int m, ns_corr corr, int K, int T, const double* d_wlogL,
+                           const double* d_nlogL, const double* d_P, const double* d_hist,
+                           const int* d_hist_n, int* d_acc_code, int* d_acc_hslot,
+                           double* d_acc_logL, int* d_rej_code, int* d_rej_hslot,
+                           double* d_rej_logL, void* hip_stream);
+
+/* The generator the sampler draws from: Philox4x32-10 (Salmon et al., SC'11)
+ * evaluated on the device for n counters {c0 + k, c1, c2, c3}, k < n, key =
+ * seed; d_out receives 4n words.  Exposed so the stream can be checked. */
+ns_status ns_philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                    int64_t n, uint32_t* d_out, void* hip_stream);
+
+/* Per-kernel-class device time, measured with HIP events recorded on the
+ * context's stream around each launch sequence: classes NS_TIME_SELECT
+ * (sort + seeds), NS_TIME_SLICE (the chains), NS_TIME_CORRECT (Algorithms
+ * 1/2, update, evidence), NS_TIME_CLUSTER (tree build).  ns_set_timing(c, 1)
+ * clears and enables the counters (it adds two event records per launch);
+ * ns_get_timing synchronises and returns total milliseconds and launch counts
+ * per class (arrays of NS_TIMING_CLASSES, may be NULL).  NS_TIME_LIK: the
+ * batched likelihood kernels of the rounds (network layers and chi^2). */
+#define NS_TIMING_CLASSES 5
+#define NS_TIME_SELECT 0
+#define NS_TIME_SLICE 1   /* fused slice kernel, or the chain kernels of batched rounds */
+#define NS_TIME_CORRECT 2
+#define NS_TIME_CLUSTER 3
+#define NS_TIME_LIK 4     /* batched likelihood of the rounds (network layers, chi^2)  */
+ns_status ns_set_timing(ns_ctx* c, int on);
+ns_status ns_get_timing(ns_ctx* c, double* ms, int64_t* launches);
+
+/* ---- dense networks (emulator likelihood, learned surrogate) --------------
+ * A fully connected network y = f(x): layer l maps widths[l] -> widths[l+1]
+ * as z = h W_l + b_l, hidden layers apply act (NS_ACT_TANH or NS_ACT_SILU),
+ * the output layer is linear.  Weights and biases are caller-owned device
+ * arrays (FP32, W_l row major widths[l] x widths[l+1]).  prec: NS_FP32 (FMA
+ * on the vector ALU), NS_BF16 (MFMA with FP32 accumulation; operands rounded
+ * to bfloat16) or NS_BF16X3 (weights rounded to bfloat16, activations split
+ * in three bfloat16 terms).  The surrogate of the sampler's own (theta, logL)
+ * pairs is trained with these two calls (behind torch.autograd.Function). */
+#define NS_ACT_TANH 1
+#define NS_ACT_SILU 2
+typedef struct {
+  int n_layers;            /* 1..8 */
+  int widths[9];
+  int act;
+  const float* W[8];
+  const float* b[8];
+} ns_mlp_desc;
+
+/* Forward pass of B rows: d_X (B x widths[0]), d_Y (B x widths[L]).  d_Z
+ * (may be NULL) receives every layer's pre-activation, layer l at offset
+ * B * (widths[1] + ... + widths[l]); d_H (may be NULL) every hidden layer's
+ * output at the same offsets (the last block unused). */
+ns_status ns_mlp_forward(const ns_mlp_desc* net, ns_prec prec, const float* d_X, int64_t B,
+                         float* d_Y, float* d_Z, float* d_H, void* hip_stream);
+
+/* Backward pass for the loss gradient d_dY (B x widths[L]), given the d_Z and
+ * d_H of the forward pass: d_dW[l] (widths[l] x widths[l+1]) and d_db[l]
+ * receive dLoss/dW_l and dLoss/db_l (overwritten), d_dX (may be NULL)
+ * dLoss/dX.  d_work: 2 * B * max(widths) floats of scratch. */
+ns_status ns_mlp_backward(const ns_mlp_desc* net, ns_prec prec, const float* d_X, int64_t B,
+                          const float* d_Z, const float* d_H, const float* d_dY,
+                          float* const* d_dW, float* const* d_db, float* d_dX, float* d_work,
+                          void* hip_stream);
+
+/* Description of the last error of c (or of the last context-free call when
+ * c is NULL); valid until the next call on c. */
+const char* ns_last_error(const ns_ctx* c);
+
+/* Release the context and all its device memory.  NULL-safe. */
+void ns_free(ns_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,367 @@
+// k_correct.hip -- end of a batched step (Sec. 3.1, Algorithms 1 and 2):
+// sort the combined set C = W u N, relax "too good" new points with their
+// last-iteration shrink history, re-sort, write the accepted points into the
+// live set, append the rejected ones to the dead store, and accumulate the
+// evidence (Eq. (1), single-point integration, log X_i = -i/N) in FP64 with
+// the stopping rule evaluated on the device.
+//
+// One workgroup; the 2m <= 2048 entries of C live in LDS.  Sorting is by
+// rank counting on the total order (logL, position), which is exact and
+// deterministic.
+#include "ns_internal.hpp"
+
+namespace ns {
+
+constexpr int kCorrT = 1024;
+constexpr int kMaxC = 2048;  // 2m
+
+struct CorrLds {
+  double logL[kMaxC];
+  double P[kMaxC];
+  int code[kMaxC];
+  int hslot[kMaxC];
+  int rank[kMaxC];
+  double tmpd[kMaxC];
+  int tmpi[kMaxC];
+  int list[kMaxC];
+  double listv[kMaxC];
+  double red[kCorrT];
+  int wave_tot[16];
+  int s_total;
+};
+
+__device__ int scan_flag(int flag, int* wave_tot, int* total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const uint64_t bal = __ballot(flag);
+  const int before = __popcll(bal & ((1ull << lane) - 1ull));
+  if (lane == 0) wave_tot[wv] = __popcll(bal);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int q = 0; q < nw; ++q) { const int v = wave_tot[q]; wave_tot[q] = acc; acc += v; }
+    *total = acc;
+  }
+  __syncthreads();
+  const int off = wave_tot[wv] + before;
+  __syncthreads();
+  return off;
+}
+
+// Stable sort of the n entries by (logL, position) via exact ranks.
+__device__ void rank_sort(CorrLds& S, int n) {
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    const double lq = S.logL[q];
+    int r = 0;
+    for (int p = 0; p < n; ++p) {
+      const double lp = S.logL[p];
+      r += (lp < lq) || (lp == lq && p < q);
+    }
+    S.rank[q] = r;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < n; q += blockDim.x) S.tmpd[S.rank[q]] = S.logL[q];
+  __syncthreads();
+  for (int q = threadIdx.x; q < n; q += blockDim.x) S.logL[q] = S.tmpd[q];
+  __syncthreads();
+  for (int q = threadIdx.x; q < n; q += blockDim.x) S.tmpd[S.rank[q]] = S.P[q];
+  __syncthreads();
+  for (int q = threadIdx.x; q < n; q += blockDim.x) S.P[q] = S.tmpd[q];
+  __syncthreads();
+  for (int q = threadIdx.x; q < n; q += blockDim.x) S.tmpi[S.rank[q]] = S.code[q];
+  __syncthreads();
+  for (int q = threadIdx.x; q < n; q += blockDim.x) S.code[q] = S.tmpi[q];
+  __syncthreads();
+  for (int q = threadIdx.x; q < n; q += blockDim.x) S.tmpi[S.rank[q]] = S.hslot[q];
+  __syncthreads();
+  for (int q = threadIdx.x; q < n; q += blockDim.x) S.hslot[q] = S.tmpi[q];
+  __syncthreads();
+}
+
+// Build C and apply the correction; afterwards positions [0, m) hold the
+// rejected entries and [m, 2m) the accepted ones.
+__device__ void correct_core(CorrLds& S, int m, int corr, int K, int TH, const double* wlogL,
+                             const double* nlogL, const double* Pn, const double* hist,
+                             const int* hist_n) {
+  const int n2 = 2 * m;
+  for (int q = threadIdx.x; q < n2; q += blockDim.x) {
+    if (q < m) { S.logL[q] = canon(wlogL[q]); S.P[q] = -1.0; }
+    else { S.logL[q] = canon(nlogL[q - m]); S.P[q] = Pn[q - m]; }
+    S.code[q] = q;
+    S.hslot[q] = -1;
+  }
+  __syncthreads();
+  if (corr != kSort && corr != kHistory) return;
+  rank_sort(S, n2);
+  if (corr != kHistory) return;
+  for (int k = 0; k < K; ++k) {
+    const double acc0 = S.logL[m];
+    // faulty accepted new points J_F, in ascending order
+    int nf = 0;
+    for (int base = 0; base < m; base += blockDim.x) {
+      const int a = base + threadIdx.x;
+      const int flag = a < m && S.code[m + a] >= m && S.P[m + a] >= acc0;
+      const int off = scan_flag(flag, S.wave_tot, &S.s_total);
+      if (flag) S.list[nf + off] = m + a;
+      nf += S.s_total;
+      __syncthreads();
+    }
+    if (nf == 0) break;
+    // instant deaths (rejected new points), ascending
+    int ni = 0;
+    for (int base = 0; base < m; base += blockDim.x) {
+      const int r = base + threadIdx.x;
+      const int flag = r < m && S.code[r] >= m;
+      const int off = scan_flag(flag, S.wave_tot, &S.s_total);
+      if (flag) S.listv[ni + off] = S.logL[r];
+      ni += S.s_total;
+      __syncthreads();
+    }
+    const int npair = nf < ni ? nf : ni;
+    for (int i = threadIdx.x; i < npair; i += blockDim.x) {
+      const int pos = S.list[i];
+      const int col = S.code[pos] - m;
+      const double thr = S.listv[i];
+      int hit = TH - 1;
+      const int hn = min(hist_n[col], TH - 1);
+      for (int t = 0; t < hn; ++t)
+        if (hist[static_cast<long>(t) * m + col] > thr) { hit = t; break; }
+      S.logL[pos] = canon(hist[static_cast<long>(hit) * m + col]);
+      S.hslot[pos] = hit;
+      S.P[pos] = thr;
+    }
+    __syncthreads();
+    rank_sort(S, n2);   // re-sort [rejected, accepted]
+  }
+}
+
+__global__ void __launch_bounds__(kCorrT)
+k_correct_arrays(int m, int corr, int K, int TH, const double* __restrict__ wlogL,
+                 const double* __restrict__ nlogL, const double* __restrict__ Pn,
+                 const double* __restrict__ hist, const int* __restrict__ hist_n,
+                 int* __restrict__ acc_code, int* __restrict__ acc_hslot, double* __restrict__ acc_logL,
+                 int* __restrict__ rej_code, int* __restrict__ rej_hslot, double* __restrict__ rej_logL) {
+  __shared__ CorrLds S;
+  correct_core(S, m, corr, K, TH, wlogL, nlogL, Pn, hist, hist_n);
+  for (int q = threadIdx.x; q < m; q += blockDim.x) {
+    rej_code[q] = S.code[q]; rej_hslot[q] = S.hslot[q]; rej_logL[q] = S.logL[q];
+    acc_code[q] = S.code[m + q]; acc_hslot[q] = S.hslot[m + q]; acc_logL[q] = S.logL[m + q];
+  }
+}
+
+__device__ double block_reduce(double v, double* red, bool is_max) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = blockDim.x >> 1; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      const double a = red[threadIdx.x], b = red[threadIdx.x + off];
+      red[threadIdx.x] = is_max ? (b > a ? b : a) : a + b;
+    }
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kCorrT)
+k_correct(int m, int corr, int K, int TH, int N, int d, int nodes, double stop_frac,
+          T* __restrict__ u, double* __restrict__ logL, int* __restrict__ label,
+          const int* __restrict__ order, const double* __restrict__ LW, const double* __restrict__ tau,
+          const T* __restrict__ new_u, const double* __restrict__ new_logL,
+          const int* __restrict__ chain_stat, const double* __restrict__ hist_logL,
+          const T* __restrict__ hist_u, const int* __restrict__ hist_n,
+          const int* __restrict__ accepted, const double* __restrict__ centre,
+          double* __restrict__ dead_u, double* __restrict__ dead_logL, RunState* __restrict__ st) {
+  if (st->done) return;
+  __shared__ CorrLds S;
+  correct_core(S, m, corr, K, TH, LW, new_logL, tau, hist_logL, hist_n);
+  const long base_dead = st->n_dead;
+  auto src_point = [&](int code, int hs) -> const T* {
+    if (code < m) return u + static_cast<long>(order[code]) * d;
+    if (hs < 0) return new_u + static_cast<long>(code - m) * d;
+    return hist_u + (static_cast<long>(code - m) * TH + hs) * d;
+  };
+  // ---- dead rows (read before any live slot is overwritten)
+  for (int q = threadIdx.x; q < m; q += blockDim.x) {
+    const T* x = src_point(S.code[q], S.hslot[q]);
+    double* o = dead_u + (base_dead + q) * d;
+    for (int i = 0; i < d; ++i) o[i] = static_cast<double>(x[i]);
+    dead_logL[base_dead + q] = S.logL[q];
+  }
+  __syncthreads();
+  // ---- rejected worst points in W order, accepted new points in order
+  for (int k = threadIdx.x; k < m; k += blockDim.x) S.tmpi[k] = 0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < m; q += blockDim.x)
+    if (S.code[q] < m) S.tmpi[S.code[q]] = 1;
+  __syncthreads();
+  int nrw = 0;
+  for (int b0 = 0; b0 < m; b0 += blockDim.x) {
+    const int k = b0 + threadIdx.x;
+    const int flag = k < m && S.tmpi[k];
+    const int off = scan_flag(flag, S.wave_tot, &S.s_total);
+    if (flag) S.list[nrw + off] = k;
+    nrw += S.s_total;
+    __syncthreads();
+  }
+  int nan = 0;
+  for (int b0 = 0; b0 < m; b0 += blockDim.x) {
+    const int q = b0 + threadIdx.x;
+    const int flag = q < m && S.code[m + q] >= m;
+    const int off = scan_flag(flag, S.wave_tot, &S.s_total);
+    if (flag) S.rank[nan + off] = m + q;
+    nan += S.s_total;
+    __syncthreads();
+  }
+  // nrw == nan: every new point that lives takes the slot of a dead worst point
+  for (int r = threadIdx.x; r < nrw; r += blockDim.x) {
+    const int slot = order[S.list[r]];
+    const int pos = S.rank[r];
+    const T* x = src_point(S.code[pos], S.hslot[pos]);
+    T xv[kMaxD];
+    for (int i = 0; i < d; ++i) xv[i] = x[i];
+    for (int i = 0; i < d; ++i) u[static_cast<long>(slot) * d + i] = xv[i];
+    logL[slot] = S.logL[pos];
+    int best = -1;
+    double bd = INFINITY;
+    for (int n = 0; n < nodes; ++n) {
+      if (!accepted[n]) continue;
+      const double* c = centre + static_cast<long>(n) * kMaxD;
+      double s = 0.0;
+      for (int i = 0; i < d; ++i) {
+        const double rr = static_cast<double>(xv[i]) - c[i];
+        s += rr * rr;
+      }
+      if (best < 0 || s < bd) { bd = s; best = n; }
+    }
+    label[slot] = best;
+  }
+  __syncthreads();
+  // ---- evidence of the m dead rows
+  const double Nd = static_cast<double>(N);
+  const double lw0 = log(-expm1(-1.0 / Nd));
+  double lwq = -INFINITY, lq = 0.0;
+  double mx_local = -INFINITY;
+  for (int q = threadIdx.x; q < m; q += blockDim.x) {
+    const double i = static_cast<double>(base_dead + q + 1);
+    const double lw = (S.logL[q] - (i - 1.0) / Nd) + lw0;
+    mx_local = lw > mx_local ? lw : mx_local;
+  }
+  const double mx = block_reduce(mx_local, S.red, true);
+  double s1 = 0.0, s2 = 0.0;
+  if (mx > -INFINITY) {
+    for (int q = threadIdx.x; q < m; q += blockDim.x) {
+      const double i = static_cast<double>(base_dead + q + 1);
+      lwq = (S.logL[q] - (i - 1.0) / Nd) + lw0;
+      lq = S.logL[q];
+      if (lwq == -INFINITY) continue;
+      const double e = exp(lwq - mx);
+      s1 += e;
+      s2 += lq * e;
+    }
+  }
+  s1 = block_reduce(s1, S.red, false);
+  s2 = block_reduce(s2, S.red, false);
+  // ---- stop test needs the best live likelihood
+  double lmax = -INFINITY;
+  for (int k = threadIdx.x; k < N; k += blockDim.x) lmax = logL[k] > lmax ? logL[k] : lmax;
+  lmax = block_reduce(lmax, S.red, true);
+  // ---- counters
+  double ce[4] = {0, 0, 0, 0};
+  for (int j = threadIdx.x; j < m; j += blockDim.x)
+    for (int c = 0; c < 4; ++c) ce[c] += static_cast<double>(chain_stat[4 * j + c]);
+  for (int c = 0; c < 4; ++c) ce[c] = block_reduce(ce[c], S.red, false);
+  if (threadIdx.x == 0) {
+    double lz = st->logZ, A = st->A;
+    if (mx > -INFINITY) {
+      const double Sb = mx + log(s1);
+      const double nz = logaddexp(lz, Sb);
+      const double keep = (lz == -INFINITY) ? 0.0 : A * exp(lz - nz);
+      A = keep + s2 * exp(mx - nz);
+      lz = nz;
+    }
+    st->logZ = lz;
+    st->A = A;
+    st->n_dead = base_dead + m;
+    st->step += 1;
+    st->evals += static_cast<unsigned long long>(ce[0]);
+    st->oob += static_cast<unsigned long long>(ce[1]);
+    st->so_caps += static_cast<unsigned long long>(ce[2]);
+    st->sh_caps += static_cast<unsigned long long>(ce[3]);
+    if (-static_cast<double>(base_dead + m) / Nd + lmax - lz < log(stop_frac)) st->done = 1;
+  }
+}
+
+// Final evidence with the live points added (each with X_end / N).
+__global__ void __launch_bounds__(kCorrT)
+k_final_logZ(int N, const double* __restrict__ logL, const RunState* __restrict__ st,
+             double* __restrict__ out3) {
+  __shared__ double red[kCorrT];
+  const double Nd = static_cast<double>(N);
+  const double base = -static_cast<double>(st->n_dead) / Nd - log(Nd);
+  double mxl = -INFINITY;
+  for (int k = threadIdx.x; k < N; k += blockDim.x) {
+    const double lw = logL[k] + base;
+    mxl = lw > mxl ? lw : mxl;
+  }
+  const double mx = block_reduce(mxl, red, true);
+  double s1 = 0.0, s2 = 0.0;
+  if (mx > -INFINITY)
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+      const double lw = logL[k] + base;
+      if (lw == -INFINITY) continue;
+      const double e = exp(lw - mx);
+      s1 += e;
+      s2 += logL[k] * e;
+    }
+  s1 = block_reduce(s1, red, false);
+  s2 = block_reduce(s2, red, false);
+  if (threadIdx.x == 0) {
+    double lz = st->logZ, A = st->A;
+    if (mx > -INFINITY) {
+      const double Sb = mx + log(s1);
+      const double nz = logaddexp(lz, Sb);
+      const double keep = (lz == -INFINITY) ? 0.0 : A * exp(lz - nz);
+      A = keep + s2 * exp(mx - nz);
+      lz = nz;
+    }
+    const double H = A - lz;
+    out3[0] = lz;
+    out3[1] = sqrt((H > 0.0 ? H : 0.0) / Nd);
+    out3[2] = H;
+  }
+}
+
+hipError_t launch_correct(const Shape& sh, const DevBufs& b, int m, int corr, int K,
+                          double stop_frac, hipStream_t s) {
+  if (sh.state_f32)
+    hipLaunchKernelGGL(k_correct<float>, dim3(1), dim3(kCorrT), 0, s, m, corr, K, sh.T, sh.N, sh.d,
+                       sh.nodes, stop_frac, static_cast<float*>(b.u), b.logL, b.label, b.order, b.LW,
+                       b.tau, static_cast<const float*>(b.new_u), b.new_logL, b.chain_stat,
+                       b.hist_logL, static_cast<const float*>(b.hist_u), b.hist_n, b.accepted,
+                       b.centre, b.dead_u, b.dead_logL, b.st);
+  else
+    hipLaunchKernelGGL(k_correct<double>, dim3(1), dim3(kCorrT), 0, s, m, corr, K, sh.T, sh.N, sh.d,
+                       sh.nodes, stop_frac, static_cast<double*>(b.u), b.logL, b.label, b.order, b.LW,
+                       b.tau, static_cast<const double*>(b.new_u), b.new_logL, b.chain_stat,
+                       b.hist_logL, static_cast<const double*>(b.hist_u), b.hist_n, b.accepted,
+                       b.centre, b.dead_u, b.dead_logL, b.st);
+  return hipGetLastError();
+}
+
+hipError_t launch_correct_arrays(int m, int corr, int K, int T, const double* wlogL,
+                                 const double* nlogL, const double* P, const double* hist,
+                                 const int* hist_n, int* acc_code, int* acc_hslot, double* acc_logL,
+                                 int* rej_code, int* rej_hslot, double* rej_logL, hipStream_t s) {
+  hipLaunchKernelGGL(k_correct_arrays, dim3(1), dim3(kCorrT), 0, s, m, corr, K, T, wlogL, nlogL, P,
+                     hist, hist_n, acc_code, acc_hslot, acc_logL, rej_code, rej_hslot, rej_logL);
+  return hipGetLastError();
+}
+
+hipError_t launch_final_logZ(const Shape& sh, const DevBufs& b, double* out3, hipStream_t s) {
+  hipLaunchKernelGGL(k_final_logZ, dim3(1), dim3(kCorrT), 0, s, sh.N, b.logL, b.st, out3);
+  return hipGetLastError();
+}
+
+}  // namespace ns

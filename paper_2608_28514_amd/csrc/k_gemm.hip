@@ -1,0 +1,262 @@
+// k_gemm.hip -- dense layers of the emulator and surrogate networks.
+//
+// C[M x N] = epilogue( sum_k A(r, k) B(k, n) ), with strided operands
+//   A(r, k) = A[r*sar + k*sak]   (FP32)
+//   B(k, n) = B[n*sbn + k*sbk]   (FP32)
+// so that the forward pass (A row major, B = W^T), dW = H^T dZ and
+// dH = dZ W^T all use the same kernel.  Epilogue: + bias[n], optional tanh /
+// SiLU, optional store of the pre-activation Z.
+//
+// Modes:
+//  * kF32   -- FP32 FMA on the vector ALU (4x4 register blocking).
+//  * kBF16S -- MFMA v_mfma_f32_16x16x32_bf16 with FP32 accumulation; every A
+//              value is split into three bfloat16 terms (hi + mid + lo, which
+//              carries ~24 significant bits) and B is rounded once to
+//              bfloat16, so for bfloat16-valued weights the product matches an
+//              FP32 GEMM up to the accumulation order.
+//  * kBF16  -- MFMA with A and B each rounded once to bfloat16.
+// Tiles: 64 x 64 outputs per 256-thread workgroup, K in steps of 32 staged
+// through LDS; each wave owns a 32 x 32 quadrant (2 x 2 MFMA tiles).
+#include "ns_internal.hpp"
+#include "ns_gemm.hpp"
+
+namespace ns {
+
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+
+constexpr int kTM = 64, kTN = 64, kTK = 32;
+constexpr int kLdsK = kTK + 4;  // padded row stride (floats)
+
+__device__ __forceinline__ float act_fwd(int act, float z) {
+  if (act == kActTanh) return tanhf(z);
+  if (act == kActSilu) return z / (1.0f + expf(-z));
+  return z;
+}
+
+__device__ __forceinline__ __bf16 to_bf16(float x) { return static_cast<__bf16>(x); }
+__device__ __forceinline__ float from_bf16(__bf16 x) { return static_cast<float>(x); }
+
+template <int MODE>
+__global__ void __launch_bounds__(256)
+k_gemm(int M, int N, int K, const float* __restrict__ A, long sar, long sak,
+       const float* __restrict__ B, long sbn, long sbk, const float* __restrict__ bias, int act,
+       float* __restrict__ C, long ldc, float* __restrict__ Z, long ldz, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  __shared__ float As[kTM * kLdsK];
+  __shared__ float Bs[kTN * kLdsK];
+  const int tid = threadIdx.x;
+  const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
+
+  // FP32 path accumulators: thread (tr, tc) owns rows tr*4.., cols tc*4..
+  float acc[4][4];
+  // MFMA path accumulators: wave w owns quadrant (w/2, w%2), 2x2 tiles of 16x16
+  f32x4 macc[2][2];
+  for (int i = 0; i < 4; ++i)
+    for (int jx = 0; jx < 4; ++jx) acc[i][jx] = 0.f;
+  for (int i = 0; i < 2; ++i)
+    for (int jx = 0; jx < 2; ++jx) macc[i][jx] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int wave = tid >> 6, lane = tid & 63;
+  for (int k0 = 0; k0 < K; k0 += kTK) {
+    // stage A (64 x 32) and B^T (64 x 32) as FP32
+    // the unit-stride index runs fastest across threads (coalesced loads)
+    for (int q = tid; q < kTM * kTK; q += 256) {
+      const int r = (sak == 1) ? q / kTK : q % kTM;
+      const int k = (sak == 1) ? q % kTK : q / kTM;
+      const int gr = m0 + r, gk = k0 + k;
+      As[r * kLdsK + k] = (gr < M && gk < K) ? A[gr * sar + gk * sak] : 0.f;
+    }
+    for (int q = tid; q < kTN * kTK; q += 256) {
+      const int r = (sbk == 1) ? q / kTK : q % kTN;
+      const int k = (sbk == 1) ? q % kTK : q / kTN;
+      const int gn = n0 + r, gk = k0 + k;
+      Bs[r * kLdsK + k] = (gn < N && gk < K) ? B[gn * sbn + gk * sbk] : 0.f;
+    }
+    __syncthreads();
+    if (MODE == kF32) {
+      const int tr = tid >> 4, tc = tid & 15;
+      for (int k = 0; k < kTK; ++k) {
+        float a[4], b[4];
+        for (int i = 0; i < 4; ++i) a[i] = As[(tr * 4 + i) * kLdsK + k];
+        for (int i = 0; i < 4; ++i) b[i] = Bs[(tc * 4 + i) * kLdsK + k];
+        for (int i = 0; i < 4; ++i)
+          for (int jx = 0; jx < 4; ++jx) acc[i][jx] = __builtin_fmaf(a[i], b[jx], acc[i][jx]);
+      }
+    } else {
+      // operand fragments: lane l -> row/col l%16, k = 8*(l/16) + i
+      const int rq = (wave >> 1) * 32, cq = (wave & 1) * 32;
+      const int fr = lane & 15, fk = 8 * (lane >> 4);
+      bf16x8 bfrag[2];
+      for (int tn = 0; tn < 2; ++tn) {
+        const float* bp = &Bs[(cq + tn * 16 + fr) * kLdsK + fk];
+        for (int i = 0; i < 8; ++i) bfrag[tn][i] = to_bf16(bp[i]);
+      }
+      for (int tm = 0; tm < 2; ++tm) {
+        const float* ap = &As[(rq + tm * 16 + fr) * kLdsK + fk];
+        bf16x8 a1, a2, a3;
+        for (int i = 0; i < 8; ++i) {
+          const float x = ap[i];
+          const __bf16 h = to_bf16(x);
+          a1[i] = h;
+          if (MODE == kBF16S) {
+            const float r1 = x - from_bf16(h);
+            const __bf16 h2 = to_bf16(r1);
+            a2[i] = h2;
+            a3[i] = to_bf16(r1 - from_bf16(h2));
+          }
+        }
+        for (int tn = 0; tn < 2; ++tn) {
+          if (MODE == kBF16S) {
+            macc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3, bfrag[tn], macc[tm][tn], 0, 0, 0);
+            macc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, bfrag[tn], macc[tm][tn], 0, 0, 0);
+          }
+          macc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bfrag[tn], macc[tm][tn], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // epilogue
+  if (MODE == kF32) {
+    const int tr = tid >> 4, tc = tid & 15;
+    for (int i = 0; i < 4; ++i) {
+      const int r = m0 + tr * 4 + i;
+      if (r >= M) continue;
+      for (int jx = 0; jx < 4; ++jx) {
+        const int n = n0 + tc * 4 + jx;
+        if (n >= N) continue;
+        float z = acc[i][jx] + (bias ? bias[n] : 0.f);
+        if (Z) Z[r * ldz + n] = z;
+        C[r * ldc + n] = act_fwd(act, z);
+      }
+    }
+  } else {
+    // output fragment: lane l holds rows 4*(l/16)+i, col l%16 of its 16x16 tile
+    const int rq = (wave >> 1) * 32, cq = (wave & 1) * 32;
+    for (int tm = 0; tm < 2; ++tm)
+      for (int tn = 0; tn < 2; ++tn)
+        for (int i = 0; i < 4; ++i) {
+          const int r = m0 + rq + tm * 16 + 4 * (lane >> 4) + i;
+          const int n = n0 + cq + tn * 16 + (lane & 15);
+          if (r >= M || n >= N) continue;
+          float z = macc[tm][tn][i] + (bias ? bias[n] : 0.f);
+          if (Z) Z[r * ldz + n] = z;
+          C[r * ldc + n] = act_fwd(act, z);
+        }
+  }
+}
+
+hipError_t launch_gemm(int mode, int M, int N, int K, const float* A, long sar, long sak,
+                       const float* B, long sbn, long sbk, const float* bias, int act, float* C,
+                       long ldc, float* Z, long ldz, const int* gate, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const dim3 grid((N + kTN - 1) / kTN, (M + kTM - 1) / kTM), block(256);
+  if (mode == kF32)
+    hipLaunchKernelGGL(k_gemm<kF32>, grid, block, 0, s, M, N, K, A, sar, sak, B, sbn, sbk, bias,
+                       act, C, ldc, Z, ldz, gate);
+  else if (mode == kBF16S)
+    hipLaunchKernelGGL(k_gemm<kBF16S>, grid, block, 0, s, M, N, K, A, sar, sak, B, sbn, sbk, bias,
+                       act, C, ldc, Z, ldz, gate);
+  else
+    hipLaunchKernelGGL(k_gemm<kBF16>, grid, block, 0, s, M, N, K, A, sar, sak, B, sbn, sbk, bias,
+                       act, C, ldc, Z, ldz, gate);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise pieces of the backward pass and the diagonal chi^2.
+
+// dZ = dH * act'(Z)
+__global__ void k_act_bwd(long n, int act, const float* __restrict__ Z, const float* __restrict__ dH,
+                          float* __restrict__ dZ) {
+  const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float z = Z[i];
+  float g = 1.f;
+  if (act == kActTanh) {
+    const float t = tanhf(z);
+    g = 1.f - t * t;
+  } else if (act == kActSilu) {
+    const float sg = 1.f / (1.f + expf(-z));
+    g = sg * (1.f + z * (1.f - sg));
+  }
+  dZ[i] = dH[i] * g;
+}
+
+hipError_t launch_act_bwd(long n, int act, const float* Z, const float* dH, float* dZ, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_act_bwd, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, n, act,
+                     Z, dH, dZ);
+  return hipGetLastError();
+}
+
+// db[n] = sum_r dZ[r, n] (fixed order: one thread per column)
+__global__ void k_colsum(int M, int N, const float* __restrict__ dZ, float* __restrict__ db) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.f;
+  for (int r = 0; r < M; ++r) s += dZ[static_cast<long>(r) * N + n];
+  db[n] = s;
+}
+
+hipError_t launch_colsum(int M, int N, const float* dZ, float* db, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_colsum, dim3((N + 255) / 256), dim3(256), 0, s, M, N, dZ, db);
+  return hipGetLastError();
+}
+
+// logL[r] = -1/2 sum_i ((y_ri - data_i) * isig_i)^2 in FP64; rows with flag 0 get -inf.
+__global__ void __launch_bounds__(64)
+k_chi2(int M, int N, const float* __restrict__ Y, const double* __restrict__ data,
+       const double* __restrict__ isig, const int* __restrict__ flag, double* __restrict__ logL,
+       const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int r = blockIdx.x;
+  if (r >= M) return;
+  const int lane = threadIdx.x;
+  if (flag && flag[r] == 0) {
+    if (lane == 0) logL[r] = -INFINITY;
+    return;
+  }
+  double s = 0.0;
+  for (int i = lane; i < N; i += 64) {
+    const double e = (static_cast<double>(Y[static_cast<long>(r) * N + i]) - data[i]) * isig[i];
+    s += e * e;
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
+  if (lane == 0) {
+    const double v = -0.5 * s;
+    logL[r] = isnan(v) ? -INFINITY : v;
+  }
+}
+
+hipError_t launch_chi2(int M, int N, const float* Y, const double* data, const double* isig,
+                       const int* flag, double* logL, const int* gate, hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_chi2, dim3(M), dim3(64), 0, s, M, N, Y, data, isig, flag, logL, gate);
+  return hipGetLastError();
+}
+
+}  // namespace ns
+
+namespace ns {
+
+hipError_t net_forward(const NetDev& net, int mode_first, int mode_rest, int M, const float* X,
+                       float* H0, float* H1, float* Y, const int* gate, hipStream_t s) {
+  const float* in = X;
+  long ldin = net.widths[0];
+  for (int l = 0; l < net.n_layers; ++l) {
+    const int K = net.widths[l], N = net.widths[l + 1];
+    const bool last = (l == net.n_layers - 1);
+    float* out = last ? Y : ((l % 2 == 0) ? H0 : H1);
+    hipError_t e = launch_gemm(l == 0 ? mode_first : mode_rest, M, N, K, in, ldin, 1, net.Wt[l], K, 1,
+                               net.b[l], last ? kActNone : net.act, out, N, nullptr, 0, gate, s);
+    if (e != hipSuccess) return e;
+    in = out;
+    ldin = N;
+  }
+  return hipSuccess;
+}
+
+}  // namespace ns

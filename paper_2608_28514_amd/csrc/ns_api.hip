@@ -1,0 +1,919 @@
+// ns_api.hip -- host orchestrator and C ABI of libns.so (declared in
+// include/ns.h).  Owns the device memory of a context, enqueues the kernels of
+// each batched step on the context's stream, and polls the device-side stop
+// flag without blocking the stream.
+#include <hip/hip_runtime.h>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <algorithm>
+#include <string>
+#include <vector>
+#include "../../include/ns.h"
+#include "ns_internal.hpp"
+#include "ns_gemm.hpp"
+#include "ns_rounds.hpp"
+
+using namespace ns;
+
+struct ns_ctx {
+  Shape sh{};
+  DevBufs b{};
+  LikDev lik{};
+  ns_config cfg{};
+  int nmin = 0;
+  int M = 0;               // batch capacity (chains)
+  int last_m = 0;          // batch size of the last enqueued step
+  long dead_cap = 0;       // rows
+  long dead_ub = 0;        // upper bound of rows after the enqueued steps
+  long since_cluster = 0;  // deaths since the last clustering (host mirror)
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  // polling of the device stop flag
+  RunState* h_st = nullptr;   // pinned
+  hipEvent_t poll_ev = nullptr;
+  bool poll_pending = false;
+  bool known_done = false;
+  double* d_out3 = nullptr;
+  // likelihood parameter arrays (device)
+  std::vector<void*> lik_bufs;
+  // batched rounds (network likelihoods, or analytic ones on request)
+  bool batched = false;
+  bool is_mlp = false;
+  RoundsParams rp{};
+  RoundBufs rb{};
+  int* h_gate = nullptr;      // pinned
+  NetDev net{};
+  int mode_first = kF32, mode_rest = kF32;
+  double* mlp_data = nullptr;
+  double* mlp_isig = nullptr;
+  std::string err;
+  // optional per-kernel-class timing with events on the context's stream
+  bool timing = false;
+  struct Pending { int cls; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> ev_pool;
+  double t_ms[NS_TIMING_CLASSES] = {0};
+  int64_t t_n[NS_TIMING_CLASSES] = {0};
+};
+
+static hipEvent_t take_event(ns_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Fold completed event pairs into the per-class totals (after a stream sync).
+static void drain_timing(ns_ctx* c) {
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->t_ms[p.cls] += ms;
+      c->t_n[p.cls] += 1;
+    }
+    c->ev_pool.push_back(p.a);
+    c->ev_pool.push_back(p.b);
+  }
+  c->pending.clear();
+}
+
+// RAII bracket of one kernel-class launch sequence.
+struct TimeScope {
+  ns_ctx* c;
+  int cls;
+  hipEvent_t a = nullptr;
+  TimeScope(ns_ctx* c_, int cls_) : c(c_), cls(cls_) {
+    if (c->timing) {
+      a = take_event(c);
+      if (a) (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~TimeScope() {
+    if (c->timing && a) {
+      hipEvent_t b = take_event(c);
+      if (b) {
+        (void)hipEventRecord(b, c->stream);
+        c->pending.push_back({cls, a, b});
+      }
+    }
+  }
+};
+
+static std::string g_err;
+
+#define NS_TRY(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      set_err(c, std::string(#call) + ": " + hipGetErrorString(e_));              \
+      return NS_EDEVICE;                                                          \
+    }                                                                             \
+  } while (0)
+
+static void set_err(ns_ctx* c, const std::string& s) {
+  if (c) c->err = s; else g_err = s;
+}
+
+static ns_status inval(ns_ctx* c, const std::string& s) {
+  set_err(c, s);
+  return NS_EINVAL;
+}
+
+template <typename T>
+static hipError_t dalloc(T** p, size_t n) {
+  return hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T) + 16);
+}
+
+static size_t state_bytes(const ns_ctx* c) { return c->sh.state_f32 ? 4 : 8; }
+
+static void hfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+static ns_status alloc_batch(ns_ctx* c, int M) {
+  DevBufs& b = c->b;
+  const int d = c->sh.d, T = c->sh.T;
+  hfree(b.seeds); hfree(b.tau); hfree(b.LW); hfree(b.new_u); hfree(b.new_logL);
+  hfree(b.chain_stat); hfree(b.hist_logL); hfree(b.hist_u); hfree(b.hist_n);
+  const size_t sb = state_bytes(c);
+  NS_TRY(dalloc(&b.seeds, M));
+  NS_TRY(dalloc(&b.tau, M));
+  NS_TRY(dalloc(&b.LW, M));
+  NS_TRY(hipMalloc(&b.new_u, sb * M * d));
+  NS_TRY(dalloc(&b.new_logL, M));
+  NS_TRY(dalloc(&b.chain_stat, 4 * M));
+  NS_TRY(dalloc(&b.hist_logL, static_cast<size_t>(T) * M));
+  NS_TRY(hipMalloc(&b.hist_u, sb * static_cast<size_t>(M) * T * d));
+  NS_TRY(dalloc(&b.hist_n, M));
+  c->M = M;
+  return NS_OK;
+}
+
+static ns_status grow_dead(ns_ctx* c, long need) {
+  if (need <= c->dead_cap) return NS_OK;
+  long nc = c->dead_cap ? c->dead_cap : 4096;
+  while (nc < need) nc *= 2;
+  double *nu = nullptr, *nl = nullptr;
+  NS_TRY(dalloc(&nu, static_cast<size_t>(nc) * c->sh.d));
+  NS_TRY(dalloc(&nl, static_cast<size_t>(nc)));
+  if (c->dead_cap) {
+    NS_TRY(hipStreamSynchronize(c->stream));
+    NS_TRY(hipMemcpyAsync(nu, c->b.dead_u, sizeof(double) * c->dead_cap * c->sh.d,
+                          hipMemcpyDeviceToDevice, c->stream));
+    NS_TRY(hipMemcpyAsync(nl, c->b.dead_logL, sizeof(double) * c->dead_cap,
+                          hipMemcpyDeviceToDevice, c->stream));
+    NS_TRY(hipStreamSynchronize(c->stream));
+    hfree(c->b.dead_u);
+    hfree(c->b.dead_logL);
+  }
+  c->b.dead_u = nu;
+  c->b.dead_logL = nl;
+  c->dead_cap = nc;
+  return NS_OK;
+}
+
+static void free_all(ns_ctx* c) {
+  DevBufs& b = c->b;
+  void* ptrs[] = {b.u, b.logL, b.label, b.order, b.seeds, b.tau, b.LW, b.new_u, b.new_logL,
+                  b.chain_stat, b.hist_logL, b.hist_u, b.hist_n, b.nodeof, b.members, b.count,
+                  b.accepted, b.split_ok, b.logV, b.logV_eff, b.centre, b.cov, b.chol, b.chol_f,
+                  b.dead_u, b.dead_logL, b.st, c->d_out3, c->rb.cs, c->rb.pts, c->rb.xin,
+                  c->rb.flag, c->rb.rlogL, c->rb.gate, c->rb.H0, c->rb.H1, c->rb.Y};
+  for (void* p : ptrs) hfree(p);
+  for (void* p : c->lik_bufs) hfree(p);
+  if (c->h_st) (void)hipHostFree(c->h_st);
+  if (c->h_gate) (void)hipHostFree(c->h_gate);
+  if (c->poll_ev) (void)hipEventDestroy(c->poll_ev);
+  for (auto& p : c->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+}
+
+template <typename T>
+static ns_status upload(ns_ctx* c, const T* host, size_t n, const T** dev) {
+  T* p = nullptr;
+  NS_TRY(dalloc(&p, n));
+  c->lik_bufs.push_back(p);
+  NS_TRY(hipMemcpy(p, host, n * sizeof(T), hipMemcpyHostToDevice));
+  *dev = p;
+  return NS_OK;
+}
+
+static ns_status enqueue_cluster(ns_ctx* c) {
+  TimeScope ts(c, NS_TIME_CLUSTER);
+  const int nmin = c->nmin;
+  NS_TRY(launch_cluster(c->sh, c->b, c->cfg.split_vol_frac, nmin, c->cfg.kmeans_iters,
+                        c->cfg.eig_floor, c->stream));
+  c->since_cluster = 0;
+  return NS_OK;
+}
+
+// Likelihood of the first n rows of the row buffers (gate: skip when zero).
+static ns_status eval_rows(ns_ctx* c, long n, const int* gate) {
+  TimeScope ts(c, NS_TIME_LIK);
+  if (c->is_mlp) {
+    NS_TRY(net_forward(c->net, c->mode_first, c->mode_rest, static_cast<int>(n), c->rb.xin, c->rb.H0,
+                       c->rb.H1, c->rb.Y, gate, c->stream));
+    NS_TRY(launch_chi2(static_cast<int>(n), c->net.widths[c->net.n_layers], c->rb.Y, c->mlp_data,
+                       c->mlp_isig, c->rb.flag, c->rb.rlogL, gate, c->stream));
+  } else {
+    NS_TRY(launch_rows_loglike(c->sh, c->lik, n, c->rb.pts, c->rb.flag, c->rb.rlogL, gate, c->stream));
+  }
+  return NS_OK;
+}
+
+// The m chains of one step as rounds of (advance, batched likelihood), in
+// chunks; a chunk boundary reads the last round's gate to see whether any
+// chain is still running.
+static ns_status run_rounds(ns_ctx* c, int m) {
+  RoundsParams p = c->rp;
+  p.m = m;
+  const long rows = static_cast<long>(m) * p.P;
+  NS_TRY(launch_fill_int(c->rb.gate, c->rb.gate_cap, 0, c->stream));
+  const int chunk = 48;
+  int r = 0;
+  for (;;) {
+    for (int q = 0; q < chunk && r < c->rb.gate_cap; ++q, ++r) {
+      {
+        TimeScope ts(c, NS_TIME_SLICE);
+        NS_TRY(launch_rounds_advance(r, p, c->sh, c->b, c->rb, c->stream));
+      }
+      ns_status e = eval_rows(c, rows, c->rb.gate + r);
+      if (e != NS_OK) return e;
+    }
+    NS_TRY(hipMemcpyAsync(c->h_gate, c->rb.gate + (r - 1), sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    NS_TRY(hipStreamSynchronize(c->stream));
+    if (*c->h_gate == 0) break;
+    if (r >= c->rb.gate_cap) {
+      set_err(c, "slice rounds did not finish within the round cap");
+      return NS_ESTATE;
+    }
+  }
+  return NS_OK;
+}
+
+extern "C" {
+
+ns_status ns_config_default(ns_config* cfg) {
+  if (!cfg) return NS_EINVAL;
+  cfg->slice_steps_per_dim = 5;
+  cfg->step_width = 1.0;
+  cfg->max_stepout = 64;
+  cfg->max_shrink = 64;
+  cfg->tree_depth = 0;
+  cfg->split_vol_frac = 0.3;
+  cfg->min_cluster_pts = 0;
+  cfg->recluster_every = 100;
+  cfg->kmeans_iters = 20;
+  cfg->correction = NS_CORR_HISTORY;
+  cfg->history_iters = 1;
+  cfg->hist_cap = 32;
+  cfg->state_prec = NS_FP64;
+  cfg->stop_frac = 1e-3;
+  cfg->eig_floor = 1e-8;
+  cfg->seed = 0;
+  cfg->batch_rounds = 0;
+  cfg->stepout_spec = 4;
+  cfg->shrink_spec = 8;
+  return NS_OK;
+}
+
+ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n_live,
+                  const ns_config* cfg, const ns_likelihood* lik, void* hip_stream) {
+  ns_ctx* c = nullptr;
+  if (!out || !lo || !hi || !cfg || !lik) return inval(nullptr, "ns_init: null argument");
+  *out = nullptr;
+  if (d < 1 || d > kMaxD) return inval(nullptr, "ns_init: d must be in [1, 32]");
+  if (n_live < 2 || n_live > 8192) return inval(nullptr, "ns_init: n_live must be in [2, 8192]");
+  for (int i = 0; i < d; ++i)
+    if (!(lo[i] < hi[i])) return inval(nullptr, "ns_init: lo < hi must hold elementwise");
+  if (cfg->tree_depth < 0 || cfg->tree_depth > 6) return inval(nullptr, "ns_init: tree_depth in [0, 6]");
+  if (cfg->hist_cap < 2 || cfg->hist_cap > 64) return inval(nullptr, "ns_init: hist_cap in [2, 64]");
+  if (cfg->slice_steps_per_dim < 1 || cfg->max_shrink < 1 || cfg->max_stepout < 0 ||
+      !(cfg->step_width > 0) || cfg->recluster_every < 1 || cfg->kmeans_iters < 0 ||
+      cfg->history_iters < 0 || !(cfg->stop_frac > 0) || !(cfg->split_vol_frac >= 0 && cfg->split_vol_frac < 1))
+    return inval(nullptr, "ns_init: invalid sampler configuration");
+  if (cfg->correction < NS_CORR_NONE || cfg->correction > NS_CORR_HISTORY)
+    return inval(nullptr, "ns_init: unknown correction");
+  if (cfg->state_prec != NS_FP64 && cfg->state_prec != NS_FP32)
+    return inval(nullptr, "ns_init: state_prec must be FP64 or FP32");
+  if (lik->kind < NS_LIK_MIXTURE || lik->kind > NS_LIK_MLP)
+    return inval(nullptr, "ns_init: unknown likelihood kind");
+  if (lik->kind != NS_LIK_MLP && lik->prec != NS_FP64 && lik->prec != NS_FP32)
+    return inval(nullptr, "ns_init: analytic likelihoods run in FP64 or FP32");
+  if (lik->kind == NS_LIK_MLP) {
+    if (lik->prec != NS_FP32 && lik->prec != NS_BF16 && lik->prec != NS_BF16X3)
+      return inval(nullptr, "ns_init: the network likelihood runs in FP32, BF16 or BF16X3");
+    if (lik->n_layers < 1 || lik->n_layers > 8 || !lik->widths || !lik->weights || !lik->biases ||
+        !lik->data || !lik->sigma)
+      return inval(nullptr, "ns_init: the network needs 1..8 layers, widths, weights, biases, data, sigma");
+    if (lik->widths[0] != d) return inval(nullptr, "ns_init: widths[0] must equal d");
+    for (int l = 1; l <= lik->n_layers; ++l)
+      if (lik->widths[l] < 1 || lik->widths[l] > 4096) return inval(nullptr, "ns_init: widths in [1, 4096]");
+    for (int i = 0; i < lik->widths[lik->n_layers]; ++i)
+      if (!(lik->sigma[i] > 0) || !std::isfinite(lik->sigma[i]))
+        return inval(nullptr, "ns_init: sigma must be positive and finite");
+  }
+  if (cfg->batch_rounds || lik->kind == NS_LIK_MLP) {
+    if (cfg->stepout_spec < 1 || cfg->stepout_spec > 32 || cfg->shrink_spec < 1 || cfg->shrink_spec > 64)
+      return inval(nullptr, "ns_init: stepout_spec in [1, 32], shrink_spec in [1, 64]");
+  }
+  if (lik->kind == NS_LIK_MIXTURE &&
+      (lik->n_comp < 1 || lik->n_comp > 4096 || !lik->logw || !lik->mu || !lik->ivar))
+    return inval(nullptr, "ns_init: mixture needs n_comp in [1,4096] and logw, mu, ivar");
+  if (lik->kind == NS_LIK_SHELL && !(lik->shell_w > 0))
+    return inval(nullptr, "ns_init: shell width must be positive");
+
+  c = new ns_ctx();
+  c->cfg = *cfg;
+  c->nmin = cfg->min_cluster_pts > 0 ? cfg->min_cluster_pts : 2 * (d + 1);
+  Shape& sh = c->sh;
+  sh.N = n_live;
+  sh.d = d;
+  sh.T = cfg->hist_cap;
+  sh.depth = cfg->tree_depth;
+  sh.nodes = (1 << (cfg->tree_depth + 1)) - 1;
+  sh.state_f32 = cfg->state_prec == NS_FP32;
+  sh.lik_f32 = lik->prec == NS_FP32;
+  ns_status rs;
+#define NS_INIT_TRY(call)                      \
+  do {                                         \
+    rs = (call);                               \
+    if (rs != NS_OK) { g_err = c->err; free_all(c); delete c; return rs; } \
+  } while (0)
+#define NS_INIT_HIP(call)                                                        \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      g_err = std::string(#call) + ": " + hipGetErrorString(e_);                 \
+      free_all(c); delete c; return NS_EDEVICE;                                  \
+    }                                                                            \
+  } while (0)
+  if (hip_stream) {
+    c->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    NS_INIT_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  // likelihood
+  LikDev& L = c->lik;
+  L.kind = lik->kind;
+  L.d = d;
+  for (int i = 0; i < d; ++i) {
+    L.lo[i] = lo[i];
+    L.span[i] = hi[i] - lo[i];
+    L.lo_f[i] = static_cast<float>(lo[i]);
+    L.span_f[i] = static_cast<float>(hi[i] - lo[i]);
+  }
+  L.ros_a = lik->ros_a;
+  L.ros_b = lik->ros_b;
+  L.shell_r0 = lik->shell_r0;
+  L.shell_w = lik->shell_w;
+  if (lik->kind == NS_LIK_MIXTURE) {
+    const int K = lik->n_comp;
+    L.n_comp = K;
+    std::vector<float> lw(K), mu(static_cast<size_t>(K) * d), iv(static_cast<size_t>(K) * d);
+    for (int k = 0; k < K; ++k) lw[k] = static_cast<float>(lik->logw[k]);
+    for (size_t q = 0; q < mu.size(); ++q) { mu[q] = static_cast<float>(lik->mu[q]); iv[q] = static_cast<float>(lik->ivar[q]); }
+    NS_INIT_TRY(upload(c, lik->logw, K, &L.logw));
+    NS_INIT_TRY(upload(c, lik->mu, mu.size(), &L.mu));
+    NS_INIT_TRY(upload(c, lik->ivar, iv.size(), &L.ivar));
+    NS_INIT_TRY(upload(c, lw.data(), lw.size(), &L.logw_f));
+    NS_INIT_TRY(upload(c, mu.data(), mu.size(), &L.mu_f));
+    NS_INIT_TRY(upload(c, iv.data(), iv.size(), &L.ivar_f));
+  }
+  c->is_mlp = lik->kind == NS_LIK_MLP;
+  c->batched = c->is_mlp || cfg->batch_rounds != 0;
+  if (c->is_mlp) {
+    NetDev& net = c->net;
+    net.n_layers = lik->n_layers;
+    net.act = kActTanh;
+    net.max_width = 0;
+    size_t off_w = 0, off_b = 0;
+    for (int l = 0; l <= lik->n_layers; ++l) {
+      net.widths[l] = lik->widths[l];
+      net.max_width = std::max(net.max_width, lik->widths[l]);
+    }
+    for (int l = 0; l < lik->n_layers; ++l) {
+      const int K = lik->widths[l], Nn = lik->widths[l + 1];
+      std::vector<float> wt(static_cast<size_t>(K) * Nn), bb(Nn);
+      for (int k = 0; k < K; ++k)
+        for (int n = 0; n < Nn; ++n) wt[static_cast<size_t>(n) * K + k] = static_cast<float>(lik->weights[off_w + static_cast<size_t>(k) * Nn + n]);
+      for (int n = 0; n < Nn; ++n) bb[n] = static_cast<float>(lik->biases[off_b + n]);
+      off_w += static_cast<size_t>(K) * Nn;
+      off_b += Nn;
+      NS_INIT_TRY(upload(c, wt.data(), wt.size(), &net.Wt[l]));
+      NS_INIT_TRY(upload(c, bb.data(), bb.size(), &net.b[l]));
+    }
+    const int nout = lik->widths[lik->n_layers];
+    std::vector<double> isig(nout);
+    for (int i = 0; i < nout; ++i) isig[i] = 1.0 / lik->sigma[i];
+    const double* dd = nullptr;
+    const double* di = nullptr;
+    NS_INIT_TRY(upload(c, lik->data, nout, &dd));
+    NS_INIT_TRY(upload(c, isig.data(), isig.size(), &di));
+    c->mlp_data = const_cast<double*>(dd);
+    c->mlp_isig = const_cast<double*>(di);
+    // layer 0 always FP32 (theta is never rounded); the rest BF16 x3-split or FP32
+    c->mode_first = kF32;
+    c->mode_rest = lik->prec == NS_BF16X3 ? kBF16S : (lik->prec == NS_BF16 ? kBF16 : kF32);
+  }
+  // state
+  DevBufs& b = c->b;
+  const size_t sb = sh.state_f32 ? 4 : 8;
+  const size_t N = n_live;
+  NS_INIT_HIP(hipMalloc(&b.u, sb * N * d));
+  NS_INIT_HIP(dalloc(&b.logL, N));
+  NS_INIT_HIP(dalloc(&b.label, N));
+  NS_INIT_HIP(dalloc(&b.order, N));
+  NS_INIT_HIP(dalloc(&b.nodeof, N));
+  NS_INIT_HIP(dalloc(&b.members, N * sh.nodes));
+  NS_INIT_HIP(dalloc(&b.count, sh.nodes));
+  NS_INIT_HIP(dalloc(&b.accepted, sh.nodes));
+  NS_INIT_HIP(dalloc(&b.split_ok, sh.nodes));
+  NS_INIT_HIP(dalloc(&b.logV, sh.nodes));
+  NS_INIT_HIP(dalloc(&b.logV_eff, sh.nodes));
+  NS_INIT_HIP(dalloc(&b.centre, static_cast<size_t>(sh.nodes) * kMaxD));
+  NS_INIT_HIP(dalloc(&b.cov, static_cast<size_t>(sh.nodes) * kMaxD * kMaxD));
+  NS_INIT_HIP(dalloc(&b.chol, static_cast<size_t>(sh.nodes) * kMaxD * kMaxD));
+  NS_INIT_HIP(dalloc(&b.chol_f, static_cast<size_t>(sh.nodes) * kMaxD * kMaxD));
+  NS_INIT_HIP(dalloc(&b.st, 1));
+  NS_INIT_HIP(dalloc(&c->d_out3, 3));
+  NS_INIT_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_st), sizeof(RunState), hipHostMallocDefault));
+  NS_INIT_HIP(hipEventCreateWithFlags(&c->poll_ev, hipEventDisableTiming));
+  NS_INIT_TRY(alloc_batch(c, 16));
+  NS_INIT_TRY(grow_dead(c, 4096));
+  // zero tree buffers once (cov entries beyond d stay zero)
+  NS_INIT_HIP(hipMemsetAsync(b.cov, 0, sizeof(double) * sh.nodes * kMaxD * kMaxD, c->stream));
+  NS_INIT_HIP(hipMemsetAsync(b.centre, 0, sizeof(double) * sh.nodes * kMaxD, c->stream));
+  RunState s0{};
+  s0.logZ = -INFINITY;
+  s0.A = 0.0;
+  s0.evals = static_cast<unsigned long long>(n_live);
+  *c->h_st = s0;
+  NS_INIT_HIP(hipMemcpyAsync(b.st, c->h_st, sizeof(RunState), hipMemcpyHostToDevice, c->stream));
+  if (c->batched) {
+    RoundsParams& rp = c->rp;
+    rp.d = d;
+    rp.T = sh.T;
+    rp.so_spec = cfg->stepout_spec;
+    rp.sh_spec = cfg->shrink_spec;
+    rp.P = std::max(2 * rp.so_spec, rp.sh_spec);
+    rp.n_iter = cfg->slice_steps_per_dim * d;
+    rp.max_stepout = cfg->max_stepout;
+    rp.max_shrink = cfg->max_shrink;
+    rp.w = cfg->step_width;
+    rp.seed = cfg->seed;
+    for (int i = 0; i < d; ++i) { rp.lo_f[i] = L.lo_f[i]; rp.span_f[i] = L.span_f[i]; }
+    RoundBufs& rb = c->rb;
+    rb.rows_cap = std::max<long>(n_live, 1024L * rp.P);
+    const int per_iter = (cfg->max_stepout + rp.so_spec - 1) / rp.so_spec + 1 +
+                         (cfg->max_shrink + rp.sh_spec - 1) / rp.sh_spec + 1;
+    rb.gate_cap = rp.n_iter * per_iter + 4;
+    const size_t csz = sh.state_f32 ? sizeof(ChainState<float>) : sizeof(ChainState<double>);
+    NS_INIT_HIP(hipMalloc(&rb.cs, csz * 1024));
+    NS_INIT_HIP(hipMalloc(&rb.pts, sb * rb.rows_cap * d));
+    NS_INIT_HIP(dalloc(&rb.xin, static_cast<size_t>(rb.rows_cap) * d));
+    NS_INIT_HIP(dalloc(&rb.flag, rb.rows_cap));
+    NS_INIT_HIP(dalloc(&rb.rlogL, rb.rows_cap));
+    NS_INIT_HIP(dalloc(&rb.gate, rb.gate_cap));
+    NS_INIT_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_gate), sizeof(int), hipHostMallocDefault));
+    if (c->is_mlp) {
+      NS_INIT_HIP(dalloc(&rb.H0, static_cast<size_t>(rb.rows_cap) * c->net.max_width));
+      NS_INIT_HIP(dalloc(&rb.H1, static_cast<size_t>(rb.rows_cap) * c->net.max_width));
+      NS_INIT_HIP(dalloc(&rb.Y, static_cast<size_t>(rb.rows_cap) * c->net.widths[c->net.n_layers]));
+    }
+    NS_INIT_HIP(launch_init_rows(n_live, d, cfg->seed, rp, sh.state_f32, b.u, rb.pts, rb.xin, rb.flag,
+                                 c->stream));
+    NS_INIT_TRY(eval_rows(c, n_live, nullptr));
+    NS_INIT_HIP(hipMemcpyAsync(b.logL, rb.rlogL, sizeof(double) * n_live, hipMemcpyDeviceToDevice,
+                               c->stream));
+  } else {
+    NS_INIT_HIP(launch_init_points(sh, b, L, cfg->seed, c->stream));
+  }
+  NS_INIT_TRY(enqueue_cluster(c));
+  NS_INIT_HIP(hipStreamSynchronize(c->stream));
+#undef NS_INIT_TRY
+#undef NS_INIT_HIP
+  *out = c;
+  return NS_OK;
+}
+
+static void poll(ns_ctx* c) {
+  if (c->poll_pending) {
+    if (hipEventQuery(c->poll_ev) == hipSuccess) {
+      c->poll_pending = false;
+      if (c->h_st->done) c->known_done = true;
+    }
+  }
+  if (!c->poll_pending && !c->known_done) {
+    if (hipMemcpyAsync(c->h_st, c->b.st, sizeof(RunState), hipMemcpyDeviceToHost, c->stream) ==
+            hipSuccess &&
+        hipEventRecord(c->poll_ev, c->stream) == hipSuccess)
+      c->poll_pending = true;
+  }
+}
+
+ns_status ns_step_batch(ns_ctx* c, int m) {
+  if (!c) return NS_EINVAL;
+  if (m < 1 || m > c->sh.N - 1 || m > 1024) return inval(c, "ns_step_batch: need 1 <= m <= min(N-1, 1024)");
+  if (c->known_done) return NS_DONE;
+  if (m > c->M) {
+    NS_TRY(hipStreamSynchronize(c->stream));
+    ns_status r = alloc_batch(c, m);
+    if (r != NS_OK) return r;
+  }
+  {
+    ns_status r = grow_dead(c, c->dead_ub + m);
+    if (r != NS_OK) return r;
+  }
+  if (c->since_cluster >= c->cfg.recluster_every) {
+    ns_status r = enqueue_cluster(c);
+    if (r != NS_OK) return r;
+  }
+  const int corr = static_cast<int>(c->cfg.correction);
+  {
+    TimeScope ts(c, NS_TIME_SELECT);
+    NS_TRY(launch_select(c->sh, c->b, m, corr, c->cfg.seed, c->stream));
+  }
+  SliceParams p{};
+  p.m = m;
+  p.n_iter = c->cfg.slice_steps_per_dim * c->sh.d;
+  p.w = c->cfg.step_width;
+  p.max_stepout = c->cfg.max_stepout;
+  p.max_shrink = c->cfg.max_shrink;
+  p.corr = corr;
+  p.seed = c->cfg.seed;
+  if (c->batched) {
+    ns_status r = run_rounds(c, m);
+    if (r != NS_OK) return r;
+  } else {
+    TimeScope ts(c, NS_TIME_SLICE);
+    NS_TRY(launch_slice(c->sh, c->b, c->lik, p, c->stream));
+  }
+  {
+    TimeScope ts(c, NS_TIME_CORRECT);
+    NS_TRY(launch_correct(c->sh, c->b, m, corr, c->cfg.history_iters, c->cfg.stop_frac, c->stream));
+  }
+  if (c->pending.size() > 4096) {
+    NS_TRY(hipStreamSynchronize(c->stream));
+    drain_timing(c);
+  }
+  c->since_cluster += m;
+  c->dead_ub += m;
+  c->last_m = m;
+  poll(c);
+  return c->known_done ? NS_DONE : NS_OK;
+}
+
+ns_status ns_sync(ns_ctx* c) {
+  if (!c) return NS_EINVAL;
+  NS_TRY(hipStreamSynchronize(c->stream));
+  drain_timing(c);
+  NS_TRY(hipMemcpy(c->h_st, c->b.st, sizeof(RunState), hipMemcpyDeviceToHost));
+  c->poll_pending = false;
+  if (c->h_st->done) c->known_done = true;
+  return NS_OK;
+}
+
+ns_status ns_run(ns_ctx* c, int m, int64_t max_steps, int64_t* steps) {
+  if (!c) return NS_EINVAL;
+  NS_TRY(hipStreamSynchronize(c->stream));
+  NS_TRY(hipMemcpy(c->h_st, c->b.st, sizeof(RunState), hipMemcpyDeviceToHost));
+  const int64_t s0 = c->h_st->step;
+  c->known_done = c->h_st->done != 0;
+  for (int64_t k = 0; k < max_steps && !c->known_done; ++k) {
+    ns_status r = ns_step_batch(c, m);
+    if (r < 0) return r;
+  }
+  ns_status r = ns_sync(c);
+  if (r != NS_OK) return r;
+  if (steps) *steps = c->h_st->step - s0;
+  return c->known_done ? NS_DONE : NS_OK;
+}
+
+ns_status ns_logZ(ns_ctx* c, double* logZ, double* sigma, double* H) {
+  if (!c) return NS_EINVAL;
+  NS_TRY(launch_final_logZ(c->sh, c->b, c->d_out3, c->stream));
+  double o[3];
+  NS_TRY(hipMemcpyAsync(o, c->d_out3, sizeof(o), hipMemcpyDeviceToHost, c->stream));
+  NS_TRY(hipStreamSynchronize(c->stream));
+  if (logZ) *logZ = o[0];
+  if (sigma) *sigma = o[1];
+  if (H) *H = o[2];
+  return NS_OK;
+}
+
+ns_status ns_get_dead(ns_ctx* c, int64_t* n, double* u, double* logL, double* logX, double* logw) {
+  if (!c || !n) return NS_EINVAL;
+  ns_status r = ns_sync(c);
+  if (r != NS_OK) return r;
+  const int64_t nd = c->h_st->n_dead;
+  *n = nd;
+  if (!u && !logL && !logX && !logw) return NS_OK;
+  const int d = c->sh.d;
+  std::vector<double> hl(nd);
+  if (u && nd) NS_TRY(hipMemcpy(u, c->b.dead_u, sizeof(double) * nd * d, hipMemcpyDeviceToHost));
+  if (nd) NS_TRY(hipMemcpy(hl.data(), c->b.dead_logL, sizeof(double) * nd, hipMemcpyDeviceToHost));
+  const double N = static_cast<double>(c->sh.N);
+  const double lw0 = std::log(-std::expm1(-1.0 / N));
+  for (int64_t i = 0; i < nd; ++i) {
+    if (logL) logL[i] = hl[i];
+    if (logX) logX[i] = -static_cast<double>(i + 1) / N;
+    if (logw) logw[i] = (hl[i] - static_cast<double>(i) / N) + lw0;
+  }
+  return NS_OK;
+}
+
+ns_status ns_get_live(ns_ctx* c, double* u, double* logL, int* label) {
+  if (!c) return NS_EINVAL;
+  ns_status r = ns_sync(c);
+  if (r != NS_OK) return r;
+  const size_t N = c->sh.N, d = c->sh.d;
+  if (u) {
+    if (c->sh.state_f32) {
+      std::vector<float> t(N * d);
+      NS_TRY(hipMemcpy(t.data(), c->b.u, sizeof(float) * N * d, hipMemcpyDeviceToHost));
+      for (size_t q = 0; q < N * d; ++q) u[q] = t[q];
+    } else {
+      NS_TRY(hipMemcpy(u, c->b.u, sizeof(double) * N * d, hipMemcpyDeviceToHost));
+    }
+  }
+  if (logL) NS_TRY(hipMemcpy(logL, c->b.logL, sizeof(double) * N, hipMemcpyDeviceToHost));
+  if (label) NS_TRY(hipMemcpy(label, c->b.label, sizeof(int) * N, hipMemcpyDeviceToHost));
+  return NS_OK;
+}
+
+ns_status ns_set_live(ns_ctx* c, const double* u, const double* logL, const int* label) {
+  if (!c) return NS_EINVAL;
+  ns_status r = ns_sync(c);
+  if (r != NS_OK) return r;
+  const size_t N = c->sh.N, d = c->sh.d;
+  if (u) {
+    if (c->sh.state_f32) {
+      std::vector<float> t(N * d);
+      for (size_t q = 0; q < N * d; ++q) t[q] = static_cast<float>(u[q]);
+      NS_TRY(hipMemcpy(c->b.u, t.data(), sizeof(float) * N * d, hipMemcpyHostToDevice));
+    } else {
+      NS_TRY(hipMemcpy(c->b.u, u, sizeof(double) * N * d, hipMemcpyHostToDevice));
+    }
+  }
+  if (logL) NS_TRY(hipMemcpy(c->b.logL, logL, sizeof(double) * N, hipMemcpyHostToDevice));
+  if (label) NS_TRY(hipMemcpy(c->b.label, label, sizeof(int) * N, hipMemcpyHostToDevice));
+  return NS_OK;
+}
+
+ns_status ns_get_tree(ns_ctx* c, int* n_nodes, int* count, int* accepted, int* split_ok,
+                      double* logV, double* centre, double* chol) {
+  if (!c) return NS_EINVAL;
+  ns_status r = ns_sync(c);
+  if (r != NS_OK) return r;
+  const int nodes = c->sh.nodes, d = c->sh.d;
+  if (n_nodes) *n_nodes = nodes;
+  if (count) NS_TRY(hipMemcpy(count, c->b.count, sizeof(int) * nodes, hipMemcpyDeviceToHost));
+  if (accepted) NS_TRY(hipMemcpy(accepted, c->b.accepted, sizeof(int) * nodes, hipMemcpyDeviceToHost));
+  if (split_ok) NS_TRY(hipMemcpy(split_ok, c->b.split_ok, sizeof(int) * nodes, hipMemcpyDeviceToHost));
+  if (logV) NS_TRY(hipMemcpy(logV, c->b.logV, sizeof(double) * nodes, hipMemcpyDeviceToHost));
+  if (centre || chol) {
+    std::vector<double> cen(static_cast<size_t>(nodes) * kMaxD), ch(static_cast<size_t>(nodes) * kMaxD * kMaxD);
+    NS_TRY(hipMemcpy(cen.data(), c->b.centre, sizeof(double) * cen.size(), hipMemcpyDeviceToHost));
+    NS_TRY(hipMemcpy(ch.data(), c->b.chol, sizeof(double) * ch.size(), hipMemcpyDeviceToHost));
+    for (int n = 0; n < nodes; ++n)
+      for (int i = 0; i < d; ++i) {
+        if (centre) centre[n * d + i] = cen[static_cast<size_t>(n) * kMaxD + i];
+        if (chol)
+          for (int j = 0; j < d; ++j)
+            chol[(static_cast<size_t>(n) * d + i) * d + j] = ch[(static_cast<size_t>(n) * kMaxD + i) * kMaxD + j];
+      }
+  }
+  return NS_OK;
+}
+
+ns_status ns_get_last_batch(ns_ctx* c, int* m_out, int* seeds, double* tau, double* new_u,
+                            double* new_logL, int64_t* chain_evals, double* hist_logL,
+                            double* hist_u, int* hist_n) {
+  if (!c) return NS_EINVAL;
+  ns_status r = ns_sync(c);
+  if (r != NS_OK) return r;
+  const int m = c->last_m;
+  if (m_out) *m_out = m;
+  if (m < 1) return inval(c, "ns_get_last_batch: no step has run yet");
+  const int d = c->sh.d, T = c->sh.T;
+  if (seeds) NS_TRY(hipMemcpy(seeds, c->b.seeds, sizeof(int) * m, hipMemcpyDeviceToHost));
+  if (tau) NS_TRY(hipMemcpy(tau, c->b.tau, sizeof(double) * m, hipMemcpyDeviceToHost));
+  if (new_logL) NS_TRY(hipMemcpy(new_logL, c->b.new_logL, sizeof(double) * m, hipMemcpyDeviceToHost));
+  if (hist_logL) NS_TRY(hipMemcpy(hist_logL, c->b.hist_logL, sizeof(double) * T * m, hipMemcpyDeviceToHost));
+  if (hist_n) NS_TRY(hipMemcpy(hist_n, c->b.hist_n, sizeof(int) * m, hipMemcpyDeviceToHost));
+  if (chain_evals) {
+    std::vector<int> cs(4 * m);
+    NS_TRY(hipMemcpy(cs.data(), c->b.chain_stat, sizeof(int) * 4 * m, hipMemcpyDeviceToHost));
+    for (int j = 0; j < m; ++j) chain_evals[j] = cs[4 * j];
+  }
+  auto conv = [&](const void* src, size_t n, double* dst) -> hipError_t {
+    if (c->sh.state_f32) {
+      std::vector<float> t(n);
+      hipError_t e = hipMemcpy(t.data(), src, sizeof(float) * n, hipMemcpyDeviceToHost);
+      for (size_t q = 0; q < n; ++q) dst[q] = t[q];
+      return e;
+    }
+    return hipMemcpy(dst, src, sizeof(double) * n, hipMemcpyDeviceToHost);
+  };
+  if (new_u) NS_TRY(conv(c->b.new_u, static_cast<size_t>(m) * d, new_u));
+  if (hist_u) NS_TRY(conv(c->b.hist_u, static_cast<size_t>(m) * T * d, hist_u));
+  return NS_OK;
+}
+
+ns_status ns_stats(ns_ctx* c, ns_stats_t* s) {
+  if (!c || !s) return NS_EINVAL;
+  ns_status r = ns_sync(c);
+  if (r != NS_OK) return r;
+  const RunState& h = *c->h_st;
+  s->steps = h.step;
+  s->dead = h.n_dead;
+  s->evals = static_cast<int64_t>(h.evals);
+  s->oob = static_cast<int64_t>(h.oob);
+  s->stepout_caps = static_cast<int64_t>(h.so_caps);
+  s->shrink_caps = static_cast<int64_t>(h.sh_caps);
+  s->clusterings = static_cast<int64_t>(h.clusterings);
+  s->nan_logL = static_cast<int64_t>(h.nan_logL);
+  s->done = h.done;
+  std::vector<int> acc(c->sh.nodes);
+  NS_TRY(hipMemcpy(acc.data(), c->b.accepted, sizeof(int) * acc.size(), hipMemcpyDeviceToHost));
+  int nc = 0;
+  for (int a : acc) nc += a;
+  s->n_clusters = nc;
+  return NS_OK;
+}
+
+ns_status ns_loglike_batch(ns_ctx* c, const double* d_u, int64_t n, double* d_out) {
+  if (!c || (n > 0 && (!d_u || !d_out)) || n < 0) return inval(c, "ns_loglike_batch: bad arguments");
+  if (!c->batched) {
+    NS_TRY(launch_loglike_points(c->sh, c->lik, d_u, static_cast<long>(n), d_out, c->stream));
+    return NS_OK;
+  }
+  for (int64_t k0 = 0; k0 < n; k0 += c->rb.rows_cap) {
+    const long nn = static_cast<long>(std::min<int64_t>(c->rb.rows_cap, n - k0));
+    NS_TRY(launch_rows_from_points(nn, c->sh.d, d_u + k0 * c->sh.d, c->rp, c->sh.state_f32, c->rb.pts,
+                                   c->rb.xin, c->rb.flag, c->stream));
+    ns_status r = eval_rows(c, nn, nullptr);
+    if (r != NS_OK) return r;
+    NS_TRY(hipMemcpyAsync(d_out + k0, c->rb.rlogL, sizeof(double) * nn, hipMemcpyDeviceToDevice,
+                          c->stream));
+  }
+  return NS_OK;
+}
+
+ns_status ns_select_order(const double* d_logL, int N, int* d_order, void* hip_stream) {
+  ns_ctx* c = nullptr;
+  if (!d_logL || !d_order || N < 1 || N > 8192) return inval(nullptr, "ns_select_order: bad arguments");
+  NS_TRY(launch_select_order(d_logL, N, d_order, static_cast<hipStream_t>(hip_stream)));
+  return NS_OK;
+}
+
+ns_status ns_correct_batch(int m, ns_corr corr, int K, int T, const double* d_wlogL,
+                           const double* d_nlogL, const double* d_P, const double* d_hist,
+                           const int* d_hist_n, int* d_acc_code, int* d_acc_hslot,
+                           double* d_acc_logL, int* d_rej_code, int* d_rej_hslot,
+                           double* d_rej_logL, void* hip_stream) {
+  ns_ctx* c = nullptr;
+  if (m < 1 || m > 1024 || T < 2 || K < 0 || corr < NS_CORR_NONE || corr > NS_CORR_HISTORY)
+    return inval(nullptr, "ns_correct_batch: bad arguments");
+  if (!d_wlogL || !d_nlogL || !d_P || !d_hist || !d_hist_n || !d_acc_code || !d_acc_hslot ||
+      !d_acc_logL || !d_rej_code || !d_rej_hslot || !d_rej_logL)
+    return inval(nullptr, "ns_correct_batch: null pointer");
+  NS_TRY(launch_correct_arrays(m, static_cast<int>(corr), K, T, d_wlogL, d_nlogL, d_P, d_hist,
+                               d_hist_n, d_acc_code, d_acc_hslot, d_acc_logL, d_rej_code,
+                               d_rej_hslot, d_rej_logL, static_cast<hipStream_t>(hip_stream)));
+  return NS_OK;
+}
+
+ns_status ns_philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n,
+                    uint32_t* d_out, void* hip_stream) {
+  ns_ctx* c = nullptr;
+  if (n < 0 || (n > 0 && !d_out)) return inval(nullptr, "ns_philox: bad arguments");
+  NS_TRY(launch_philox(seed, c0, c1, c2, c3, static_cast<long>(n), d_out,
+                       static_cast<hipStream_t>(hip_stream)));
+  return NS_OK;
+}
+
+ns_status ns_set_timing(ns_ctx* c, int on) {
+  if (!c) return NS_EINVAL;
+  ns_status r = ns_sync(c);
+  if (r != NS_OK) return r;
+  c->timing = on != 0;
+  for (int k = 0; k < NS_TIMING_CLASSES; ++k) { c->t_ms[k] = 0.0; c->t_n[k] = 0; }
+  return NS_OK;
+}
+
+ns_status ns_get_timing(ns_ctx* c, double* ms, int64_t* launches) {
+  if (!c) return NS_EINVAL;
+  ns_status r = ns_sync(c);
+  if (r != NS_OK) return r;
+  for (int k = 0; k < NS_TIMING_CLASSES; ++k) {
+    if (ms) ms[k] = c->t_ms[k];
+    if (launches) launches[k] = c->t_n[k];
+  }
+  return NS_OK;
+}
+
+static ns_status check_net(const ns_mlp_desc* net, ns_prec prec, int64_t B) {
+  if (!net || net->n_layers < 1 || net->n_layers > 8 || B < 0 || B > (1ll << 30))
+    return inval(nullptr, "ns_mlp: bad network or batch");
+  if (prec != NS_FP32 && prec != NS_BF16 && prec != NS_BF16X3)
+    return inval(nullptr, "ns_mlp: prec must be FP32, BF16 or BF16X3");
+  if (net->act != NS_ACT_TANH && net->act != NS_ACT_SILU) return inval(nullptr, "ns_mlp: unknown act");
+  for (int l = 0; l <= net->n_layers; ++l)
+    if (net->widths[l] < 1 || net->widths[l] > 4096) return inval(nullptr, "ns_mlp: widths in [1, 4096]");
+  for (int l = 0; l < net->n_layers; ++l)
+    if (!net->W[l] || !net->b[l]) return inval(nullptr, "ns_mlp: null weights");
+  return NS_OK;
+}
+
+ns_status ns_mlp_forward(const ns_mlp_desc* net, ns_prec prec, const float* d_X, int64_t B,
+                         float* d_Y, float* d_Z, float* d_H, void* hip_stream) {
+  ns_ctx* c = nullptr;
+  ns_status r = check_net(net, prec, B);
+  if (r != NS_OK) return r;
+  if (B == 0) return NS_OK;
+  if (!d_X || !d_Y) return inval(nullptr, "ns_mlp_forward: null input or output");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int mode = prec == NS_BF16X3 ? kBF16S : (prec == NS_BF16 ? kBF16 : kF32);
+  const int L = net->n_layers;
+  const float* in = d_X;
+  long off = 0;
+  for (int l = 0; l < L; ++l) {
+    const int K = net->widths[l], N = net->widths[l + 1];
+    const bool last = l == L - 1;
+    float* out = last ? d_Y : (d_H ? d_H + off : nullptr);
+    if (!out) return inval(nullptr, "ns_mlp_forward: d_H is required for hidden layers");
+    float* z = d_Z ? d_Z + off : nullptr;
+    // W row major K x N: B(k, n) = W[k*N + n]
+    NS_TRY(launch_gemm(mode, static_cast<int>(B), N, K, in, K, 1, net->W[l], 1, N, net->b[l],
+                       last ? kActNone : net->act, out, N, z, N, nullptr, s));
+    in = out;
+    off += B * N;
+  }
+  return NS_OK;
+}
+
+ns_status ns_mlp_backward(const ns_mlp_desc* net, ns_prec prec, const float* d_X, int64_t B,
+                          const float* d_Z, const float* d_H, const float* d_dY,
+                          float* const* d_dW, float* const* d_db, float* d_dX, float* d_work,
+                          void* hip_stream) {
+  ns_ctx* c = nullptr;
+  ns_status r = check_net(net, prec, B);
+  if (r != NS_OK) return r;
+  if (!d_X || !d_Z || !d_dY || !d_dW || !d_db || !d_work || (net->n_layers > 1 && !d_H))
+    return inval(nullptr, "ns_mlp_backward: null argument");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int mode = prec == NS_BF16X3 ? kBF16S : (prec == NS_BF16 ? kBF16 : kF32);
+  const int L = net->n_layers;
+  int maxw = 0;
+  for (int l = 0; l <= L; ++l) maxw = std::max(maxw, net->widths[l]);
+  float* dZ = d_work;
+  float* dH = d_work + B * maxw;
+  std::vector<long> off(L + 1, 0);
+  for (int l = 0; l < L; ++l) off[l + 1] = off[l] + B * net->widths[l + 1];
+  const float* g = d_dY;   // gradient w.r.t. the output of layer l
+  for (int l = L - 1; l >= 0; --l) {
+    const int K = net->widths[l], N = net->widths[l + 1];
+    const float* dz = g;
+    if (l < L - 1) {
+      NS_TRY(launch_act_bwd(B * N, net->act, d_Z + off[l], g, dZ, s));
+      dz = dZ;
+    }
+    const float* hin = (l == 0) ? d_X : d_H + off[l - 1];
+    // dW = H^T dZ : M = K, N = N, depth B
+    NS_TRY(launch_gemm(mode, K, N, static_cast<int>(B), hin, 1, K, dz, 1, N, nullptr, kActNone,
+                       d_dW[l], N, nullptr, 0, nullptr, s));
+    NS_TRY(launch_colsum(static_cast<int>(B), N, dz, d_db[l], s));
+    if (l > 0 || d_dX) {
+      float* out = (l == 0) ? d_dX : dH;
+      // dH = dZ W^T : M = B, N = K, depth N; B(k=n, col=i) = W[i*N + n]
+      NS_TRY(launch_gemm(mode, static_cast<int>(B), K, N, dz, N, 1, net->W[l], N, 1, nullptr, kActNone,
+                         out, K, nullptr, 0, nullptr, s));
+      if (l > 0) {
+        // move dH into place for the next layer (dZ buffer is reused)
+        g = dH;
+        std::swap(dZ, dH);
+      }
+    }
+  }
+  return NS_OK;
+}
+
+const char* ns_last_error(const ns_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+void ns_free(ns_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+}
+
+}  // extern "C"

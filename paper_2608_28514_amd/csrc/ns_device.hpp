@@ -1,0 +1,244 @@
+// ns_device.hpp -- device-side building blocks shared by the sampler kernels:
+// the Philox4x32-10 generator, the likelihood families, and the device state.
+// gfx950 only; wave64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <math.h>
+
+namespace ns {
+
+constexpr int kMaxD = 32;
+constexpr int kMaxNodes = 127;
+constexpr int kWave = 64;
+
+// Philox counter word 3 = stream << 24 | sub-index; word 2 = step; word 1 =
+// chain or point; word 0 = draw slot.
+constexpr uint32_t kStreamInit = 1, kStreamSeed = 2, kStreamSlice = 3;
+constexpr uint32_t kSlotDir0 = 0, kSlotStepout = 16, kSlotShrink0 = 32;
+
+enum LikKind : int { kMixture = 0, kRosenbrock = 1, kShell = 2, kMlp = 3 };
+enum Corr : int { kNone = 0, kBestOfWorst = 1, kSort = 2, kHistory = 3 };
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds with the
+// multipliers 0xD2511F53 / 0xCD9E8D57, Weyl key increments 0x9E3779B9 /
+// 0xBB67AE85.
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+  }
+  return c;
+}
+
+// A double in (0,1) from two words: (53 random bits + 0.5) * 2^-53.
+__device__ __forceinline__ double u01(uint32_t hi, uint32_t lo) {
+  const uint64_t v = (static_cast<uint64_t>(hi) << 21) | static_cast<uint64_t>(lo >> 11);
+  return (static_cast<double>(v) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+struct Draw2 { double a, b; };
+__device__ __forceinline__ Draw2 uniform2(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                                          uint32_t c3) {
+  const U4 w = philox4x32_10(U4{c0, c1, c2, c3}, static_cast<uint32_t>(seed),
+                             static_cast<uint32_t>(seed >> 32));
+  return Draw2{u01(w.x, w.y), u01(w.z, w.w)};
+}
+
+// ---------------------------------------------------------------------------
+// Likelihood parameters (passed by value to kernels).  Arrays live in device
+// memory; each kernel reads them through the read-only path.
+struct LikDev {
+  int kind;
+  int d;
+  int n_comp;
+  double lo[kMaxD];
+  double span[kMaxD];    // hi - lo
+  float lo_f[kMaxD];
+  float span_f[kMaxD];
+  double ros_a, ros_b, shell_r0, shell_w;
+  const double* logw;    // K
+  const double* mu;      // K x d
+  const double* ivar;    // K x d
+  const float* logw_f;
+  const float* mu_f;
+  const float* ivar_f;
+};
+
+// Analytic families, in the likelihood precision LT (double or float).  `y`
+// holds unit-cube coordinates already known to be inside the box.
+template <typename LT>
+struct LikAt;
+
+template <>
+struct LikAt<double> {
+  template <typename T>
+  __device__ static double eval(const LikDev& P, const T* y) {
+    double th[kMaxD];
+    const int d = P.d;
+    for (int i = 0; i < d; ++i) th[i] = P.lo[i] + P.span[i] * static_cast<double>(y[i]);
+    if (P.kind == kMixture) {
+      if (P.n_comp == 1) {
+        double q = 0.0;
+        for (int i = 0; i < d; ++i) {
+          const double r = th[i] - P.mu[i];
+          q += r * r * P.ivar[i];
+        }
+        return P.logw[0] - 0.5 * q;
+      }
+      double best = -INFINITY;
+      for (int k = 0; k < P.n_comp; ++k) {
+        double q = 0.0;
+        for (int i = 0; i < d; ++i) {
+          const double r = th[i] - P.mu[k * d + i];
+          q += r * r * P.ivar[k * d + i];
+        }
+        const double e = P.logw[k] - 0.5 * q;
+        best = e > best ? e : best;
+      }
+      if (best == -INFINITY) return -INFINITY;
+      double s = 0.0;
+      for (int k = 0; k < P.n_comp; ++k) {
+        double q = 0.0;
+        for (int i = 0; i < d; ++i) {
+          const double r = th[i] - P.mu[k * d + i];
+          q += r * r * P.ivar[k * d + i];
+        }
+        s += exp((P.logw[k] - 0.5 * q) - best);
+      }
+      return best + log(s);
+    }
+    if (P.kind == kRosenbrock) {
+      double s = 0.0;
+      for (int i = 0; i + 1 < d; ++i) {
+        const double t = th[i + 1] - th[i] * th[i];
+        const double r = P.ros_a - th[i];
+        s += P.ros_b * t * t + r * r;
+      }
+      return -s;
+    }
+    // shell
+    double s = 0.0;
+    for (int i = 0; i < d; ++i) s += th[i] * th[i];
+    const double r = (sqrt(s) - P.shell_r0) / P.shell_w;
+    return -0.5 * r * r;
+  }
+};
+
+template <>
+struct LikAt<float> {
+  template <typename T>
+  __device__ static double eval(const LikDev& P, const T* y) {
+    float th[kMaxD];
+    const int d = P.d;
+    for (int i = 0; i < d; ++i) th[i] = P.lo_f[i] + P.span_f[i] * static_cast<float>(y[i]);
+    if (P.kind == kMixture) {
+      if (P.n_comp == 1) {
+        float q = 0.0f;
+        for (int i = 0; i < d; ++i) {
+          const float r = th[i] - P.mu_f[i];
+          q += r * r * P.ivar_f[i];
+        }
+        return static_cast<double>(P.logw_f[0] - 0.5f * q);
+      }
+      float best = -INFINITY;
+      for (int k = 0; k < P.n_comp; ++k) {
+        float q = 0.0f;
+        for (int i = 0; i < d; ++i) {
+          const float r = th[i] - P.mu_f[k * d + i];
+          q += r * r * P.ivar_f[k * d + i];
+        }
+        const float e = P.logw_f[k] - 0.5f * q;
+        best = e > best ? e : best;
+      }
+      if (best == -INFINITY) return -INFINITY;
+      float s = 0.0f;
+      for (int k = 0; k < P.n_comp; ++k) {
+        float q = 0.0f;
+        for (int i = 0; i < d; ++i) {
+          const float r = th[i] - P.mu_f[k * d + i];
+          q += r * r * P.ivar_f[k * d + i];
+        }
+        s += expf((P.logw_f[k] - 0.5f * q) - best);
+      }
+      return static_cast<double>(best + logf(s));
+    }
+    if (P.kind == kRosenbrock) {
+      float s = 0.0f;
+      const float a = static_cast<float>(P.ros_a), b = static_cast<float>(P.ros_b);
+      for (int i = 0; i + 1 < d; ++i) {
+        const float t = th[i + 1] - th[i] * th[i];
+        const float r = a - th[i];
+        s += b * t * t + r * r;
+      }
+      return static_cast<double>(-s);
+    }
+    float s = 0.0f;
+    for (int i = 0; i < d; ++i) s += th[i] * th[i];
+    const float r = (sqrtf(s) - static_cast<float>(P.shell_r0)) / static_cast<float>(P.shell_w);
+    return static_cast<double>(-0.5f * r * r);
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ bool in_box(const T* y, int d) {
+  bool ok = true;
+  for (int i = 0; i < d; ++i) ok = ok && (y[i] >= T(0) && y[i] <= T(1));
+  return ok;
+}
+
+// NaN likelihoods count as -inf (they can never satisfy a hard constraint).
+__device__ __forceinline__ double clean_logL(double v) { return isnan(v) ? -INFINITY : v; }
+
+// Order-preserving map of a canonical double (no NaN, -0 folded) to uint64.
+__device__ __forceinline__ double canon(double x) {
+  return isnan(x) ? -INFINITY : (x == 0.0 ? 0.0 : x);
+}
+__device__ __forceinline__ uint64_t order_key(double x) {
+  const uint64_t b = static_cast<uint64_t>(__double_as_longlong(canon(x)));
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// Direction math in the state precision (Box-Muller radius, sin/cos, sqrt).
+template <typename T>
+struct DirMath;
+template <>
+struct DirMath<double> {
+  __device__ static double r_of(double u) { return sqrt(-2.0 * log(u)); }
+  __device__ static void sc(double a, double* s, double* c) { *s = sin(a); *c = cos(a); }
+  __device__ static double sq(double x) { return sqrt(x); }
+};
+template <>
+struct DirMath<float> {
+  __device__ static float r_of(float u) { return sqrtf(-2.0f * logf(u)); }
+  __device__ static void sc(float a, float* s, float* c) { *s = sinf(a); *c = cosf(a); }
+  __device__ static float sq(float x) { return sqrtf(x); }
+};
+
+// ---------------------------------------------------------------------------
+// Device-resident run state (one per context).
+struct RunState {
+  int64_t step;          // steps that did work (Philox word 2)
+  int64_t n_dead;
+  double logZ;           // running log evidence of the dead points
+  double A;              // Z-weighted mean of logL of the dead points
+  int32_t done;
+  int32_t pad;
+  // counters
+  unsigned long long evals, oob, so_caps, sh_caps, nan_logL, clusterings;
+};
+
+__device__ __forceinline__ double logaddexp(double a, double b) {
+  if (a == -INFINITY) return b;
+  if (b == -INFINITY) return a;
+  const double mx = a > b ? a : b;
+  return mx + log1p(exp(-fabs(a - b)));
+}
+
+}  // namespace ns

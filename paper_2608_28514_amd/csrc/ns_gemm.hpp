@@ -1,0 +1,37 @@
+// ns_gemm.hpp -- launchers of the dense-layer kernels (k_gemm.hip) and of the
+// round-based slice sampler used with network likelihoods (k_slice_rounds.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "ns_device.hpp"
+
+namespace ns {
+
+enum GemmMode : int { kF32 = 0, kBF16S = 1, kBF16 = 2 };
+enum Act : int { kActNone = 0, kActTanh = 1, kActSilu = 2 };
+
+hipError_t launch_gemm(int mode, int M, int N, int K, const float* A, long sar, long sak,
+                       const float* B, long sbn, long sbk, const float* bias, int act, float* C,
+                       long ldc, float* Z, long ldz, const int* gate, hipStream_t s);
+hipError_t launch_act_bwd(long n, int act, const float* Z, const float* dH, float* dZ, hipStream_t s);
+hipError_t launch_colsum(int M, int N, const float* dZ, float* db, hipStream_t s);
+hipError_t launch_chi2(int M, int N, const float* Y, const double* data, const double* isig,
+                       const int* flag, double* logL, const int* gate, hipStream_t s);
+
+// A network held on the device: layer l maps widths[l] -> widths[l+1]; the
+// weights are stored transposed (Wt_l: widths[l+1] x widths[l], FP32).
+struct NetDev {
+  int n_layers;
+  int widths[9];
+  int act;              // hidden activation (output layer is linear)
+  const float* Wt[8];
+  const float* b[8];
+  int max_width;
+};
+
+// Forward over M rows of X (M x widths[0]); H0/H1 ping-pong buffers of
+// M x max_width floats; output Y (M x widths[L]).  mode_first applies to
+// layer 0, mode_rest to the others.
+hipError_t net_forward(const NetDev& net, int mode_first, int mode_rest, int M, const float* X,
+                       float* H0, float* H1, float* Y, const int* gate, hipStream_t s);
+
+}  // namespace ns

@@ -1,0 +1,81 @@
+// ns_internal.hpp -- host-side view of the device buffers of one sampler
+// context and the kernel launchers that operate on them.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "ns_device.hpp"
+
+namespace ns {
+
+// Device pointers of one context.  Sizes: N live points, d dims, M = max batch
+// (chains), T = history capacity, nodes = 2^(D+1)-1.
+struct DevBufs {
+  void* u;              // N x d, state precision
+  double* logL;         // N
+  int* label;           // N (cluster node)
+  int* order;           // N (ascending (logL, slot))
+  int* seeds;           // M
+  double* tau;          // M (shrink thresholds)
+  double* LW;           // M (logL of the m worst, ascending)
+  void* new_u;          // M x d
+  double* new_logL;     // M
+  int* chain_stat;      // M x 4: evals, oob, stepout caps, shrink caps
+  double* hist_logL;    // T x M (row t, column chain)
+  void* hist_u;         // M x T x d
+  int* hist_n;          // M
+  // cluster tree
+  int* nodeof;          // N: deepest tree node of each point
+  int* members;         // nodes x N scratch
+  int* count;           // nodes
+  int* accepted;        // nodes
+  int* split_ok;        // nodes
+  double* logV;         // nodes
+  double* logV_eff;     // nodes
+  double* centre;       // nodes x 32
+  double* cov;          // nodes x 32 x 32
+  double* chol;         // nodes x 32 x 32
+  float* chol_f;        // nodes x 32 x 32
+  // dead store
+  double* dead_u;       // cap x d
+  double* dead_logL;    // cap
+  RunState* st;
+};
+
+struct Shape {
+  int N, d, T, nodes, depth;
+  int state_f32;   // sampler state in FP32 (else FP64)
+  int lik_f32;     // analytic likelihood in FP32 (else FP64)
+};
+
+struct SliceParams {
+  int m;
+  int n_iter;
+  double w;
+  int max_stepout;
+  int max_shrink;
+  int corr;
+  uint64_t seed;
+};
+
+// kernels.  Every launcher enqueues on `s` and returns hipGetLastError().
+hipError_t launch_init_points(const Shape& sh, const DevBufs& b, const LikDev& lik, uint64_t seed,
+                              hipStream_t s);
+hipError_t launch_loglike_points(const Shape& sh, const LikDev& lik, const double* u, long n,
+                                 double* out, hipStream_t s);
+hipError_t launch_select(const Shape& sh, const DevBufs& b, int m, int corr, uint64_t seed,
+                         hipStream_t s);
+hipError_t launch_select_order(const double* logL, int N, int* order, hipStream_t s);
+hipError_t launch_slice(const Shape& sh, const DevBufs& b, const LikDev& lik, const SliceParams& p,
+                        hipStream_t s);
+hipError_t launch_correct(const Shape& sh, const DevBufs& b, int m, int corr, int K,
+                          double stop_frac, hipStream_t s);
+hipError_t launch_correct_arrays(int m, int corr, int K, int T, const double* wlogL,
+                                 const double* nlogL, const double* P, const double* hist,
+                                 const int* hist_n, int* acc_code, int* acc_hslot, double* acc_logL,
+                                 int* rej_code, int* rej_hslot, double* rej_logL, hipStream_t s);
+hipError_t launch_cluster(const Shape& sh, const DevBufs& b, double p, int nmin, int iters,
+                          double eps, hipStream_t s);
+hipError_t launch_final_logZ(const Shape& sh, const DevBufs& b, double* out3, hipStream_t s);
+hipError_t launch_philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, long n,
+                         uint32_t* out, hipStream_t s);
+
+}  // namespace ns

@@ -1,0 +1,53 @@
+// ns_rounds.hpp -- state and launchers of the round-based slice sampler
+// (k_slice_rounds.hip), used when the likelihood is evaluated in batches.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "ns_internal.hpp"
+
+namespace ns {
+
+enum Phase : int { kPhaseDir = 0, kPhaseStepout = 1, kPhaseShrink = 2, kPhaseDone = 3 };
+
+template <typename T>
+struct ChainState {
+  T x[kMaxD];
+  T v[kMaxD];
+  double lx;
+  T a0, b0, a, b, br_a, br_b;
+  int it, phase, ka, kb, base, s0, hn, n_evals, n_oob, n_so, n_sh, label, seed_slot, pad;
+};
+
+struct RoundsParams {
+  int m, d, T, P, n_iter, so_spec, sh_spec, max_stepout, max_shrink;
+  double w;
+  uint64_t seed;
+  float lo_f[kMaxD];
+  float span_f[kMaxD];
+};
+
+struct RoundBufs {
+  void* cs;        // m chain states
+  void* pts;       // rows x d, state precision
+  float* xin;      // rows x d, network input theta
+  int* flag;       // rows: 1 = in the box, evaluate
+  double* rlogL;   // rows
+  int* gate;       // per round: some chain still running
+  long rows_cap;
+  int gate_cap;
+  float* H0;       // rows x max_width
+  float* H1;
+  float* Y;        // rows x out_width
+};
+
+hipError_t launch_fill_int(int* p, long n, int v, hipStream_t s);
+hipError_t launch_rounds_advance(int round, const RoundsParams& p, const Shape& sh, const DevBufs& b,
+                                 const RoundBufs& r, hipStream_t s);
+hipError_t launch_rows_from_points(long n, int d, const double* u, const RoundsParams& p,
+                                   int state_f32, void* pts, float* xin, int* flag, hipStream_t s);
+hipError_t launch_init_rows(int N, int d, uint64_t seed, const RoundsParams& p, int state_f32, void* u,
+                            void* pts, float* xin, int* flag, hipStream_t s);
+// analytic likelihood on rows (the batched driver with an analytic family)
+hipError_t launch_rows_loglike(const Shape& sh, const LikDev& lik, long n, const void* pts,
+                               const int* flag, double* out, const int* gate, hipStream_t s);
+
+}  // namespace ns

@@ -1,0 +1,180 @@
+"""GPU parity of the batched-round slice sampler and of the dense-network
+kernels (emulator likelihood, surrogate forward/backward) against the FP64
+oracle.
+
+* Rounds driver, FP64 state, analytic likelihood: the whole run equals the
+  oracle's within 1e-10 (same draws, same decisions).
+* Rounds driver, FP32 state: bit-identical to the single-kernel path.
+* Dense layers: each GEMM output within the FP32-accumulation bound
+  gamma_K * sum |a||w| (gamma_K = K 2^-24) of the FP64 product; single-bfloat16
+  operands within the bfloat16 rounding bound.
+* Network backward: against the oracle's FP64 backward within FP32 bounds.
+* Emulator likelihood: quantiles of |dlogL| against the FP64 oracle.
+"""
+import math
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2608_28514_amd import native, workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _close(got, ref, rtol):
+    got, ref = np.asarray(got), np.asarray(ref)
+    if not np.array_equal(np.isinf(got), np.isinf(ref)):
+        return False
+    f = np.isfinite(ref)
+    return bool(np.all(np.abs(got[f] - ref[f]) <= rtol * np.maximum(1.0, np.abs(ref[f]))))
+
+
+@pytest.mark.parametrize("spec_name,N,m,depth,corr", [
+    ("c1", 100, 1, 0, "history"),
+    ("eq5", 200, 10, 1, "history"),
+    ("array", 300, 30, 3, "sort"),
+])
+def test_rounds_fp64_matches_oracle(spec_name, N, m, depth, corr):
+    spec = {"c1": W.likelihood(1), "eq5": W.paper_problem("eq5_gauss2d"),
+            "array": W.paper_problem("test1_array49")}[spec_name]
+    s = native.Sampler(spec, N, seed=4, tree_depth=depth, correction=corr, batch_rounds=1)
+    o = oracle.Oracle(spec, N, seed=4, tree_depth=depth, correction=corr)
+    s.run(m)
+    o.run(m)
+    g, r = s.dead(), o.dead()
+    assert g["logL"].size == r["logL"].size
+    assert _close(g["logL"], r["logL"], 1e-10)
+    assert np.allclose(g["u"], r["u"], rtol=0, atol=1e-10)
+    st, oc = s.stats(), o.counters()
+    assert st["evals"] == oc["evals"] and st["oob"] == oc["oob"] and st["steps"] == oc["steps"]
+
+
+@pytest.mark.parametrize("so,sh", [(4, 8), (1, 1), (32, 64), (3, 5)])
+def test_rounds_fp32_identical_to_fused_kernel(so, sh):
+    spec = W.likelihood(3, seed=2)
+    kw = dict(prec="f32", state="f32", seed=2, tree_depth=3)
+    a = native.Sampler(spec, 1000, **kw)
+    b = native.Sampler(spec, 1000, batch_rounds=1, stepout_spec=so, shrink_spec=sh, **kw)
+    a.run(100, max_steps=20)
+    b.run(100, max_steps=20)
+    da, db = a.dead(), b.dead()
+    assert np.array_equal(da["logL"], db["logL"])
+    assert np.array_equal(da["u"], db["u"])
+    sa, sb = a.stats(), b.stats()
+    for k in ("evals", "oob", "stepout_caps", "shrink_caps", "steps", "dead"):
+        assert sa[k] == sb[k], k
+
+
+def _gemm_ref(X, Wm):
+    return X.astype(np.float64) @ Wm.astype(np.float64)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "bf16"])
+@pytest.mark.parametrize("M,K,N", [(1, 27, 512), (200, 512, 512), (77, 33, 130), (1600, 512, 1024)])
+def test_dense_layer_bounds(prec, M, K, N):
+    rng = np.random.default_rng(M + K + N)
+    X = rng.normal(size=(M, K)).astype(np.float32)
+    Wm = W._round_bf16(rng.normal(size=(K, N)) * 0.1).astype(np.float32)
+    b = np.zeros(N, dtype=np.float32)
+    Xd = torch.tensor(X, device=DEV)
+    Yd = torch.zeros((M, N), dtype=torch.float32, device=DEV)
+    Wt = [torch.tensor(Wm, device=DEV)]
+    bt = [torch.tensor(b, device=DEV)]
+    d = native.mlp_desc(Wt, bt, "tanh")
+    native.ns_mlp_forward(d, prec, Xd, Yd)
+    torch.cuda.synchronize()
+    Y = Yd.cpu().numpy().astype(np.float64)
+    ref = _gemm_ref(X, Wm)
+    mag = np.abs(X).astype(np.float64) @ np.abs(Wm).astype(np.float64)
+    if prec == "bf16":
+        bound = (2.0 * 2.0 ** -8 + K * 2.0 ** -24) * mag
+    else:
+        bound = 2.0 * (K + 3) * 2.0 ** -24 * mag
+    assert np.all(np.abs(Y - ref) <= bound + 1e-30)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_network_backward_against_oracle(prec):
+    rng = np.random.default_rng(7)
+    widths = [27, 64, 48, 1]
+    Ws = [W._round_bf16(rng.normal(size=(widths[l], widths[l + 1])) * 0.3) for l in range(3)]
+    bs = [rng.normal(size=widths[l + 1]) * 0.1 for l in range(3)]
+    B = 300
+    X = rng.uniform(size=(B, 27)).astype(np.float32).astype(np.float64)
+    dY = rng.normal(size=(B, 1)).astype(np.float32).astype(np.float64)
+    Yr, acts = oracle.mlp_forward(widths, Ws, bs, 1, X)
+    dWr, dbr, dXr = oracle.mlp_backward(widths, Ws, bs, 1, X, acts, dY)
+    f32 = lambda a: torch.tensor(np.asarray(a, dtype=np.float32), device=DEV)
+    Wd, bd = [f32(w) for w in Ws], [f32(b) for b in bs]
+    desc = native.mlp_desc(Wd, bd, "silu")
+    Xd = f32(X)
+    Yd = torch.zeros((B, 1), dtype=torch.float32, device=DEV)
+    tot = B * sum(widths[1:])
+    Zd = torch.zeros(tot, dtype=torch.float32, device=DEV)
+    Hd = torch.zeros(tot, dtype=torch.float32, device=DEV)
+    native.ns_mlp_forward(desc, prec, Xd, Yd, Zd, Hd)
+    dWd = [torch.zeros_like(w) for w in Wd]
+    dbd = [torch.zeros_like(b) for b in bd]
+    dXd = torch.zeros_like(Xd)
+    work = torch.zeros(2 * B * max(widths), dtype=torch.float32, device=DEV)
+    native.ns_mlp_backward(desc, prec, Xd, Zd, Hd, f32(dY), dWd, dbd, dXd, work)
+    torch.cuda.synchronize()
+    assert np.allclose(Yd.cpu().numpy(), Yr, rtol=1e-4, atol=1e-5)
+    for l in range(3):
+        g, r = dWd[l].cpu().numpy(), dWr[l]
+        assert np.max(np.abs(g - r)) <= 1e-4 * max(1.0, np.max(np.abs(r))), l
+        g, r = dbd[l].cpu().numpy(), dbr[l]
+        assert np.max(np.abs(g - r)) <= 1e-4 * max(1.0, np.max(np.abs(r))), l
+    assert np.max(np.abs(dXd.cpu().numpy() - dXr)) <= 1e-4 * max(1.0, np.max(np.abs(dXr)))
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_emulator_loglike_quantiles(prec):
+    spec = W.emulator(seed=0)
+    rng = np.random.default_rng(1)
+    th0 = spec["theta0"]
+    near = np.clip(th0 + rng.normal(0, 3e-4, size=(300, 27)), 0, 1)
+    prior = rng.uniform(size=(200, 27))
+    u = np.concatenate([near, prior]).astype(np.float32).astype(np.float64)
+    s = native.Sampler(spec, 64, prec=prec, state="f32", seed=0, tree_depth=1)
+    d_u = torch.tensor(u, device=DEV)
+    d_o = torch.zeros(len(u), dtype=torch.float64, device=DEV)
+    native.ns_loglike_batch(s.ctx, d_u, d_o)
+    native.ns_sync(s.ctx)
+    got = d_o.cpu().numpy()
+    ref = oracle.loglike(spec, u)
+    dn = np.abs(got[:300] - ref[:300])
+    rel = np.abs(got[300:] - ref[300:]) / np.abs(ref[300:])
+    print(f"{prec}: near-posterior |dlogL| p50={np.median(dn):.3g} p99={np.quantile(dn, 0.99):.3g} "
+          f"(logL median {np.median(ref[:300]):.1f}); prior-typical rel p50={np.median(rel):.3g} "
+          f"p99={np.quantile(rel, 0.99):.3g}")
+    assert np.median(dn) < 1.0 and np.quantile(dn, 0.99) < 10.0
+    assert np.quantile(rel, 0.99) < 1e-4
+
+
+def test_small_emulator_run_agrees_with_oracle():
+    spec = W.emulator(seed=3, widths=(5, 32, 32, 32, 16), noise_frac=0.05)
+    res = {}
+    for prec in ("f32", "bf16x3"):
+        z = []
+        for seed in range(3):
+            s = native.Sampler(spec, 200, prec=prec, state="f32", seed=seed, tree_depth=1)
+            s.run(20)
+            z.append(s.logZ())
+        res[prec] = z
+    oracle.set_threads(8)
+    zo = []
+    for seed in range(3):
+        o = oracle.Oracle(spec, 200, seed=seed, tree_depth=1)
+        o.run(20)
+        zo.append(o.logZ())
+    oracle.set_threads(1)
+    mo = np.mean([x[0] for x in zo])
+    so = np.mean([x[1] for x in zo])
+    for prec, z in res.items():
+        mg = np.mean([x[0] for x in z])
+        sg = np.mean([x[1] for x in z])
+        print(prec, mg, mo, sg, so)
+        assert abs(mg - mo) < 2 * math.sqrt((sg ** 2 + so ** 2) / 3) * 1.5
