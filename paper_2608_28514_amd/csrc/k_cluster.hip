@@ -4,8 +4,8 @@
 // (ordered compaction), computes their mean and unbiased covariance in FP64,
 // and, above the last level, splits them with k-means (k = 2, Lloyd) started
 // from the point farthest from the mean and the point farthest from that one.
-// A second launch regularises every node's covariance (cyclic Jacobi in one
-// wave, eigenvalues clipped from below at eps * lambda_max, Cholesky, log
+// A second launch regularises every node's covariance (parallel-order Jacobi in
+// one wave, eigenvalues clipped from below at eps * lambda_max, Cholesky, log
 // volume = sum log L_ii); a last single-workgroup launch prunes the tree bottom
 // up (children kept when both hold more than n_min points and their combined
 // volume is more than p*100 % below the parent's) and labels every point with
@@ -15,7 +15,8 @@
 
 namespace ns {
 
-constexpr int kCT = 1024;  // threads of the per-node workgroup
+constexpr int kCT = 256;   // threads of the per-node workgroup
+constexpr int kCG = kCT / 32;  // coordinate groups of the per-coordinate sums
 
 // Exclusive scan of one flag per thread over the workgroup; returns the
 // thread's offset and writes the total to *total.
@@ -47,19 +48,19 @@ __device__ __forceinline__ double sqdist_pt(const T* x, const double* c, int d) 
 }
 
 // Per-coordinate sums over a member list.  Layout: thread (i = tid % 32,
-// g = tid / 32) sums members r = g, g+32, ...; then 32 partials per coordinate.
+// g = tid / 32) sums members r = g, g+kCG, ...; then kCG partials per coordinate.
 template <typename T>
 __device__ void coord_sums(const T* __restrict__ u, int d, const int* mem, int cnt,
-                           double* part /* 32x32 */, double* out /* 32 */) {
+                           double* part /* kCG x 32 */, double* out /* 32 */) {
   const int i = threadIdx.x & 31, g = threadIdx.x >> 5;
   double s = 0.0;
   if (i < d)
-    for (int r = g; r < cnt; r += 32) s += static_cast<double>(u[static_cast<long>(mem[r]) * d + i]);
+    for (int r = g; r < cnt; r += kCG) s += static_cast<double>(u[static_cast<long>(mem[r]) * d + i]);
   part[g * 32 + i] = s;
   __syncthreads();
   if (threadIdx.x < 32) {
     double t = 0.0;
-    for (int q = 0; q < 32; ++q) t += part[q * 32 + threadIdx.x];
+    for (int q = 0; q < kCG; ++q) t += part[q * 32 + threadIdx.x];
     out[threadIdx.x] = t;
   }
   __syncthreads();
@@ -90,7 +91,7 @@ k_cluster_level(int level, int depth, int N, int d, int iters, const T* __restri
                 double* __restrict__ centre, double* __restrict__ cov, const RunState* __restrict__ st) {
   if (st->done) return;
   const int node = (1 << level) - 1 + blockIdx.x;
-  __shared__ int wave_tot[16];
+  __shared__ int wave_tot[kCT / 64];
   __shared__ int s_total;
   __shared__ double part[1024];
   __shared__ int ipart[1024];
@@ -119,35 +120,48 @@ k_cluster_level(int level, int depth, int N, int d, int iters, const T* __restri
   __syncthreads();
   double* cen = centre + static_cast<long>(node) * kMaxD;
   if (threadIdx.x < 32) cen[threadIdx.x] = mu[threadIdx.x];
-  // ---- unbiased covariance (lower triangle, mirrored)
+  // ---- unbiased covariance (lower triangle, mirrored): G point groups per
+  // entry when the entries leave threads idle, else entries strided over threads
   if (cnt >= 2) {
     const int E = d * (d + 1) / 2;
-    const int G = kCT / E;
-    const int e = threadIdx.x % E, g = threadIdx.x / E;
-    int ii = 0, jj = 0;
-    {
-      int rem = e;
-      while (rem > ii) { rem -= ii + 1; ++ii; }
-      jj = rem;
-    }
-    double s = 0.0;
-    if (g < G) {
-      for (int r = g; r < cnt; r += G) {
-        const T* x = u + static_cast<long>(mem[r]) * d;
-        s += (static_cast<double>(x[ii]) - mu[ii]) * (static_cast<double>(x[jj]) - mu[jj]);
+    const int G = E >= kCT ? 1 : kCT / E;
+    for (int e0 = 0; e0 < E; e0 += kCT) {
+      const int slot = threadIdx.x;
+      const int e = (G > 1) ? slot % E : e0 + slot;
+      const int g = (G > 1) ? slot / E : 0;
+      double s = 0.0;
+      int ii = 0, jj = 0;
+      if (e < E && g < G) {
+        int rem = e;
+        while (rem > ii) { rem -= ii + 1; ++ii; }
+        jj = rem;
+        for (int r = g; r < cnt; r += G) {
+          const T* x = u + static_cast<long>(mem[r]) * d;
+          s += (static_cast<double>(x[ii]) - mu[ii]) * (static_cast<double>(x[jj]) - mu[jj]);
+        }
       }
+      part[threadIdx.x] = s;
+      __syncthreads();
+      if (G > 1) {
+        if (threadIdx.x < E) {
+          double t = 0.0;
+          for (int q = 0; q < G; ++q) t += part[q * E + threadIdx.x];
+          t /= static_cast<double>(cnt - 1);
+          int i2 = 0, rem = threadIdx.x;
+          while (rem > i2) { rem -= i2 + 1; ++i2; }
+          double* C = cov + static_cast<long>(node) * kMaxD * kMaxD;
+          C[i2 * kMaxD + rem] = t;
+          C[rem * kMaxD + i2] = t;
+        }
+      } else if (e < E) {
+        const double t = s / static_cast<double>(cnt - 1);
+        double* C = cov + static_cast<long>(node) * kMaxD * kMaxD;
+        C[ii * kMaxD + jj] = t;
+        C[jj * kMaxD + ii] = t;
+      }
+      __syncthreads();
+      if (G > 1) break;
     }
-    part[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x < E) {
-      double t = 0.0;
-      for (int q = 0; q < G; ++q) t += part[q * E + threadIdx.x];
-      t /= static_cast<double>(cnt - 1);
-      double* C = cov + static_cast<long>(node) * kMaxD * kMaxD;
-      C[ii * kMaxD + jj] = t;
-      C[jj * kMaxD + ii] = t;
-    }
-    __syncthreads();
   }
   if (level >= depth || cnt < 2) return;
   // ---- 2-means: deterministic farthest-point start, then Lloyd; the side of
@@ -180,24 +194,26 @@ k_cluster_level(int level, int depth, int N, int d, int iters, const T* __restri
   __syncthreads();
   for (int itn = 0; itn < iters; ++itn) {
     // centres of the two sides
-    for (int sd = 0; sd < 2; ++sd) {
+    {
+      // both sides' coordinate sums in one pass
       const int i = threadIdx.x & 31, g = threadIdx.x >> 5;
-      double s = 0.0;
-      int n = 0;
-      for (int r = g; r < cnt; r += 32) {
+      double s0 = 0.0, s1 = 0.0;
+      int n0 = 0, n1 = 0;
+      for (int r = g; r < cnt; r += kCG) {
         const int k = mem[r];
-        if (nodeof[k] != c1 + sd) continue;
-        if (i < d) s += static_cast<double>(u[static_cast<long>(k) * d + i]);
-        ++n;
+        const double x = (i < d) ? static_cast<double>(u[static_cast<long>(k) * d + i]) : 0.0;
+        if (nodeof[k] == c1) { s0 += x; ++n0; } else { s1 += x; ++n1; }
       }
-      part[g * 32 + i] = s;
-      if (i == 0) ipart[g] = n;
+      part[g * 32 + i] = s0;
+      part[kCG * 32 + g * 32 + i] = s1;
+      if (i == 0) { ipart[g] = n0; ipart[kCG + g] = n1; }
       __syncthreads();
-      if (threadIdx.x < 32) {
+      if (threadIdx.x < 64) {
+        const int sd = threadIdx.x >> 5, ci = threadIdx.x & 31;
         double t = 0.0;
         int nt = 0;
-        for (int q = 0; q < 32; ++q) { t += part[q * 32 + threadIdx.x]; nt += ipart[q]; }
-        if (nt > 0 && threadIdx.x < d) (sd == 0 ? ca : cb)[threadIdx.x] = t / static_cast<double>(nt);
+        for (int q = 0; q < kCG; ++q) { t += part[sd * kCG * 32 + q * 32 + ci]; nt += ipart[sd * kCG + q]; }
+        if (nt > 0 && ci < d) (sd == 0 ? ca : cb)[ci] = t / static_cast<double>(nt);
       }
       __syncthreads();
     }
@@ -218,7 +234,9 @@ k_cluster_level(int level, int depth, int N, int d, int iters, const T* __restri
   }
 }
 
-// Eigen-clip + Cholesky of every node's covariance; one wave per node.
+// Eigen-clip + Cholesky of every node's covariance; one wave per node.  The
+// eigen decomposition only decides whether (and how) the spectrum is clipped:
+// an unclipped covariance is factorised as it is.
 __global__ void __launch_bounds__(64)
 k_cluster_regularise(int d, double eps, const int* __restrict__ count, const double* __restrict__ cov,
                      double* __restrict__ chol, float* __restrict__ chol_f, double* __restrict__ logV,
@@ -249,42 +267,73 @@ k_cluster_regularise(int d, double eps, const int* __restrict__ count, const dou
     L[q] = 0.0;
   }
   __syncthreads();
-  // ---- cyclic Jacobi (Golub & Van Loan, Sec. 8.5)
+  // ---- parallel-order Jacobi (Golub & Van Loan, Sec. 8.5): each round of a
+  // sweep applies d/2 disjoint rotations at once (round-robin pairing), so a
+  // sweep costs d-1 rounds; converged when the off-diagonal mass is below
+  // 1e-30 of the squared Frobenius norm.
+  __shared__ double rc[kMaxD / 2 + 1], rs[kMaxD / 2 + 1];
+  __shared__ int rp[kMaxD / 2 + 1], rq[kMaxD / 2 + 1];
+  const int P = (d + 1) & ~1;          // players, one dummy when d is odd
+  const int npair = P / 2;
   double frob = 0.0;
-  for (int i = 0; i < d; ++i)
-    for (int jj = 0; jj < d; ++jj) frob += a[i * kMaxD + jj] * a[i * kMaxD + jj];
-  for (int sweep = 0; sweep < 60; ++sweep) {
+  if (lane < d)
+    for (int jj = 0; jj < d; ++jj) frob += a[lane * kMaxD + jj] * a[lane * kMaxD + jj];
+  for (int off = 32; off > 0; off >>= 1) frob += __shfl_xor(frob, off);
+  for (int sweep = 0; sweep < 60 && d > 1; ++sweep) {
     double off = 0.0;
-    for (int pp = 0; pp < d; ++pp)
-      for (int qq = 0; qq < d; ++qq)
-        if (pp != qq) off += a[pp * kMaxD + qq] * a[pp * kMaxD + qq];
+    if (lane < d)
+      for (int jj = 0; jj < d; ++jj)
+        if (jj != lane) off += a[lane * kMaxD + jj] * a[lane * kMaxD + jj];
+    for (int sh = 32; sh > 0; sh >>= 1) off += __shfl_xor(off, sh);
     if (off <= 1e-30 * frob || off == 0.0) break;
-    for (int pp = 0; pp < d - 1; ++pp) {
-      for (int qq = pp + 1; qq < d; ++qq) {
-        const double apq = a[pp * kMaxD + qq];
-        if (apq == 0.0) continue;
-        const double app = a[pp * kMaxD + pp], aqq = a[qq * kMaxD + qq];
-        const double tau = (aqq - app) / (2.0 * apq);
-        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-        const double c = 1.0 / sqrt(1.0 + t * t);
-        const double s = t * c;
-        __syncthreads();
-        if (lane < d) {
-          const double akp = a[lane * kMaxD + pp], akq = a[lane * kMaxD + qq];
-          a[lane * kMaxD + pp] = c * akp - s * akq;
-          a[lane * kMaxD + qq] = s * akp + c * akq;
+    for (int r = 0; r < P - 1; ++r) {
+      if (lane < npair) {
+        // circle method: player 0 fixed, players 1..P-1 rotate by r
+        const int ia = lane, ib = P - 1 - lane;
+        const int pa = ia == 0 ? 0 : 1 + (ia - 1 + r) % (P - 1);
+        const int pb = 1 + (ib - 1 + r) % (P - 1);
+        int pp = pa < pb ? pa : pb, qq = pa < pb ? pb : pa;
+        double c = 1.0, sn = 0.0;
+        if (qq < d) {
+          const double apq = a[pp * kMaxD + qq];
+          if (apq != 0.0) {
+            const double app = a[pp * kMaxD + pp], aqq = a[qq * kMaxD + qq];
+            const double tau = (aqq - app) / (2.0 * apq);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sn = t * c;
+          }
+        } else {
+          pp = qq = -1;
         }
-        __syncthreads();
-        if (lane < d) {
-          const double apk = a[pp * kMaxD + lane], aqk = a[qq * kMaxD + lane];
-          a[pp * kMaxD + lane] = c * apk - s * aqk;
-          a[qq * kMaxD + lane] = s * apk + c * aqk;
-          const double qkp = Q[lane * kMaxD + pp], qkq = Q[lane * kMaxD + qq];
-          Q[lane * kMaxD + pp] = c * qkp - s * qkq;
-          Q[lane * kMaxD + qq] = s * qkp + c * qkq;
-        }
-        __syncthreads();
+        rc[lane] = c; rs[lane] = sn; rp[lane] = pp; rq[lane] = qq;
       }
+      __syncthreads();
+      // A <- A J: every row (lane) rotates its columns p, q of each pair
+      if (lane < d)
+        for (int k = 0; k < npair; ++k) {
+          const int pp = rp[k], qq = rq[k];
+          if (pp < 0 || rs[k] == 0.0) continue;
+          const double c = rc[k], sn = rs[k];
+          const double akp = a[lane * kMaxD + pp], akq = a[lane * kMaxD + qq];
+          a[lane * kMaxD + pp] = c * akp - sn * akq;
+          a[lane * kMaxD + qq] = sn * akp + c * akq;
+        }
+      __syncthreads();
+      // A <- J^T A (rows p, q), Q <- Q J (columns p, q); lane = column / row index
+      if (lane < d)
+        for (int k = 0; k < npair; ++k) {
+          const int pp = rp[k], qq = rq[k];
+          if (pp < 0 || rs[k] == 0.0) continue;
+          const double c = rc[k], sn = rs[k];
+          const double apk = a[pp * kMaxD + lane], aqk = a[qq * kMaxD + lane];
+          a[pp * kMaxD + lane] = c * apk - sn * aqk;
+          a[qq * kMaxD + lane] = sn * apk + c * aqk;
+          const double qkp = Q[lane * kMaxD + pp], qkq = Q[lane * kMaxD + qq];
+          Q[lane * kMaxD + pp] = c * qkp - sn * qkq;
+          Q[lane * kMaxD + qq] = sn * qkp + c * qkq;
+        }
+      __syncthreads();
     }
   }
   if (lane < d) lam[lane] = a[lane * kMaxD + lane];

@@ -219,9 +219,8 @@ k_correct(int m, int corr, int K, int TH, int N, int d, int nodes, double stop_f
     const int slot = order[S.list[r]];
     const int pos = S.rank[r];
     const T* x = src_point(S.code[pos], S.hslot[pos]);
-    T xv[kMaxD];
+    T* xv = u + static_cast<long>(slot) * d;
     for (int i = 0; i < d; ++i) xv[i] = x[i];
-    for (int i = 0; i < d; ++i) u[static_cast<long>(slot) * d + i] = xv[i];
     logL[slot] = S.logL[pos];
     int best = -1;
     double bd = INFINITY;

@@ -100,15 +100,14 @@ __global__ void k_init_points(int N, int d, uint64_t seed, LikDev lik, T* __rest
                               double* __restrict__ logL, RunState* __restrict__ st) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
-  T y[kMaxD];
+  T* y = u + static_cast<long>(k) * d;
   for (int p = 0; 2 * p < d; ++p) {
     const Draw2 w = uniform2(seed, static_cast<uint32_t>(p), static_cast<uint32_t>(k), 0u,
                              kStreamInit << 24);
     y[2 * p] = static_cast<T>(w.a);
     if (2 * p + 1 < d) y[2 * p + 1] = static_cast<T>(w.b);
   }
-  for (int i = 0; i < d; ++i) u[static_cast<long>(k) * d + i] = y[i];
-  double v = in_box(y, d) ? LikAt<LT>::eval(lik, y) : -INFINITY;
+  double v = in_box(y, d) ? LikAt<LT>::eval(lik, PtAt<T>{y}) : -INFINITY;
   if (isnan(v)) atomicAdd(&st->nan_logL, 1ull);
   logL[k] = clean_logL(v);
 }
@@ -136,14 +135,21 @@ hipError_t launch_init_points(const Shape& sh, const DevBufs& b, const LikDev& l
 
 // Likelihood of arbitrary unit-cube points, rounded to the state precision
 // exactly as the sampler stores them.
+template <typename T>
+struct CvtAt {
+  const double* p;
+  __device__ T operator()(int i) const { return static_cast<T>(p[i]); }
+};
+
 template <typename T, typename LT>
 __global__ void k_loglike_points(int d, LikDev lik, const double* __restrict__ u, long n,
                                  double* __restrict__ out) {
   const long k = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  T y[kMaxD];
-  for (int i = 0; i < d; ++i) y[i] = static_cast<T>(u[k * d + i]);
-  out[k] = in_box(y, d) ? clean_logL(LikAt<LT>::eval(lik, y)) : -INFINITY;
+  const CvtAt<T> y{u + k * d};
+  bool ok = true;
+  for (int i = 0; i < d; ++i) ok = ok && (y(i) >= T(0) && y(i) <= T(1));
+  out[k] = ok ? clean_logL(LikAt<LT>::eval(lik, y)) : -INFINITY;
 }
 
 hipError_t launch_loglike_points(const Shape& sh, const LikDev& lik, const double* u, long n,

@@ -13,7 +13,10 @@
 //    first one with L > L_W[j].
 // Every draw is addressed by its counter (chain, step, iteration, slot), so
 // the result is the same as the one-proposal-at-a-time algorithm: the extra
-// speculative evaluations are simply not counted as likelihood calls.
+// speculative evaluations are simply not counted as likelihood calls.  All
+// draws of an iteration are generated in one parallel pass at its start
+// (lanes 0-15 direction pairs, lane 16 the bracket offset, lanes 32-63 the
+// first 32 shrink uniforms).
 //
 // The last iteration's shrink proposals (up to T-1 of them) and the chain's
 // final point (slot T-1) are written out as the history of Algorithm 2.
@@ -22,6 +25,7 @@
 namespace ns {
 
 constexpr int kShrinkSpec = 16;
+constexpr int kShrinkPre = 32;  // shrink uniforms drawn in the per-iteration pass
 
 template <typename T, typename LT>
 __global__ void __launch_bounds__(64)
@@ -41,7 +45,8 @@ k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
   __shared__ T vs[kMaxD];
   __shared__ T zs[kMaxD];
   __shared__ T Ls[kMaxD * kMaxD];
-  __shared__ T Us[kShrinkSpec];
+  __shared__ T Us[kShrinkPre + kShrinkSpec];
+  __shared__ T s_a0;
   __shared__ T br[2];
 
   const int s = seeds[j];
@@ -59,17 +64,26 @@ k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
   for (int it = 0; it < n_iter; ++it) {
     const uint32_t c3 = (kStreamSlice << 24) | static_cast<uint32_t>(it);
     const bool last = (it == n_iter - 1);
-    // ---- isotropic direction, whitened by the cluster's Cholesky factor
-    if (2 * lane < d) {
-      const Draw2 dr = uniform2(p.seed, kSlotDir0 + lane, static_cast<uint32_t>(j), step, c3);
-      const T r = DirMath<T>::r_of(static_cast<T>(dr.a));
-      const T ang = static_cast<T>(6.283185307179586) * static_cast<T>(dr.b);
-      T sn, cs;
-      DirMath<T>::sc(ang, &sn, &cs);
-      zs[2 * lane] = r * cs;
-      if (2 * lane + 1 < d) zs[2 * lane + 1] = r * sn;
+    // ---- all draws of the iteration in one pass
+    if (lane < 16) {
+      if (2 * lane < d) {
+        const Draw2 dr = uniform2(p.seed, kSlotDir0 + lane, static_cast<uint32_t>(j), step, c3);
+        const T r = DirMath<T>::r_of(static_cast<T>(dr.a));
+        const T ang = static_cast<T>(6.283185307179586) * static_cast<T>(dr.b);
+        T sn, cs;
+        DirMath<T>::sc(ang, &sn, &cs);
+        zs[2 * lane] = r * cs;
+        if (2 * lane + 1 < d) zs[2 * lane + 1] = r * sn;
+      }
+    } else if (lane == 16) {
+      const Draw2 d0 = uniform2(p.seed, kSlotStepout, static_cast<uint32_t>(j), step, c3);
+      s_a0 = -w * static_cast<T>(d0.a);
+    } else if (lane >= 32 && lane - 32 < p.max_shrink) {
+      const Draw2 du = uniform2(p.seed, kSlotShrink0 + (lane - 32), static_cast<uint32_t>(j), step, c3);
+      Us[lane - 32] = static_cast<T>(du.a);
     }
     __syncthreads();
+    // ---- isotropic direction, whitened by the cluster's Cholesky factor
     T nrm = T(0);
     for (int i = 0; i < d; ++i) nrm += zs[i] * zs[i];
     nrm = DirMath<T>::sq(nrm);
@@ -81,8 +95,7 @@ k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
     __syncthreads();
 
     // ---- stepping out against the batch-worst threshold L_W[0]
-    const Draw2 d0 = uniform2(p.seed, kSlotStepout, static_cast<uint32_t>(j), step, c3);
-    const T a0 = -w * static_cast<T>(d0.a);
+    const T a0 = s_a0;
     const T b0 = a0 + w;
     int ka = -1, kb = -1;
     for (int base = 0; ka < 0 || kb < 0; base += 32) {
@@ -92,10 +105,10 @@ k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
       bool pass = false, oob = false;
       if (active) {
         const T off = left ? a0 - static_cast<T>(k) * w : b0 + static_cast<T>(k) * w;
-        T y[kMaxD];
-        for (int i = 0; i < d; ++i) y[i] = xs[i] + off * vs[i];
-        if (in_box(y, d)) pass = clean_logL(LikAt<LT>::eval(lik, y)) > tau_e;
-        else oob = true;
+        if (line_in_box(xs, vs, off, d))
+          pass = clean_logL(LikAt<LT>::eval(lik, LineAt<T>{xs, vs, off})) > tau_e;
+        else
+          oob = true;
       }
       const uint64_t mp = __ballot(pass);
       const uint64_t mo = __ballot(oob);
@@ -125,23 +138,29 @@ k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
     bool accepted = false;
     for (int s0 = 0; s0 < p.max_shrink && !accepted; s0 += kShrinkSpec) {
       const int S = min(kShrinkSpec, p.max_shrink - s0);
-      if (lane < S) {
-        const Draw2 du = uniform2(p.seed, kSlotShrink0 + s0 + lane, static_cast<uint32_t>(j), step, c3);
-        Us[lane] = static_cast<T>(du.a);
+      const T* U = Us + s0;
+      if (s0 + kShrinkSpec > kShrinkPre) {
+        // beyond the pre-drawn uniforms: draw this round's on demand
+        if (lane < S) {
+          const Draw2 du = uniform2(p.seed, kSlotShrink0 + s0 + lane, static_cast<uint32_t>(j), step, c3);
+          Us[kShrinkPre + lane] = static_cast<T>(du.a);
+        }
+        __syncthreads();
+        U = Us + kShrinkPre;
       }
-      __syncthreads();
-      T y[kMaxD];
       bool pass = false, inb = false;
       T aa = a, bb = b, t = T(0);
       double l = -INFINITY;
       if (lane < S) {
-        for (int q = 0; q <= lane; ++q) {
-          t = aa + Us[q] * (bb - aa);
-          if (t < T(0)) aa = t; else bb = t;
+#pragma unroll
+        for (int q = 0; q < kShrinkSpec; ++q) {
+          if (q <= lane) {
+            t = aa + U[q] * (bb - aa);
+            if (t < T(0)) aa = t; else bb = t;
+          }
         }
-        for (int i = 0; i < d; ++i) y[i] = xs[i] + t * vs[i];
-        inb = in_box(y, d);
-        if (inb) l = clean_logL(LikAt<LT>::eval(lik, y));
+        inb = line_in_box(xs, vs, t, d);
+        if (inb) l = clean_logL(LikAt<LT>::eval(lik, LineAt<T>{xs, vs, t}));
         pass = l > tau_j;
       }
       const uint64_t mp = __ballot(pass);
@@ -154,14 +173,15 @@ k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
         const int slot = s0 + lane;
         hist_logL[static_cast<long>(slot) * m + j] = l;
         T* hu = hist_u + (static_cast<long>(j) * TH + slot) * d;
-        for (int i = 0; i < d; ++i) hu[i] = y[i];
+        for (int i = 0; i < d; ++i) hu[i] = xs[i] + t * vs[i];
       }
       if (last) hn = min(s0 + upto + 1, TH - 1);
       if (mp) {
         accepted = true;
         lx = __shfl(l, upto);
-        if (lane == upto)
-          for (int i = 0; i < d; ++i) xs[i] = y[i];
+        const T tacc = __shfl(t, upto);
+        __syncthreads();
+        if (lane < d) xs[lane] = xs[lane] + tacc * vs[lane];
       } else if (lane == S - 1) {
         br[0] = aa;
         br[1] = bb;

@@ -194,16 +194,15 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
     __syncthreads();
   }
   bool has = false, inb = false;
-  T y[kMaxD];
+  T toff = T(0);   // proposal = x + toff v
   if (S.phase == kPhaseStepout) {
     const int E = p.so_spec;
     const bool left = lane < E;
     const int k = S.base + (left ? lane : lane - E);
     has = lane < 2 * E && (left ? S.ka < 0 : S.kb < 0) && k < p.max_stepout;
     if (has) {
-      const T off = left ? S.a0 - static_cast<T>(k) * w : S.b0 + static_cast<T>(k) * w;
-      for (int i = 0; i < d; ++i) y[i] = S.x[i] + off * S.v[i];
-      inb = in_box(y, d);
+      toff = left ? S.a0 - static_cast<T>(k) * w : S.b0 + static_cast<T>(k) * w;
+      inb = line_in_box(S.x, S.v, toff, d);
     }
   } else if (S.phase == kPhaseShrink) {
     const uint32_t c3 = (kStreamSlice << 24) | static_cast<uint32_t>(S.it);
@@ -219,9 +218,9 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
         t = aa + Us[q] * (bb - aa);
         if (t < T(0)) aa = t; else bb = t;
       }
-      for (int i = 0; i < d; ++i) y[i] = S.x[i] + t * S.v[i];
+      toff = t;
       has = true;
-      inb = in_box(y, d);
+      inb = line_in_box(S.x, S.v, t, d);
       if (lane == Sn - 1) { S.br_a = aa; S.br_b = bb; }
     }
   }
@@ -230,8 +229,9 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
     flag[r] = inb ? 1 : 0;
     if (has)
       for (int i = 0; i < d; ++i) {
-        pts[r * d + i] = y[i];
-        xin[r * d + i] = p.lo_f[i] + p.span_f[i] * static_cast<float>(y[i]);
+        const T yi = S.x[i] + toff * S.v[i];
+        pts[r * d + i] = yi;
+        xin[r * d + i] = p.lo_f[i] + p.span_f[i] * static_cast<float>(yi);
       }
   }
   __syncthreads();
@@ -277,13 +277,12 @@ __global__ void k_rows_from_points(long n, int d, const double* __restrict__ u, 
                                    T* __restrict__ pts, float* __restrict__ xin, int* __restrict__ flag) {
   const long k = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  T y[kMaxD];
-  for (int i = 0; i < d; ++i) y[i] = static_cast<T>(u[k * d + i]);
-  flag[k] = in_box(y, d) ? 1 : 0;
   for (int i = 0; i < d; ++i) {
-    pts[k * d + i] = y[i];
-    xin[k * d + i] = p.lo_f[i] + p.span_f[i] * static_cast<float>(y[i]);
+    const T yi = static_cast<T>(u[k * d + i]);
+    pts[k * d + i] = yi;
+    xin[k * d + i] = p.lo_f[i] + p.span_f[i] * static_cast<float>(yi);
   }
+  flag[k] = in_box(pts + k * d, d) ? 1 : 0;
 }
 
 hipError_t launch_rows_from_points(long n, int d, const double* u, const RoundsParams& p, int state_f32,
@@ -306,14 +305,13 @@ __global__ void k_init_rows(int N, int d, uint64_t seed, RoundsParams p, T* __re
                             T* __restrict__ pts, float* __restrict__ xin, int* __restrict__ flag) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
-  T y[kMaxD];
+  T* y = u + static_cast<long>(k) * d;
   for (int q = 0; 2 * q < d; ++q) {
     const Draw2 w = uniform2(seed, static_cast<uint32_t>(q), static_cast<uint32_t>(k), 0u, kStreamInit << 24);
     y[2 * q] = static_cast<T>(w.a);
     if (2 * q + 1 < d) y[2 * q + 1] = static_cast<T>(w.b);
   }
   for (int i = 0; i < d; ++i) {
-    u[static_cast<long>(k) * d + i] = y[i];
     pts[static_cast<long>(k) * d + i] = y[i];
     xin[static_cast<long>(k) * d + i] = p.lo_f[i] + p.span_f[i] * static_cast<float>(y[i]);
   }
@@ -340,9 +338,7 @@ __global__ void k_rows_loglike(long n, LikDev lik, const T* __restrict__ pts, co
   const long k = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= n) return;
   if (!flag[k]) { out[k] = -INFINITY; return; }
-  T y[kMaxD];
-  for (int i = 0; i < lik.d; ++i) y[i] = pts[k * lik.d + i];
-  out[k] = clean_logL(LikAt<LT>::eval(lik, y));
+  out[k] = clean_logL(LikAt<LT>::eval(lik, PtAt<T>{pts + k * lik.d}));
 }
 
 hipError_t launch_rows_loglike(const Shape& sh, const LikDev& lik, long n, const void* pts,

@@ -71,23 +71,23 @@ struct LikDev {
   const float* ivar_f;
 };
 
-// Analytic families, in the likelihood precision LT (double or float).  `y`
-// holds unit-cube coordinates already known to be inside the box.
+// Analytic families, in the likelihood precision LT (double or float).  The
+// point is read through an accessor y(i) returning unit-cube coordinate i
+// (already known to lie in the box); theta_i = lo_i + span_i y_i is formed on
+// the fly so no per-lane array is materialised.
 template <typename LT>
 struct LikAt;
 
 template <>
 struct LikAt<double> {
-  template <typename T>
-  __device__ static double eval(const LikDev& P, const T* y) {
-    double th[kMaxD];
+  template <typename Y>
+  __device__ static double eval(const LikDev& P, Y y) {
     const int d = P.d;
-    for (int i = 0; i < d; ++i) th[i] = P.lo[i] + P.span[i] * static_cast<double>(y[i]);
     if (P.kind == kMixture) {
       if (P.n_comp == 1) {
         double q = 0.0;
         for (int i = 0; i < d; ++i) {
-          const double r = th[i] - P.mu[i];
+          const double r = (P.lo[i] + P.span[i] * static_cast<double>(y(i))) - P.mu[i];
           q += r * r * P.ivar[i];
         }
         return P.logw[0] - 0.5 * q;
@@ -96,7 +96,7 @@ struct LikAt<double> {
       for (int k = 0; k < P.n_comp; ++k) {
         double q = 0.0;
         for (int i = 0; i < d; ++i) {
-          const double r = th[i] - P.mu[k * d + i];
+          const double r = (P.lo[i] + P.span[i] * static_cast<double>(y(i))) - P.mu[k * d + i];
           q += r * r * P.ivar[k * d + i];
         }
         const double e = P.logw[k] - 0.5 * q;
@@ -107,7 +107,7 @@ struct LikAt<double> {
       for (int k = 0; k < P.n_comp; ++k) {
         double q = 0.0;
         for (int i = 0; i < d; ++i) {
-          const double r = th[i] - P.mu[k * d + i];
+          const double r = (P.lo[i] + P.span[i] * static_cast<double>(y(i))) - P.mu[k * d + i];
           q += r * r * P.ivar[k * d + i];
         }
         s += exp((P.logw[k] - 0.5 * q) - best);
@@ -116,16 +116,21 @@ struct LikAt<double> {
     }
     if (P.kind == kRosenbrock) {
       double s = 0.0;
+      double prev = P.lo[0] + P.span[0] * static_cast<double>(y(0));
       for (int i = 0; i + 1 < d; ++i) {
-        const double t = th[i + 1] - th[i] * th[i];
-        const double r = P.ros_a - th[i];
+        const double next = P.lo[i + 1] + P.span[i + 1] * static_cast<double>(y(i + 1));
+        const double t = next - prev * prev;
+        const double r = P.ros_a - prev;
         s += P.ros_b * t * t + r * r;
+        prev = next;
       }
       return -s;
     }
-    // shell
     double s = 0.0;
-    for (int i = 0; i < d; ++i) s += th[i] * th[i];
+    for (int i = 0; i < d; ++i) {
+      const double th = P.lo[i] + P.span[i] * static_cast<double>(y(i));
+      s += th * th;
+    }
     const double r = (sqrt(s) - P.shell_r0) / P.shell_w;
     return -0.5 * r * r;
   }
@@ -133,16 +138,14 @@ struct LikAt<double> {
 
 template <>
 struct LikAt<float> {
-  template <typename T>
-  __device__ static double eval(const LikDev& P, const T* y) {
-    float th[kMaxD];
+  template <typename Y>
+  __device__ static double eval(const LikDev& P, Y y) {
     const int d = P.d;
-    for (int i = 0; i < d; ++i) th[i] = P.lo_f[i] + P.span_f[i] * static_cast<float>(y[i]);
     if (P.kind == kMixture) {
       if (P.n_comp == 1) {
         float q = 0.0f;
         for (int i = 0; i < d; ++i) {
-          const float r = th[i] - P.mu_f[i];
+          const float r = (P.lo_f[i] + P.span_f[i] * static_cast<float>(y(i))) - P.mu_f[i];
           q += r * r * P.ivar_f[i];
         }
         return static_cast<double>(P.logw_f[0] - 0.5f * q);
@@ -151,7 +154,7 @@ struct LikAt<float> {
       for (int k = 0; k < P.n_comp; ++k) {
         float q = 0.0f;
         for (int i = 0; i < d; ++i) {
-          const float r = th[i] - P.mu_f[k * d + i];
+          const float r = (P.lo_f[i] + P.span_f[i] * static_cast<float>(y(i))) - P.mu_f[k * d + i];
           q += r * r * P.ivar_f[k * d + i];
         }
         const float e = P.logw_f[k] - 0.5f * q;
@@ -162,7 +165,7 @@ struct LikAt<float> {
       for (int k = 0; k < P.n_comp; ++k) {
         float q = 0.0f;
         for (int i = 0; i < d; ++i) {
-          const float r = th[i] - P.mu_f[k * d + i];
+          const float r = (P.lo_f[i] + P.span_f[i] * static_cast<float>(y(i))) - P.mu_f[k * d + i];
           q += r * r * P.ivar_f[k * d + i];
         }
         s += expf((P.logw_f[k] - 0.5f * q) - best);
@@ -172,15 +175,21 @@ struct LikAt<float> {
     if (P.kind == kRosenbrock) {
       float s = 0.0f;
       const float a = static_cast<float>(P.ros_a), b = static_cast<float>(P.ros_b);
+      float prev = P.lo_f[0] + P.span_f[0] * static_cast<float>(y(0));
       for (int i = 0; i + 1 < d; ++i) {
-        const float t = th[i + 1] - th[i] * th[i];
-        const float r = a - th[i];
+        const float next = P.lo_f[i + 1] + P.span_f[i + 1] * static_cast<float>(y(i + 1));
+        const float t = next - prev * prev;
+        const float r = a - prev;
         s += b * t * t + r * r;
+        prev = next;
       }
       return static_cast<double>(-s);
     }
     float s = 0.0f;
-    for (int i = 0; i < d; ++i) s += th[i] * th[i];
+    for (int i = 0; i < d; ++i) {
+      const float th = P.lo_f[i] + P.span_f[i] * static_cast<float>(y(i));
+      s += th * th;
+    }
     const float r = (sqrtf(s) - static_cast<float>(P.shell_r0)) / static_cast<float>(P.shell_w);
     return static_cast<double>(-0.5f * r * r);
   }
@@ -190,6 +199,29 @@ template <typename T>
 __device__ __forceinline__ bool in_box(const T* y, int d) {
   bool ok = true;
   for (int i = 0; i < d; ++i) ok = ok && (y[i] >= T(0) && y[i] <= T(1));
+  return ok;
+}
+
+// Accessors for LikAt::eval: a stored point, or x + t v formed on the fly.
+template <typename T>
+struct PtAt {
+  const T* p;
+  __device__ T operator()(int i) const { return p[i]; }
+};
+template <typename T>
+struct LineAt {
+  const T* x;
+  const T* v;
+  T t;
+  __device__ T operator()(int i) const { return x[i] + t * v[i]; }
+};
+template <typename T>
+__device__ __forceinline__ bool line_in_box(const T* x, const T* v, T t, int d) {
+  bool ok = true;
+  for (int i = 0; i < d; ++i) {
+    const T yi = x[i] + t * v[i];
+    ok = ok && (yi >= T(0) && yi <= T(1));
+  }
   return ok;
 }
 

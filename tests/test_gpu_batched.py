@@ -95,7 +95,7 @@ def test_dense_layer_bounds(prec, M, K, N):
     assert np.all(np.abs(Y - ref) <= bound + 1e-30)
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "bf16"])
 def test_network_backward_against_oracle(prec):
     rng = np.random.default_rng(7)
     widths = [27, 64, 48, 1]
@@ -121,13 +121,17 @@ def test_network_backward_against_oracle(prec):
     work = torch.zeros(2 * B * max(widths), dtype=torch.float32, device=DEV)
     native.ns_mlp_backward(desc, prec, Xd, Zd, Hd, f32(dY), dWd, dbd, dXd, work)
     torch.cuda.synchronize()
-    assert np.allclose(Yd.cpu().numpy(), Yr, rtol=1e-4, atol=1e-5)
+    # FP32: accumulation-order bound; bfloat16 operands (the gradients in the
+    # backward products are rounded once even in the split mode): 2^-7 relative
+    tol = 1e-4 if prec == "f32" else 2.0 ** -7
+    ytol = 1e-4 if prec != "bf16" else 2.0 ** -7
+    assert np.max(np.abs(Yd.cpu().numpy() - Yr)) <= ytol * max(1.0, np.max(np.abs(Yr)))
     for l in range(3):
         g, r = dWd[l].cpu().numpy(), dWr[l]
-        assert np.max(np.abs(g - r)) <= 1e-4 * max(1.0, np.max(np.abs(r))), l
+        assert np.max(np.abs(g - r)) <= tol * max(1.0, np.max(np.abs(r))), l
         g, r = dbd[l].cpu().numpy(), dbr[l]
-        assert np.max(np.abs(g - r)) <= 1e-4 * max(1.0, np.max(np.abs(r))), l
-    assert np.max(np.abs(dXd.cpu().numpy() - dXr)) <= 1e-4 * max(1.0, np.max(np.abs(dXr)))
+        assert np.max(np.abs(g - r)) <= tol * max(1.0, np.max(np.abs(r))), l
+    assert np.max(np.abs(dXd.cpu().numpy() - dXr)) <= tol * max(1.0, np.max(np.abs(dXr)))
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16x3"])
