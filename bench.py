@@ -29,6 +29,11 @@ ROSEN_QUADRATURE_LOGZ = -43.10836   # transfer-matrix quadrature of the 10-d cha
 FP64_PEAK = 78.6e12                 # MI355X FP64 vector FLOP/s
 
 
+EMU_FLOPS = 2 * (27 * 512 + 512 * 512 * 2 + 512 * 1024)   # one emulator evaluation
+BF16_PEAK = 2.5e15                                          # MI355X dense BF16 MFMA FLOP/s
+FP32_PEAK = 157.3e12                                        # MI355X FP32 vector FLOP/s
+
+
 def rosen_flops_per_eval(d):
     # theta = lo + span*u (2d) + 9 terms of 8 flops + proposal x + t v (2d)
     return 2 * d + 8 * (d - 1) + 2 * d
@@ -44,7 +49,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--m", type=int, default=50)
+    ap.add_argument("--m", type=int, default=None)
+    ap.add_argument("--workload", type=int, default=2,
+                    help="2: 10-d Rosenbrock (default); 4: 27-d emulator; 5: emulator + learned screen")
+    ap.add_argument("--prec", default=None, help="emulator layers: bf16x3 (default) or f32")
+    ap.add_argument("--max-steps", type=int, default=0,
+                    help="emulator workloads: stop each run after this many batched steps (timing probe)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -70,8 +80,10 @@ def main():
     from paper_2608_28514_amd import native, workloads
 
     torch.cuda.set_device(0)
+    if args.workload in (4, 5):
+        return bench_emulator(args, np, torch, native, workloads)
     spec = workloads.likelihood(2)
-    N, m, d, depth = 500, args.m, 10, 2
+    N, m, d, depth = 500, args.m or 50, 10, 2
     n_iter = 5 * d
     kw = dict(prec="f64", state="f32", tree_depth=depth)
 
@@ -163,6 +175,82 @@ def main():
     out["pass_2sigma_vs_quadrature"] = \
         f"{sum(abs(r['logZ'] - ROSEN_QUADRATURE_LOGZ) < 2 * r['sigma'] for r in runs)}/{len(runs)}"
     print(json.dumps(out))
+
+
+def bench_emulator(args, np, torch, native, workloads):
+    """27-d random-MLP emulator (workload 4) or the same with the learned screen
+    and N=4000, m=400 (workload 5).  One step = one complete run; the dominant
+    kernels are the dense layers (MFMA for bf16x3)."""
+    wl = args.workload
+    prec = args.prec or "bf16x3"
+    N, m = (2000, 200) if wl == 4 else (4000, 400)
+    m = args.m or m
+    spec = workloads.likelihood(wl, seed=0)
+    kw = dict(prec=prec, state="f32", tree_depth=1)
+    runs, t_total = [], 0.0
+    kern = {c: [0.0, 0] for c in native.TIMING_CLASSES}
+    for k in range(args.warmup + args.steps):
+        s = native.Sampler(spec, N, seed=(999 + k) if k < args.warmup else k - args.warmup, **kw)
+        if wl == 5:
+            s.enable_surrogate(prec="bf16")
+        timed = k >= args.warmup
+        if timed:
+            native.ns_set_timing(s.ctx, True)
+        native.ns_sync(s.ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if args.max_steps:
+            s.run(m, max_steps=args.max_steps)
+        else:
+            s.run(m)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        print(f"[bench] workload {wl} run {k} ({'timed' if timed else 'warm-up'}): {t1 - t0:.1f} s",
+              file=sys.stderr, flush=True)
+        if not timed:
+            s.close()
+            continue
+        t_total += t1 - t0
+        for c, (ms, n) in native.ns_get_timing(s.ctx).items():
+            kern[c][0] += ms
+            kern[c][1] += n
+        st = s.stats()
+        lz, sig, H = s.logZ()
+        r = {"seed": k - args.warmup, "time_s": t1 - t0, "dead": st["dead"], "steps": st["steps"],
+             "evals": st["evals"] - N, "net_rows": st["net_rows"], "screened": st["screened"],
+             "logZ": lz, "sigma": sig, "H": H}
+        if wl == 5:
+            r["surrogate"] = s.surrogate_stats()
+        runs.append(r)
+        s.close()
+    dead = sum(r["dead"] for r in runs)
+    evals = sum(r["evals"] for r in runs)
+    rows = sum(r["net_rows"] for r in runs)
+    lik_ms = kern["lik"][0]
+    flops = rows * EMU_FLOPS
+    peak = BF16_PEAK if prec.startswith("bf16") else FP32_PEAK
+    achieved = flops / (lik_ms * 1e-3) if lik_ms > 0 else 0.0
+    out = {
+        "metric": "live-point updates/s at |dlogZ|<2sigma vs oracle, 1 GPU",
+        "value": dead / t_total, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t_total / max(args.steps, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16" if prec.startswith("bf16") else "f32", "data": "synthetic",
+        "config": {"workload": f"emulator27d MLP 27-512-512-512-1024 N_live={N} m={m} depth=1 "
+                               f"layers={prec}{' +learned-screen' if wl == 5 else ''}"
+                               f"{f' PARTIAL first {args.max_steps} steps' if args.max_steps else ''}",
+                   "n_live": N, "m": m, "d": 27},
+        "evals_per_s": evals / t_total, "net_rows_per_s": rows / t_total,
+        "kernel_ms": {c: round(v[0], 3) for c, v in kern.items()},
+        "kernel_launches": {c: v[1] for c, v in kern.items()},
+        "roofline": {"kernel": "k_gemm (emulator layers) + k_chi2, batched rounds", "bound": "mfma"
+                     if prec.startswith("bf16") else "alu", "achieved": achieved / 1e12,
+                     "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "note": "useful emulator FLOPs (2,124,800 per row) over the batched-likelihood "
+                             "kernel time; the split activations issue 3x the MFMA work on layers 2-4"},
+        "runs": runs,
+    }
+    print(json.dumps(out, default=float))
 
 
 if __name__ == "__main__":

@@ -20,9 +20,9 @@
  *    during the call and copied; the caller keeps ownership.
  *  - Device pointers (arguments named d_*) must point to device memory of the
  *    current HIP device, sized as stated; the library never frees them.
- *  - All device work of a context runs on one HIP stream (the one given to
- *    ns_init, or an own default-priority stream when NULL).  Only ns_logZ,
- *    ns_sync and the ns_get_* getters synchronise that stream.
+ *  - All device work of a context runs on one HIP stream: the one given to
+ *    ns_init, or the default (null) stream when NULL.  Only ns_logZ, ns_sync
+ *    and the ns_get_* / ns_*stats getters synchronise that stream.
  *  - Points are stored in unit-cube coordinates u in [0,1]^d, theta = lo +
  *    (hi - lo) u.  Arrays of points are row major: point k occupies
  *    [k*d, (k+1)*d).
@@ -132,6 +132,9 @@ typedef struct {
   int64_t nan_logL;        /* likelihood values that were NaN (counted as -inf)         */
   int32_t done;            /* stopping rule reached                                     */
   int32_t n_clusters;      /* clusters of the current tree                              */
+  int64_t screened;        /* proposals the surrogate screened out (not evaluated)      */
+  int64_t net_rows;        /* rows evaluated by the likelihood network, speculative
+                              rows of the batched rounds included                       */
 } ns_stats_t;
 
 /* Defaults listed above. */
@@ -139,7 +142,8 @@ ns_status ns_config_default(ns_config* cfg);
 
 /* Create a sampler: N = n_live initial points drawn uniformly in [lo, hi]
  * (Sec. 1), their likelihoods, and the first cluster tree (Sec. 2.1).
- * lo, hi: host arrays of d doubles.  hip_stream: a hipStream_t or NULL.
+ * lo, hi: host arrays of d doubles.  hip_stream: a hipStream_t, or NULL for
+ * the default (null) stream.
  * On success *out owns all device memory of the context (freed by ns_free). */
 ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n_live,
                   const ns_config* cfg, const ns_likelihood* lik, void* hip_stream);
@@ -274,6 +278,56 @@ ns_status ns_mlp_backward(const ns_mlp_desc* net, ns_prec prec, const float* d_X
                           const float* d_Z, const float* d_H, const float* d_dY,
                           float* const* d_dW, float* const* d_db, float* d_dX, float* d_work,
                           void* hip_stream);
+
+/* ---- learned pre-screen (network likelihoods) -------------------------------
+ * A small surrogate network widths {d, hidden, hidden, 1} with SiLU hidden
+ * layers, trained on the device on the (theta, logL) pairs the sampler itself
+ * evaluates (replay ring), with the kernels of ns_mlp_forward/backward, an MSE
+ * loss and Adam.  Targets t = max(logL, L_W[0] - floor_below) are mapped
+ * linearly from [L_W[0] - floor_below, best live logL] to [-1, 1]; inputs are
+ * standardised with the live set's mean and standard deviation.  Once
+ * min_pairs pairs are stored training starts, and while the last minibatch's
+ * RMS error is below margin/2 nats each round's proposals are scored:
+ * a proposal whose estimate lies below its threshold minus `margin` is taken
+ * as failing without evaluating the true likelihood, except every
+ * audit_period-th such proposal, which is evaluated; if a step's audited
+ * false-screen rate exceeds max_fn_rate the screen pauses for five steps
+ * (plain sampler as fallback).  Accepted points always carry their true
+ * likelihood.  Only for NS_LIK_MLP contexts. */
+typedef struct {
+  int hidden;            /* 256 */
+  int replay_cap;        /* 65536 pairs */
+  int batch;             /* 2048 */
+  int train_every;       /* steps between training calls; 1 */
+  int train_iters;       /* Adam steps per call; 25 */
+  float lr;              /* 1e-3 */
+  double margin;         /* nats; 5 */
+  double floor_below;    /* nats; 40 */
+  int audit_period;      /* 16 */
+  double max_fn_rate;    /* 0.02 */
+  int min_pairs;         /* 16384 */
+  ns_prec prec;          /* NS_FP32 or NS_BF16 layers; NS_BF16 */
+  uint64_t seed;
+} ns_surrogate_config;
+
+typedef struct {
+  int64_t pairs;          /* pairs appended to the replay ring                     */
+  int64_t net_rows;       /* true-likelihood network rows                          */
+  int64_t screened;       /* proposals the surrogate placed below threshold-margin */
+  int64_t audited;
+  int64_t false_screens;
+  int64_t train_calls;
+  int32_t screening;      /* screen active now                                      */
+  int32_t disabled;       /* paused by the audit                                    */
+  double last_loss;       /* MSE of the last minibatch (normalised units)           */
+} ns_surrogate_stats_t;
+
+ns_status ns_surrogate_default(ns_surrogate_config* sc);
+ns_status ns_surrogate_enable(ns_ctx* c, const ns_surrogate_config* sc);
+ns_status ns_surrogate_stats(ns_ctx* c, ns_surrogate_stats_t* s);
+/* logL estimate of n points d_theta (n*d FP32 parameter values, device) into
+ * d_out (n FP32). */
+ns_status ns_surrogate_predict(ns_ctx* c, const float* d_theta, int64_t n, float* d_out);
 
 /* Description of the last error of c (or of the last context-free call when
  * c is NULL); valid until the next call on c. */

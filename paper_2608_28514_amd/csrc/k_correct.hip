@@ -267,10 +267,10 @@ k_correct(int m, int corr, int K, int TH, int N, int d, int nodes, double stop_f
   for (int k = threadIdx.x; k < N; k += blockDim.x) lmax = logL[k] > lmax ? logL[k] : lmax;
   lmax = block_reduce(lmax, S.red, true);
   // ---- counters
-  double ce[4] = {0, 0, 0, 0};
+  double ce[5] = {0, 0, 0, 0, 0};
   for (int j = threadIdx.x; j < m; j += blockDim.x)
-    for (int c = 0; c < 4; ++c) ce[c] += static_cast<double>(chain_stat[4 * j + c]);
-  for (int c = 0; c < 4; ++c) ce[c] = block_reduce(ce[c], S.red, false);
+    for (int c = 0; c < 5; ++c) ce[c] += static_cast<double>(chain_stat[kStatW * j + c]);
+  for (int c = 0; c < 5; ++c) ce[c] = block_reduce(ce[c], S.red, false);
   if (threadIdx.x == 0) {
     double lz = st->logZ, A = st->A;
     if (mx > -INFINITY) {
@@ -283,11 +283,13 @@ k_correct(int m, int corr, int K, int TH, int N, int d, int nodes, double stop_f
     st->logZ = lz;
     st->A = A;
     st->n_dead = base_dead + m;
+    st->lmax = lmax;
     st->step += 1;
     st->evals += static_cast<unsigned long long>(ce[0]);
     st->oob += static_cast<unsigned long long>(ce[1]);
     st->so_caps += static_cast<unsigned long long>(ce[2]);
     st->sh_caps += static_cast<unsigned long long>(ce[3]);
+    st->screened += static_cast<unsigned long long>(ce[4]);
     if (-static_cast<double>(base_dead + m) / Nd + lmax - lz < log(stop_frac)) st->done = 1;
   }
 }

@@ -41,8 +41,11 @@ template <int MODE>
 __global__ void __launch_bounds__(256)
 k_gemm(int M, int N, int K, const float* __restrict__ A, long sar, long sak,
        const float* __restrict__ B, long sbn, long sbk, const float* __restrict__ bias, int act,
-       float* __restrict__ C, long ldc, float* __restrict__ Z, long ldz, const int* __restrict__ gate) {
+       float* __restrict__ C, long ldc, float* __restrict__ Z, long ldz, const int* __restrict__ gate,
+       const int* __restrict__ dM) {
   if (gate && *gate == 0) return;
+  if (dM) M = min(M, *dM);              // row count decided on the device
+  if (static_cast<int>(blockIdx.y) * kTM >= M) return;
   __shared__ float As[kTM * kLdsK];
   __shared__ float Bs[kTN * kLdsK];
   const int tid = threadIdx.x;
@@ -149,18 +152,18 @@ k_gemm(int M, int N, int K, const float* __restrict__ A, long sar, long sak,
 
 hipError_t launch_gemm(int mode, int M, int N, int K, const float* A, long sar, long sak,
                        const float* B, long sbn, long sbk, const float* bias, int act, float* C,
-                       long ldc, float* Z, long ldz, const int* gate, hipStream_t s) {
+                       long ldc, float* Z, long ldz, const int* gate, hipStream_t s, const int* dM) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const dim3 grid((N + kTN - 1) / kTN, (M + kTM - 1) / kTM), block(256);
   if (mode == kF32)
     hipLaunchKernelGGL(k_gemm<kF32>, grid, block, 0, s, M, N, K, A, sar, sak, B, sbn, sbk, bias,
-                       act, C, ldc, Z, ldz, gate);
+                       act, C, ldc, Z, ldz, gate, dM);
   else if (mode == kBF16S)
     hipLaunchKernelGGL(k_gemm<kBF16S>, grid, block, 0, s, M, N, K, A, sar, sak, B, sbn, sbk, bias,
-                       act, C, ldc, Z, ldz, gate);
+                       act, C, ldc, Z, ldz, gate, dM);
   else
     hipLaunchKernelGGL(k_gemm<kBF16>, grid, block, 0, s, M, N, K, A, sar, sak, B, sbn, sbk, bias,
-                       act, C, ldc, Z, ldz, gate);
+                       act, C, ldc, Z, ldz, gate, dM);
   return hipGetLastError();
 }
 
@@ -210,10 +213,10 @@ hipError_t launch_colsum(int M, int N, const float* dZ, float* db, hipStream_t s
 __global__ void __launch_bounds__(64)
 k_chi2(int M, int N, const float* __restrict__ Y, const double* __restrict__ data,
        const double* __restrict__ isig, const int* __restrict__ flag, double* __restrict__ logL,
-       const int* __restrict__ gate) {
+       const int* __restrict__ gate, const int* __restrict__ dM) {
   if (gate && *gate == 0) return;
   const int r = blockIdx.x;
-  if (r >= M) return;
+  if (r >= M || (dM && r >= *dM)) return;
   const int lane = threadIdx.x;
   if (flag && flag[r] == 0) {
     if (lane == 0) logL[r] = -INFINITY;
@@ -232,9 +235,9 @@ k_chi2(int M, int N, const float* __restrict__ Y, const double* __restrict__ dat
 }
 
 hipError_t launch_chi2(int M, int N, const float* Y, const double* data, const double* isig,
-                       const int* flag, double* logL, const int* gate, hipStream_t s) {
+                       const int* flag, double* logL, const int* gate, hipStream_t s, const int* dM) {
   if (M <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_chi2, dim3(M), dim3(64), 0, s, M, N, Y, data, isig, flag, logL, gate);
+  hipLaunchKernelGGL(k_chi2, dim3(M), dim3(64), 0, s, M, N, Y, data, isig, flag, logL, gate, dM);
   return hipGetLastError();
 }
 
@@ -243,15 +246,16 @@ hipError_t launch_chi2(int M, int N, const float* Y, const double* data, const d
 namespace ns {
 
 hipError_t net_forward(const NetDev& net, int mode_first, int mode_rest, int M, const float* X,
-                       float* H0, float* H1, float* Y, const int* gate, hipStream_t s) {
+                       float* H0, float* H1, float* Y, const int* gate, hipStream_t s, const int* dM) {
   const float* in = X;
   long ldin = net.widths[0];
   for (int l = 0; l < net.n_layers; ++l) {
     const int K = net.widths[l], N = net.widths[l + 1];
     const bool last = (l == net.n_layers - 1);
     float* out = last ? Y : ((l % 2 == 0) ? H0 : H1);
-    hipError_t e = launch_gemm(l == 0 ? mode_first : mode_rest, M, N, K, in, ldin, 1, net.Wt[l], K, 1,
-                               net.b[l], last ? kActNone : net.act, out, N, nullptr, 0, gate, s);
+    hipError_t e = launch_gemm(l == 0 ? mode_first : mode_rest, M, N, K, in, ldin, 1, net.Wt[l],
+                               net.w_rowmajor ? 1 : K, net.w_rowmajor ? N : 1, net.b[l],
+                               last ? kActNone : net.act, out, N, nullptr, 0, gate, s, dM);
     if (e != hipSuccess) return e;
     in = out;
     ldin = N;

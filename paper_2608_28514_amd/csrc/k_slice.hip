@@ -202,10 +202,11 @@ k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
     new_logL[j] = lx;
     hist_logL[static_cast<long>(TH - 1) * m + j] = lx;
     hist_n[j] = hn;
-    chain_stat[4 * j + 0] = n_evals;
-    chain_stat[4 * j + 1] = n_oob;
-    chain_stat[4 * j + 2] = n_so;
-    chain_stat[4 * j + 3] = n_sh;
+    chain_stat[kStatW * j + 0] = n_evals;
+    chain_stat[kStatW * j + 1] = n_oob;
+    chain_stat[kStatW * j + 2] = n_so;
+    chain_stat[kStatW * j + 3] = n_sh;
+    chain_stat[kStatW * j + 4] = 0;
   }
 }
 

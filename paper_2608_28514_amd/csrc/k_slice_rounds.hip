@@ -24,6 +24,7 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
                  const int* __restrict__ seeds, const double* __restrict__ tau,
                  const double* __restrict__ LW, ChainState<T>* __restrict__ cs, T* __restrict__ pts,
                  float* __restrict__ xin, int* __restrict__ flag, const double* __restrict__ rlogL,
+                 double* __restrict__ rthr, const int* __restrict__ sflag,
                  int* __restrict__ gate, T* __restrict__ new_u, double* __restrict__ new_logL,
                  int* __restrict__ chain_stat, double* __restrict__ hist_logL,
                  T* __restrict__ hist_u, int* __restrict__ hist_n, const RunState* __restrict__ st) {
@@ -45,7 +46,7 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
     if (lane == 0) {
       const int s = seeds[j];
       S.it = 0; S.phase = kPhaseDir; S.ka = -1; S.kb = -1; S.base = 0; S.s0 = 0; S.hn = 0;
-      S.n_evals = 0; S.n_oob = 0; S.n_so = 0; S.n_sh = 0; S.label = label[s];
+      S.n_evals = 0; S.n_oob = 0; S.n_so = 0; S.n_sh = 0; S.n_scr = 0; S.label = label[s];
       S.lx = logL[s];
       S.seed_slot = s;
     }
@@ -67,24 +68,29 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
     const int k = S.base + (left ? lane : lane - E);
     const bool active = lane < 2 * E && (left ? S.ka < 0 : S.kb < 0) && k < p.max_stepout;
     const bool inb = active && flag[row0 + lane] != 0;
-    const bool pass = inb && rlogL[row0 + lane] > tau_e;
+    const bool scr = inb && sflag && sflag[row0 + lane] != 0;   // screened: predicted to fail
+    const bool pass = inb && !scr && rlogL[row0 + lane] > tau_e;
     const uint64_t mp = __ballot(pass);
     const uint64_t mo = __ballot(active && !inb);
-    int ka = S.ka, kb = S.kb, ne = 0, no = 0, nso = 0;
+    const uint64_t ms = __ballot(scr);
+    int ka = S.ka, kb = S.kb, ne = 0, no = 0, nso = 0, nsc = 0;
     const uint32_t emask = (E >= 32) ? 0xffffffffu : ((1u << E) - 1u);
     for (int side = 0; side < 2; ++side) {
       int& kk = side == 0 ? ka : kb;
       if (kk >= 0) continue;
       const uint32_t bits = static_cast<uint32_t>(mp >> (E * side)) & emask;
       const uint32_t obits = static_cast<uint32_t>(mo >> (E * side)) & emask;
+      const uint32_t sbits = static_cast<uint32_t>(ms >> (E * side)) & emask;
       const int kf = (bits == emask) ? E : __builtin_ctz(~bits);
       if (S.base + kf >= p.max_stepout) {        // k == E_max is never evaluated
         ne += p.max_stepout - S.base;
         nso += 1;
         kk = p.max_stepout;
       } else if (kf < E) {
-        ne += kf + (((obits >> kf) & 1u) ? 0 : 1);
-        no += (obits >> kf) & 1u;
+        const uint32_t o = (obits >> kf) & 1u, sc = (sbits >> kf) & 1u;
+        ne += kf + ((o | sc) ? 0 : 1);
+        no += o;
+        nsc += sc;
         kk = S.base + kf;
       } else {
         ne += E;
@@ -93,7 +99,7 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
     __syncthreads();
     if (lane == 0) {
       S.ka = ka; S.kb = kb;
-      S.n_evals += ne; S.n_oob += no; S.n_so += nso;
+      S.n_evals += ne; S.n_oob += no; S.n_so += nso; S.n_scr += nsc;
       if (ka >= 0 && kb >= 0) {
         S.a = S.a0 - static_cast<T>(ka) * w;
         S.b = S.b0 + static_cast<T>(kb) * w;
@@ -108,10 +114,12 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
     const int Sn = min(p.sh_spec, p.max_shrink - S.s0);
     const bool mine = lane < Sn;
     const bool inb = mine && flag[row0 + lane] != 0;
-    const double l = inb ? rlogL[row0 + lane] : -INFINITY;
+    const bool scr = inb && sflag && sflag[row0 + lane] != 0;
+    const double l = (inb && !scr) ? rlogL[row0 + lane] : -INFINITY;
     const bool pass = mine && l > tau_j;
     const uint64_t mp = __ballot(pass);
-    const uint64_t mi = __ballot(inb);
+    const uint64_t mi = __ballot(inb && !scr);
+    const uint64_t ms = __ballot(scr);
     const int upto = mp ? __builtin_ctzll(mp) : Sn - 1;
     const uint64_t taken = (upto >= 63) ? ~0ull : ((2ull << upto) - 1ull);
     const bool last = (S.it == p.n_iter - 1);
@@ -128,7 +136,8 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
     __syncthreads();
     if (lane == 0) {
       S.n_evals += __popcll(mi & taken);
-      S.n_oob += (upto + 1) - __popcll(mi & taken);
+      S.n_scr += __popcll(ms & taken);
+      S.n_oob += (upto + 1) - __popcll(mi & taken) - __popcll(ms & taken);
       if (last) S.hn = min(S.s0 + upto + 1, TH - 1);
       bool next_iter = false;
       if (mp) {
@@ -154,10 +163,11 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
         new_logL[j] = S.lx;
         hist_logL[static_cast<long>(TH - 1) * m + j] = S.lx;
         hist_n[j] = S.hn;
-        chain_stat[4 * j + 0] = S.n_evals;
-        chain_stat[4 * j + 1] = S.n_oob;
-        chain_stat[4 * j + 2] = S.n_so;
-        chain_stat[4 * j + 3] = S.n_sh;
+        chain_stat[kStatW * j + 0] = S.n_evals;
+        chain_stat[kStatW * j + 1] = S.n_oob;
+        chain_stat[kStatW * j + 2] = S.n_so;
+        chain_stat[kStatW * j + 3] = S.n_sh;
+        chain_stat[kStatW * j + 4] = S.n_scr;
       }
     }
   }
@@ -227,6 +237,7 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
   if (lane < P) {
     const long r = row0 + lane;
     flag[r] = inb ? 1 : 0;
+    if (rthr) rthr[r] = (S.phase == kPhaseStepout) ? tau_e : tau_j;
     if (has)
       for (int i = 0; i < d; ++i) {
         const T yi = S.x[i] + toff * S.v[i];
@@ -260,13 +271,14 @@ hipError_t launch_rounds_advance(int round, const RoundsParams& p, const Shape& 
     hipLaunchKernelGGL(k_rounds_advance<float>, dim3(p.m), dim3(64), 0, s, round, p,
                        static_cast<const float*>(b.u), b.logL, b.label, b.chol_f, b.seeds, b.tau, b.LW,
                        static_cast<ChainState<float>*>(r.cs), static_cast<float*>(r.pts), r.xin, r.flag,
-                       r.rlogL, r.gate, static_cast<float*>(b.new_u), b.new_logL, b.chain_stat,
+                       r.rlogL, r.rthr, r.sflag, r.gate, static_cast<float*>(b.new_u), b.new_logL, b.chain_stat,
                        b.hist_logL, static_cast<float*>(b.hist_u), b.hist_n, b.st);
   else
     hipLaunchKernelGGL(k_rounds_advance<double>, dim3(p.m), dim3(64), 0, s, round, p,
                        static_cast<const double*>(b.u), b.logL, b.label, b.chol, b.seeds, b.tau, b.LW,
                        static_cast<ChainState<double>*>(r.cs), static_cast<double*>(r.pts), r.xin,
-                       r.flag, r.rlogL, r.gate, static_cast<double*>(b.new_u), b.new_logL, b.chain_stat,
+                       r.flag, r.rlogL, r.rthr, r.sflag, r.gate, static_cast<double*>(b.new_u), b.new_logL,
+                       b.chain_stat,
                        b.hist_logL, static_cast<double*>(b.hist_u), b.hist_n, b.st);
   return hipGetLastError();
 }

@@ -13,6 +13,7 @@
 #include "ns_internal.hpp"
 #include "ns_gemm.hpp"
 #include "ns_rounds.hpp"
+#include "ns_surrogate.hpp"
 
 using namespace ns;
 
@@ -47,6 +48,33 @@ struct ns_ctx {
   int mode_first = kF32, mode_rest = kF32;
   double* mlp_data = nullptr;
   double* mlp_isig = nullptr;
+  // compaction of the rows to evaluate (network likelihoods) + learned screen
+  SurrCounters* d_sc = nullptr;
+  SurrCounters* h_sc = nullptr;   // pinned
+  int* d_count = nullptr;
+  int* d_idx = nullptr;
+  int* d_aud = nullptr;
+  float* d_xc = nullptr;
+  double* d_clogL = nullptr;
+  float* d_yhat = nullptr;
+  bool surr = false, screening = false, surr_disabled = false;
+  ns_surrogate_config scfg{};
+  float *sP = nullptr, *sG = nullptr, *sM = nullptr, *sV = nullptr;
+  long s_np = 0;
+  int s_adam_t = 0;
+  int64_t s_calls = 0, s_steps = 0;
+  ns_mlp_desc s_net{}, s_grad{};
+  float *s_norm = nullptr, *s_loss = nullptr, *s_Xb = nullptr, *s_yb = nullptr, *s_Yb = nullptr;
+  float *s_Z = nullptr, *s_H = nullptr, *s_dY = nullptr, *s_work = nullptr, *s_H0 = nullptr, *s_H1 = nullptr;
+  float* rep_x = nullptr;
+  double* rep_y = nullptr;
+  long rep_cap = 0;
+  float* s_xs = nullptr;          // standardised surrogate input of the rows
+  double* d_lo_box = nullptr;     // prior box (device) for the input standardisation
+  double* d_span_box = nullptr;
+  int s_cooldown = 0;
+  unsigned long long s_aud_prev = 0, s_fn_prev = 0;
+  double s_rmse = 0.0;
   std::string err;
   // optional per-kernel-class timing with events on the context's stream
   bool timing = false;
@@ -146,7 +174,7 @@ static ns_status alloc_batch(ns_ctx* c, int M) {
   NS_TRY(dalloc(&b.LW, M));
   NS_TRY(hipMalloc(&b.new_u, sb * M * d));
   NS_TRY(dalloc(&b.new_logL, M));
-  NS_TRY(dalloc(&b.chain_stat, 4 * M));
+  NS_TRY(dalloc(&b.chain_stat, kStatW * M));
   NS_TRY(dalloc(&b.hist_logL, static_cast<size_t>(T) * M));
   NS_TRY(hipMalloc(&b.hist_u, sb * static_cast<size_t>(M) * T * d));
   NS_TRY(dalloc(&b.hist_n, M));
@@ -183,11 +211,16 @@ static void free_all(ns_ctx* c) {
                   b.chain_stat, b.hist_logL, b.hist_u, b.hist_n, b.nodeof, b.members, b.count,
                   b.accepted, b.split_ok, b.logV, b.logV_eff, b.centre, b.cov, b.chol, b.chol_f,
                   b.dead_u, b.dead_logL, b.st, c->d_out3, c->rb.cs, c->rb.pts, c->rb.xin,
-                  c->rb.flag, c->rb.rlogL, c->rb.gate, c->rb.H0, c->rb.H1, c->rb.Y};
+                  c->rb.flag, c->rb.rlogL, c->rb.gate, c->rb.H0, c->rb.H1, c->rb.Y, c->rb.rthr,
+                  c->rb.sflag, c->d_sc, c->d_count, c->d_idx, c->d_aud, c->d_xc, c->d_clogL,
+                  c->d_yhat, c->sP, c->sG, c->sM, c->sV, c->s_norm, c->s_loss, c->s_Xb, c->s_yb,
+                  c->s_Yb, c->s_Z, c->s_H, c->s_dY, c->s_work, c->s_H0, c->s_H1, c->rep_x, c->rep_y,
+                  c->s_xs, c->d_lo_box, c->d_span_box};
   for (void* p : ptrs) hfree(p);
   for (void* p : c->lik_bufs) hfree(p);
   if (c->h_st) (void)hipHostFree(c->h_st);
   if (c->h_gate) (void)hipHostFree(c->h_gate);
+  if (c->h_sc) (void)hipHostFree(c->h_sc);
   if (c->poll_ev) (void)hipEventDestroy(c->poll_ev);
   for (auto& p : c->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -213,14 +246,108 @@ static ns_status enqueue_cluster(ns_ctx* c) {
   return NS_OK;
 }
 
+static int gemm_mode(ns_prec prec) {
+  return prec == NS_BF16X3 ? kBF16S : (prec == NS_BF16 ? kBF16 : kF32);
+}
+
+// Forward pass of a row-major network (ns_mlp_desc) over B rows; Z/H as in
+// ns_mlp_forward.
+static hipError_t mlp_fwd_impl(const ns_mlp_desc* net, int mode, const float* X, long B, float* Y,
+                               float* Zs, float* Hs, hipStream_t s) {
+  const int L = net->n_layers;
+  const float* in = X;
+  long off = 0;
+  for (int l = 0; l < L; ++l) {
+    const int K = net->widths[l], N = net->widths[l + 1];
+    const bool last = l == L - 1;
+    float* out = last ? Y : Hs + off;
+    float* z = Zs ? Zs + off : nullptr;
+    hipError_t e = launch_gemm(mode, static_cast<int>(B), N, K, in, K, 1, net->W[l], 1, N, net->b[l],
+                               last ? kActNone : net->act, out, N, z, N, nullptr, s);
+    if (e != hipSuccess) return e;
+    in = out;
+    off += B * N;
+  }
+  return hipSuccess;
+}
+
+static hipError_t mlp_bwd_impl(const ns_mlp_desc* net, int mode, const float* X, long B, const float* Zs,
+                               const float* Hs, const float* dY, float* const* dW, float* const* db,
+                               float* dX, float* work, hipStream_t s) {
+  const int L = net->n_layers;
+  int maxw = 0;
+  for (int l = 0; l <= L; ++l) maxw = std::max(maxw, net->widths[l]);
+  float* dZ = work;
+  float* dH = work + B * maxw;
+  std::vector<long> off(L + 1, 0);
+  for (int l = 0; l < L; ++l) off[l + 1] = off[l] + B * net->widths[l + 1];
+  const float* g = dY;
+  for (int l = L - 1; l >= 0; --l) {
+    const int K = net->widths[l], N = net->widths[l + 1];
+    const float* dz = g;
+    hipError_t e;
+    if (l < L - 1) {
+      e = launch_act_bwd(B * N, net->act, Zs + off[l], g, dZ, s);
+      if (e != hipSuccess) return e;
+      dz = dZ;
+    }
+    const float* hin = (l == 0) ? X : Hs + off[l - 1];
+    // dW = H^T dZ
+    e = launch_gemm(mode, K, N, static_cast<int>(B), hin, 1, K, dz, 1, N, nullptr, kActNone, dW[l], N,
+                    nullptr, 0, nullptr, s);
+    if (e != hipSuccess) return e;
+    e = launch_colsum(static_cast<int>(B), N, dz, db[l], s);
+    if (e != hipSuccess) return e;
+    if (l > 0 || dX) {
+      float* out = (l == 0) ? dX : dH;
+      // dH = dZ W^T
+      e = launch_gemm(mode, static_cast<int>(B), K, N, dz, N, 1, net->W[l], N, 1, nullptr, kActNone, out,
+                      K, nullptr, 0, nullptr, s);
+      if (e != hipSuccess) return e;
+      if (l > 0) {
+        g = dH;
+        std::swap(dZ, dH);
+      }
+    }
+  }
+  return hipSuccess;
+}
+
+static NetDev surr_netdev(const ns_ctx* c) {
+  NetDev n{};
+  n.n_layers = c->s_net.n_layers;
+  for (int l = 0; l <= n.n_layers; ++l) n.widths[l] = c->s_net.widths[l];
+  n.act = c->s_net.act;
+  for (int l = 0; l < n.n_layers; ++l) { n.Wt[l] = c->s_net.W[l]; n.b[l] = c->s_net.b[l]; }
+  n.max_width = c->scfg.hidden;
+  n.w_rowmajor = 1;
+  return n;
+}
+
 // Likelihood of the first n rows of the row buffers (gate: skip when zero).
-static ns_status eval_rows(ns_ctx* c, long n, const int* gate) {
+// Network likelihoods: in-box rows (minus the ones the surrogate screens out,
+// when allowed) are compacted, evaluated, and scattered back.
+static ns_status eval_rows(ns_ctx* c, long n, const int* gate, bool allow_screen = false) {
   TimeScope ts(c, NS_TIME_LIK);
   if (c->is_mlp) {
-    NS_TRY(net_forward(c->net, c->mode_first, c->mode_rest, static_cast<int>(n), c->rb.xin, c->rb.H0,
-                       c->rb.H1, c->rb.Y, gate, c->stream));
+    const int screening = (allow_screen && c->screening) ? 1 : 0;
+    const int d = c->sh.d;
+    if (screening) {
+      const NetDev sn = surr_netdev(c);
+      const int mode = gemm_mode(c->scfg.prec);
+      NS_TRY(launch_standardize(n, d, c->rb.xin, c->s_norm, c->s_xs, gate, c->stream));
+      NS_TRY(net_forward(sn, mode, mode, static_cast<int>(n), c->s_xs, c->s_H0, c->s_H1, c->d_yhat, gate,
+                         c->stream));
+    }
+    NS_TRY(launch_screen(static_cast<int>(n), d, screening, c->scfg.margin, std::max(1, c->scfg.audit_period),
+                         c->rb.flag, c->rb.rthr, c->d_yhat, c->s_norm, c->rb.xin, c->rb.sflag, c->d_idx,
+                         c->d_aud, c->d_xc, c->d_count, c->rb.rlogL, c->d_sc, gate, c->stream));
+    NS_TRY(net_forward(c->net, c->mode_first, c->mode_rest, static_cast<int>(n), c->d_xc, c->rb.H0,
+                       c->rb.H1, c->rb.Y, gate, c->stream, c->d_count));
     NS_TRY(launch_chi2(static_cast<int>(n), c->net.widths[c->net.n_layers], c->rb.Y, c->mlp_data,
-                       c->mlp_isig, c->rb.flag, c->rb.rlogL, gate, c->stream));
+                       c->mlp_isig, nullptr, c->d_clogL, gate, c->stream, c->d_count));
+    NS_TRY(launch_scatter(d, c->d_count, c->d_idx, c->d_aud, c->d_clogL, c->rb.rthr, c->d_xc, c->rb.rlogL,
+                          c->rep_x, c->rep_y, c->surr ? c->rep_cap : 0, c->d_sc, gate, c->stream));
   } else {
     NS_TRY(launch_rows_loglike(c->sh, c->lik, n, c->rb.pts, c->rb.flag, c->rb.rlogL, gate, c->stream));
   }
@@ -243,7 +370,7 @@ static ns_status run_rounds(ns_ctx* c, int m) {
         TimeScope ts(c, NS_TIME_SLICE);
         NS_TRY(launch_rounds_advance(r, p, c->sh, c->b, c->rb, c->stream));
       }
-      ns_status e = eval_rows(c, rows, c->rb.gate + r);
+      ns_status e = eval_rows(c, rows, c->rb.gate + r, true);
       if (e != NS_OK) return e;
     }
     NS_TRY(hipMemcpyAsync(c->h_gate, c->rb.gate + (r - 1), sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -254,6 +381,72 @@ static ns_status run_rounds(ns_ctx* c, int m) {
       return NS_ESTATE;
     }
   }
+  return NS_OK;
+}
+
+// One training call of the surrogate (train_iters Adam steps on minibatches
+// of the replay ring), entirely on the context's stream.
+static ns_status surr_train(ns_ctx* c) {
+  const ns_surrogate_config& sc = c->scfg;
+  const int B = sc.batch, d = c->sh.d;
+  const int mode = gemm_mode(sc.prec);
+  for (int it = 0; it < sc.train_iters; ++it) {
+    NS_TRY(launch_sample_batch(B, d, sc.seed, static_cast<uint32_t>(c->s_calls), static_cast<uint32_t>(it),
+                               c->rep_x, c->rep_y, c->rep_cap, c->d_sc, c->b.LW, c->b.st, c->b.centre,
+                               c->b.cov, c->d_lo_box, c->d_span_box, sc.floor_below, c->s_Xb, c->s_yb,
+                               c->s_norm, c->stream));
+    NS_TRY(mlp_fwd_impl(&c->s_net, mode, c->s_Xb, B, c->s_Yb, c->s_Z, c->s_H, c->stream));
+    NS_TRY(launch_mse_grad(B, c->s_Yb, c->s_yb, c->s_dY, c->s_loss, c->stream));
+    float* dW[8];
+    float* db[8];
+    for (int l = 0; l < c->s_grad.n_layers; ++l) {
+      dW[l] = const_cast<float*>(c->s_grad.W[l]);
+      db[l] = const_cast<float*>(c->s_grad.b[l]);
+    }
+    NS_TRY(mlp_bwd_impl(&c->s_net, mode, c->s_Xb, B, c->s_Z, c->s_H, c->s_dY, dW, db, nullptr, c->s_work,
+                        c->stream));
+    NS_TRY(launch_adam(c->s_np, sc.lr, 0.9f, 0.999f, 1e-8f, ++c->s_adam_t, c->sP, c->sG, c->sM, c->sV,
+                       c->stream));
+  }
+  c->s_calls += 1;
+  return NS_OK;
+}
+
+// After a step: train every train_every steps, then decide whether the screen
+// runs in the next step: trained, the last minibatch error (in nats) below
+// half the margin, and no cool-down after an audit window whose false-screen
+// rate exceeded max_fn_rate.
+static ns_status surr_after_step(ns_ctx* c) {
+  if (c->known_done) return NS_OK;
+  c->s_steps += 1;
+  NS_TRY(hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(SurrCounters), hipMemcpyDeviceToHost, c->stream));
+  NS_TRY(hipStreamSynchronize(c->stream));
+  const SurrCounters h = *c->h_sc;
+  bool trained = false;
+  if (h.pairs >= static_cast<unsigned long long>(std::min<long>(c->scfg.min_pairs, c->rep_cap)) &&
+      c->s_steps % std::max(1, c->scfg.train_every) == 0) {
+    ns_status r = surr_train(c);
+    if (r != NS_OK) return r;
+    trained = true;
+  }
+  // audit window of the step that just ran
+  const unsigned long long da = h.audited - c->s_aud_prev, df = h.false_screens - c->s_fn_prev;
+  c->s_aud_prev = h.audited;
+  c->s_fn_prev = h.false_screens;
+  if (da >= 8 && static_cast<double>(df) > c->scfg.max_fn_rate * static_cast<double>(da)) {
+    c->s_cooldown = 5;
+    c->surr_disabled = true;
+  }
+  if (c->s_cooldown > 0) --c->s_cooldown;
+  if (trained) {
+    float hn[2], loss = 0.f;
+    NS_TRY(hipMemcpyAsync(hn, c->s_norm, sizeof(hn), hipMemcpyDeviceToHost, c->stream));
+    NS_TRY(hipMemcpyAsync(&loss, c->s_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    NS_TRY(hipStreamSynchronize(c->stream));
+    c->s_rmse = std::isfinite(loss) ? static_cast<double>(hn[1]) * std::sqrt(static_cast<double>(loss)) : 1e300;
+  }
+  c->screening = c->s_calls > 0 && c->s_cooldown == 0 && c->s_rmse < 0.5 * c->scfg.margin;
+  if (c->screening) c->surr_disabled = false;
   return NS_OK;
 }
 
@@ -354,12 +547,8 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
       free_all(c); delete c; return NS_EDEVICE;                                  \
     }                                                                            \
   } while (0)
-  if (hip_stream) {
-    c->stream = static_cast<hipStream_t>(hip_stream);
-  } else {
-    NS_INIT_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
-    c->own_stream = true;
-  }
+  // NULL is the default (null) stream, ordered with every blocking stream
+  c->stream = static_cast<hipStream_t>(hip_stream);
   // likelihood
   LikDev& L = c->lik;
   L.kind = lik->kind;
@@ -487,6 +676,19 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
       NS_INIT_HIP(dalloc(&rb.H0, static_cast<size_t>(rb.rows_cap) * c->net.max_width));
       NS_INIT_HIP(dalloc(&rb.H1, static_cast<size_t>(rb.rows_cap) * c->net.max_width));
       NS_INIT_HIP(dalloc(&rb.Y, static_cast<size_t>(rb.rows_cap) * c->net.widths[c->net.n_layers]));
+      NS_INIT_HIP(dalloc(&rb.rthr, rb.rows_cap));
+      NS_INIT_HIP(dalloc(&rb.sflag, rb.rows_cap));
+      NS_INIT_HIP(dalloc(&c->d_sc, 1));
+      NS_INIT_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_sc), sizeof(SurrCounters), hipHostMallocDefault));
+      NS_INIT_HIP(dalloc(&c->d_count, 1));
+      NS_INIT_HIP(dalloc(&c->d_idx, rb.rows_cap));
+      NS_INIT_HIP(dalloc(&c->d_aud, rb.rows_cap));
+      NS_INIT_HIP(dalloc(&c->d_xc, static_cast<size_t>(rb.rows_cap) * d));
+      NS_INIT_HIP(dalloc(&c->d_clogL, rb.rows_cap));
+      NS_INIT_HIP(dalloc(&c->s_norm, kNormLen));
+      NS_INIT_HIP(hipMemsetAsync(c->d_sc, 0, sizeof(SurrCounters), c->stream));
+      NS_INIT_HIP(hipMemsetAsync(rb.rthr, 0, sizeof(double) * rb.rows_cap, c->stream));
+      NS_INIT_HIP(hipMemsetAsync(c->s_norm, 0, sizeof(float) * kNormLen, c->stream));
     }
     NS_INIT_HIP(launch_init_rows(n_live, d, cfg->seed, rp, sh.state_f32, b.u, rb.pts, rb.xin, rb.flag,
                                  c->stream));
@@ -567,6 +769,10 @@ ns_status ns_step_batch(ns_ctx* c, int m) {
   c->since_cluster += m;
   c->dead_ub += m;
   c->last_m = m;
+  if (c->surr) {
+    ns_status r = surr_after_step(c);
+    if (r != NS_OK) return r;
+  }
   poll(c);
   return c->known_done ? NS_DONE : NS_OK;
 }
@@ -710,9 +916,9 @@ ns_status ns_get_last_batch(ns_ctx* c, int* m_out, int* seeds, double* tau, doub
   if (hist_logL) NS_TRY(hipMemcpy(hist_logL, c->b.hist_logL, sizeof(double) * T * m, hipMemcpyDeviceToHost));
   if (hist_n) NS_TRY(hipMemcpy(hist_n, c->b.hist_n, sizeof(int) * m, hipMemcpyDeviceToHost));
   if (chain_evals) {
-    std::vector<int> cs(4 * m);
-    NS_TRY(hipMemcpy(cs.data(), c->b.chain_stat, sizeof(int) * 4 * m, hipMemcpyDeviceToHost));
-    for (int j = 0; j < m; ++j) chain_evals[j] = cs[4 * j];
+    std::vector<int> cs(kStatW * m);
+    NS_TRY(hipMemcpy(cs.data(), c->b.chain_stat, sizeof(int) * kStatW * m, hipMemcpyDeviceToHost));
+    for (int j = 0; j < m; ++j) chain_evals[j] = cs[kStatW * j];
   }
   auto conv = [&](const void* src, size_t n, double* dst) -> hipError_t {
     if (c->sh.state_f32) {
@@ -742,6 +948,13 @@ ns_status ns_stats(ns_ctx* c, ns_stats_t* s) {
   s->clusterings = static_cast<int64_t>(h.clusterings);
   s->nan_logL = static_cast<int64_t>(h.nan_logL);
   s->done = h.done;
+  s->screened = static_cast<int64_t>(h.screened);
+  s->net_rows = 0;
+  if (c->d_sc) {
+    SurrCounters sc{};
+    NS_TRY(hipMemcpy(&sc, c->d_sc, sizeof(sc), hipMemcpyDeviceToHost));
+    s->net_rows = static_cast<int64_t>(sc.emu_rows);
+  }
   std::vector<int> acc(c->sh.nodes);
   NS_TRY(hipMemcpy(acc.data(), c->b.accepted, sizeof(int) * acc.size(), hipMemcpyDeviceToHost));
   int nc = 0;
@@ -841,23 +1054,8 @@ ns_status ns_mlp_forward(const ns_mlp_desc* net, ns_prec prec, const float* d_X,
   if (r != NS_OK) return r;
   if (B == 0) return NS_OK;
   if (!d_X || !d_Y) return inval(nullptr, "ns_mlp_forward: null input or output");
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  const int mode = prec == NS_BF16X3 ? kBF16S : (prec == NS_BF16 ? kBF16 : kF32);
-  const int L = net->n_layers;
-  const float* in = d_X;
-  long off = 0;
-  for (int l = 0; l < L; ++l) {
-    const int K = net->widths[l], N = net->widths[l + 1];
-    const bool last = l == L - 1;
-    float* out = last ? d_Y : (d_H ? d_H + off : nullptr);
-    if (!out) return inval(nullptr, "ns_mlp_forward: d_H is required for hidden layers");
-    float* z = d_Z ? d_Z + off : nullptr;
-    // W row major K x N: B(k, n) = W[k*N + n]
-    NS_TRY(launch_gemm(mode, static_cast<int>(B), N, K, in, K, 1, net->W[l], 1, N, net->b[l],
-                       last ? kActNone : net->act, out, N, z, N, nullptr, s));
-    in = out;
-    off += B * N;
-  }
+  if (net->n_layers > 1 && !d_H) return inval(nullptr, "ns_mlp_forward: d_H is required for hidden layers");
+  NS_TRY(mlp_fwd_impl(net, gemm_mode(prec), d_X, B, d_Y, d_Z, d_H, static_cast<hipStream_t>(hip_stream)));
   return NS_OK;
 }
 
@@ -870,40 +1068,133 @@ ns_status ns_mlp_backward(const ns_mlp_desc* net, ns_prec prec, const float* d_X
   if (r != NS_OK) return r;
   if (!d_X || !d_Z || !d_dY || !d_dW || !d_db || !d_work || (net->n_layers > 1 && !d_H))
     return inval(nullptr, "ns_mlp_backward: null argument");
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  const int mode = prec == NS_BF16X3 ? kBF16S : (prec == NS_BF16 ? kBF16 : kF32);
-  const int L = net->n_layers;
-  int maxw = 0;
-  for (int l = 0; l <= L; ++l) maxw = std::max(maxw, net->widths[l]);
-  float* dZ = d_work;
-  float* dH = d_work + B * maxw;
-  std::vector<long> off(L + 1, 0);
-  for (int l = 0; l < L; ++l) off[l + 1] = off[l] + B * net->widths[l + 1];
-  const float* g = d_dY;   // gradient w.r.t. the output of layer l
-  for (int l = L - 1; l >= 0; --l) {
-    const int K = net->widths[l], N = net->widths[l + 1];
-    const float* dz = g;
-    if (l < L - 1) {
-      NS_TRY(launch_act_bwd(B * N, net->act, d_Z + off[l], g, dZ, s));
-      dz = dZ;
-    }
-    const float* hin = (l == 0) ? d_X : d_H + off[l - 1];
-    // dW = H^T dZ : M = K, N = N, depth B
-    NS_TRY(launch_gemm(mode, K, N, static_cast<int>(B), hin, 1, K, dz, 1, N, nullptr, kActNone,
-                       d_dW[l], N, nullptr, 0, nullptr, s));
-    NS_TRY(launch_colsum(static_cast<int>(B), N, dz, d_db[l], s));
-    if (l > 0 || d_dX) {
-      float* out = (l == 0) ? d_dX : dH;
-      // dH = dZ W^T : M = B, N = K, depth N; B(k=n, col=i) = W[i*N + n]
-      NS_TRY(launch_gemm(mode, static_cast<int>(B), K, N, dz, N, 1, net->W[l], N, 1, nullptr, kActNone,
-                         out, K, nullptr, 0, nullptr, s));
-      if (l > 0) {
-        // move dH into place for the next layer (dZ buffer is reused)
-        g = dH;
-        std::swap(dZ, dH);
-      }
-    }
+  NS_TRY(mlp_bwd_impl(net, gemm_mode(prec), d_X, B, d_Z, d_H, d_dY, d_dW, d_db, d_dX, d_work,
+                      static_cast<hipStream_t>(hip_stream)));
+  return NS_OK;
+}
+
+ns_status ns_surrogate_default(ns_surrogate_config* sc) {
+  if (!sc) return NS_EINVAL;
+  sc->hidden = 256;
+  sc->replay_cap = 65536;
+  sc->batch = 2048;
+  sc->train_every = 1;
+  sc->train_iters = 25;
+  sc->lr = 1e-3f;
+  sc->margin = 5.0;
+  sc->floor_below = 40.0;
+  sc->audit_period = 16;
+  sc->max_fn_rate = 0.02;
+  sc->min_pairs = 16384;
+  sc->prec = NS_BF16;
+  sc->seed = 7;
+  return NS_OK;
+}
+
+ns_status ns_surrogate_enable(ns_ctx* c, const ns_surrogate_config* sc) {
+  if (!c || !sc) return NS_EINVAL;
+  if (!c->is_mlp) return inval(c, "ns_surrogate_enable: only for network likelihoods");
+  if (c->surr) return inval(c, "ns_surrogate_enable: already enabled");
+  if (sc->hidden < 1 || sc->hidden > 4096 || sc->replay_cap < 1 || sc->batch < 1 || sc->batch > (1 << 20) ||
+      sc->train_iters < 0 || !(sc->lr > 0) || !(sc->margin >= 0) || !(sc->floor_below > 0) ||
+      sc->audit_period < 1 || (sc->prec != NS_FP32 && sc->prec != NS_BF16))
+    return inval(c, "ns_surrogate_enable: invalid configuration");
+  ns_status r = ns_sync(c);
+  if (r != NS_OK) return r;
+  c->scfg = *sc;
+  const int d = c->sh.d, H = sc->hidden;
+  ns_mlp_desc& net = c->s_net;
+  net.n_layers = 3;
+  net.widths[0] = d; net.widths[1] = H; net.widths[2] = H; net.widths[3] = 1;
+  net.act = NS_ACT_SILU;
+  long off[7];
+  off[0] = 0;
+  off[1] = off[0] + static_cast<long>(d) * H;   // b1
+  off[2] = off[1] + H;                          // W2
+  off[3] = off[2] + static_cast<long>(H) * H;   // b2
+  off[4] = off[3] + H;                          // W3
+  off[5] = off[4] + H;                          // b3
+  off[6] = off[5] + 1;
+  c->s_np = off[6];
+  NS_TRY(dalloc(&c->sP, c->s_np));
+  NS_TRY(dalloc(&c->sG, c->s_np));
+  NS_TRY(dalloc(&c->sM, c->s_np));
+  NS_TRY(dalloc(&c->sV, c->s_np));
+  NS_TRY(hipMemsetAsync(c->sP, 0, sizeof(float) * c->s_np, c->stream));
+  NS_TRY(hipMemsetAsync(c->sM, 0, sizeof(float) * c->s_np, c->stream));
+  NS_TRY(hipMemsetAsync(c->sV, 0, sizeof(float) * c->s_np, c->stream));
+  NS_TRY(launch_glorot(static_cast<long>(d) * H, d, H, sc->seed, 0, c->sP + off[0], c->stream));
+  NS_TRY(launch_glorot(static_cast<long>(H) * H, H, H, sc->seed, 1, c->sP + off[2], c->stream));
+  NS_TRY(launch_glorot(H, H, 1, sc->seed, 2, c->sP + off[4], c->stream));
+  ns_mlp_desc& g = c->s_grad;
+  g = net;
+  for (int l = 0; l < 3; ++l) {
+    net.W[l] = c->sP + off[2 * l];
+    net.b[l] = c->sP + off[2 * l + 1];
+    g.W[l] = c->sG + off[2 * l];
+    g.b[l] = c->sG + off[2 * l + 1];
   }
+  const long B = sc->batch;
+  c->rep_cap = sc->replay_cap;
+  NS_TRY(dalloc(&c->rep_x, static_cast<size_t>(c->rep_cap) * d));
+  NS_TRY(dalloc(&c->rep_y, static_cast<size_t>(c->rep_cap)));
+  NS_TRY(dalloc(&c->s_loss, 1));
+  NS_TRY(dalloc(&c->s_Xb, static_cast<size_t>(B) * d));
+  NS_TRY(dalloc(&c->s_yb, B));
+  NS_TRY(dalloc(&c->s_Yb, B));
+  NS_TRY(dalloc(&c->s_dY, B));
+  NS_TRY(dalloc(&c->s_Z, static_cast<size_t>(B) * (2 * H + 1)));
+  NS_TRY(dalloc(&c->s_H, static_cast<size_t>(B) * (2 * H + 1)));
+  NS_TRY(dalloc(&c->s_work, static_cast<size_t>(2) * B * std::max(H, d)));
+  NS_TRY(dalloc(&c->s_H0, static_cast<size_t>(c->rb.rows_cap) * H));
+  NS_TRY(dalloc(&c->s_H1, static_cast<size_t>(c->rb.rows_cap) * H));
+  NS_TRY(dalloc(&c->d_yhat, c->rb.rows_cap));
+  NS_TRY(dalloc(&c->s_xs, static_cast<size_t>(c->rb.rows_cap) * d));
+  std::vector<double> lo_box(d), span_box(d);
+  for (int i = 0; i < d; ++i) { lo_box[i] = c->lik.lo[i]; span_box[i] = c->lik.span[i]; }
+  NS_TRY(dalloc(&c->d_lo_box, d));
+  NS_TRY(dalloc(&c->d_span_box, d));
+  NS_TRY(hipMemcpy(c->d_lo_box, lo_box.data(), sizeof(double) * d, hipMemcpyHostToDevice));
+  NS_TRY(hipMemcpy(c->d_span_box, span_box.data(), sizeof(double) * d, hipMemcpyHostToDevice));
+  NS_TRY(hipStreamSynchronize(c->stream));
+  c->surr = true;
+  return NS_OK;
+}
+
+ns_status ns_surrogate_stats(ns_ctx* c, ns_surrogate_stats_t* s) {
+  if (!c || !s) return NS_EINVAL;
+  if (!c->is_mlp) return inval(c, "ns_surrogate_stats: only for network likelihoods");
+  ns_status r = ns_sync(c);
+  if (r != NS_OK) return r;
+  SurrCounters h{};
+  NS_TRY(hipMemcpy(&h, c->d_sc, sizeof(h), hipMemcpyDeviceToHost));
+  float loss = 0.f;
+  if (c->surr) NS_TRY(hipMemcpy(&loss, c->s_loss, sizeof(float), hipMemcpyDeviceToHost));
+  s->pairs = static_cast<int64_t>(h.pairs);
+  s->net_rows = static_cast<int64_t>(h.emu_rows);
+  s->screened = static_cast<int64_t>(h.screened_seen);
+  s->audited = static_cast<int64_t>(h.audited);
+  s->false_screens = static_cast<int64_t>(h.false_screens);
+  s->train_calls = c->s_calls;
+  s->screening = c->screening ? 1 : 0;
+  s->disabled = c->surr_disabled ? 1 : 0;
+  s->last_loss = loss;
+  return NS_OK;
+}
+
+ns_status ns_surrogate_predict(ns_ctx* c, const float* d_u, int64_t n, float* d_out) {
+  if (!c || n < 0 || (n > 0 && (!d_u || !d_out))) return NS_EINVAL;
+  if (!c->surr) return inval(c, "ns_surrogate_predict: surrogate not enabled");
+  const int d = c->sh.d;
+  const NetDev sn = surr_netdev(c);
+  const int mode = gemm_mode(c->scfg.prec);
+  for (int64_t k0 = 0; k0 < n; k0 += c->rb.rows_cap) {
+    const long nn = static_cast<long>(std::min<int64_t>(c->rb.rows_cap, n - k0));
+    NS_TRY(launch_standardize(nn, d, d_u + k0 * d, c->s_norm, c->s_xs, nullptr, c->stream));
+    NS_TRY(net_forward(sn, mode, mode, static_cast<int>(nn), c->s_xs, c->s_H0, c->s_H1, d_out + k0, nullptr,
+                       c->stream));
+  }
+  NS_TRY(launch_norm_apply(n, c->s_norm, d_out, c->stream));
   return NS_OK;
 }
 

@@ -262,8 +262,9 @@ struct RunState {
   double A;              // Z-weighted mean of logL of the dead points
   int32_t done;
   int32_t pad;
+  double lmax;           // best live logL after the last step
   // counters
-  unsigned long long evals, oob, so_caps, sh_caps, nan_logL, clusterings;
+  unsigned long long evals, oob, so_caps, sh_caps, nan_logL, clusterings, screened;
 };
 
 __device__ __forceinline__ double logaddexp(double a, double b) {

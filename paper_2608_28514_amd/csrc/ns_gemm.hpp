@@ -9,16 +9,20 @@ namespace ns {
 enum GemmMode : int { kF32 = 0, kBF16S = 1, kBF16 = 2 };
 enum Act : int { kActNone = 0, kActTanh = 1, kActSilu = 2 };
 
+// dM (may be null): device-side row count; rows at or beyond it are skipped.
 hipError_t launch_gemm(int mode, int M, int N, int K, const float* A, long sar, long sak,
                        const float* B, long sbn, long sbk, const float* bias, int act, float* C,
-                       long ldc, float* Z, long ldz, const int* gate, hipStream_t s);
+                       long ldc, float* Z, long ldz, const int* gate, hipStream_t s,
+                       const int* dM = nullptr);
 hipError_t launch_act_bwd(long n, int act, const float* Z, const float* dH, float* dZ, hipStream_t s);
 hipError_t launch_colsum(int M, int N, const float* dZ, float* db, hipStream_t s);
 hipError_t launch_chi2(int M, int N, const float* Y, const double* data, const double* isig,
-                       const int* flag, double* logL, const int* gate, hipStream_t s);
+                       const int* flag, double* logL, const int* gate, hipStream_t s,
+                       const int* dM = nullptr);
 
 // A network held on the device: layer l maps widths[l] -> widths[l+1]; the
-// weights are stored transposed (Wt_l: widths[l+1] x widths[l], FP32).
+// weights are stored transposed (Wt_l: widths[l+1] x widths[l], FP32), or
+// row major (widths[l] x widths[l+1]) when w_rowmajor is set.
 struct NetDev {
   int n_layers;
   int widths[9];
@@ -26,12 +30,14 @@ struct NetDev {
   const float* Wt[8];
   const float* b[8];
   int max_width;
+  int w_rowmajor;
 };
 
 // Forward over M rows of X (M x widths[0]); H0/H1 ping-pong buffers of
 // M x max_width floats; output Y (M x widths[L]).  mode_first applies to
 // layer 0, mode_rest to the others.
 hipError_t net_forward(const NetDev& net, int mode_first, int mode_rest, int M, const float* X,
-                       float* H0, float* H1, float* Y, const int* gate, hipStream_t s);
+                       float* H0, float* H1, float* Y, const int* gate, hipStream_t s,
+                       const int* dM = nullptr);
 
 }  // namespace ns

@@ -18,7 +18,7 @@ struct DevBufs {
   double* LW;           // M (logL of the m worst, ascending)
   void* new_u;          // M x d
   double* new_logL;     // M
-  int* chain_stat;      // M x 4: evals, oob, stepout caps, shrink caps
+  int* chain_stat;      // M x kStatW: evals, oob, stepout caps, shrink caps, screened
   double* hist_logL;    // T x M (row t, column chain)
   void* hist_u;         // M x T x d
   int* hist_n;          // M
@@ -39,6 +39,8 @@ struct DevBufs {
   double* dead_logL;    // cap
   RunState* st;
 };
+
+constexpr int kStatW = 8;  // ints per chain in chain_stat
 
 struct Shape {
   int N, d, T, nodes, depth;

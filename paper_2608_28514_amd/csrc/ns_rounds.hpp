@@ -14,7 +14,7 @@ struct ChainState {
   T v[kMaxD];
   double lx;
   T a0, b0, a, b, br_a, br_b;
-  int it, phase, ka, kb, base, s0, hn, n_evals, n_oob, n_so, n_sh, label, seed_slot, pad;
+  int it, phase, ka, kb, base, s0, hn, n_evals, n_oob, n_so, n_sh, label, seed_slot, n_scr;
 };
 
 struct RoundsParams {
@@ -31,6 +31,8 @@ struct RoundBufs {
   float* xin;      // rows x d, network input theta
   int* flag;       // rows: 1 = in the box, evaluate
   double* rlogL;   // rows
+  double* rthr;    // rows: the threshold the row is tested against
+  int* sflag;      // rows: 1 = screened out by the surrogate (not evaluated)
   int* gate;       // per round: some chain still running
   long rows_cap;
   int gate_cap;

@@ -49,7 +49,20 @@ class NsStats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("dead", C.c_int64), ("evals", C.c_int64),
                 ("oob", C.c_int64), ("stepout_caps", C.c_int64), ("shrink_caps", C.c_int64),
                 ("clusterings", C.c_int64), ("nan_logL", C.c_int64), ("done", C.c_int32),
-                ("n_clusters", C.c_int32)]
+                ("n_clusters", C.c_int32), ("screened", C.c_int64), ("net_rows", C.c_int64)]
+
+
+class NsSurrogateConfig(C.Structure):
+    _fields_ = [("hidden", C.c_int), ("replay_cap", C.c_int), ("batch", C.c_int), ("train_every", C.c_int),
+                ("train_iters", C.c_int), ("lr", C.c_float), ("margin", C.c_double),
+                ("floor_below", C.c_double), ("audit_period", C.c_int), ("max_fn_rate", C.c_double),
+                ("min_pairs", C.c_int), ("prec", C.c_int), ("seed", C.c_uint64)]
+
+
+class NsSurrogateStats(C.Structure):
+    _fields_ = [("pairs", C.c_int64), ("net_rows", C.c_int64), ("screened", C.c_int64),
+                ("audited", C.c_int64), ("false_screens", C.c_int64), ("train_calls", C.c_int64),
+                ("screening", C.c_int32), ("disabled", C.c_int32), ("last_loss", C.c_double)]
 
 
 class NsMlpDesc(C.Structure):
@@ -94,6 +107,10 @@ def lib():
             "ns_philox": [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int64, vp,
                           vp],
             "ns_set_timing": [vp, C.c_int],
+            "ns_surrogate_default": [C.POINTER(NsSurrogateConfig)],
+            "ns_surrogate_enable": [vp, C.POINTER(NsSurrogateConfig)],
+            "ns_surrogate_stats": [vp, C.POINTER(NsSurrogateStats)],
+            "ns_surrogate_predict": [vp, vp, C.c_int64, vp],
             "ns_mlp_forward": [C.POINTER(NsMlpDesc), C.c_int, vp, C.c_int64, vp, vp, vp, vp],
             "ns_mlp_backward": [C.POINTER(NsMlpDesc), C.c_int, vp, C.c_int64, vp, vp, vp,
                                 C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), vp, vp, vp],
@@ -335,6 +352,33 @@ def ns_mlp_backward(desc, prec, X, Z, H, dY, dWs, dbs, dX, work, stream=None):
            None, "ns_mlp_backward")
 
 
+def ns_surrogate_default():
+    c = NsSurrogateConfig()
+    _check(lib().ns_surrogate_default(C.byref(c)), None, "ns_surrogate_default")
+    return c
+
+
+def ns_surrogate_enable(ctx, **kw):
+    c = ns_surrogate_default()
+    for k, v in kw.items():
+        if k == "prec" and isinstance(v, str):
+            v = PREC[v]
+        setattr(c, k, v)
+    _check(lib().ns_surrogate_enable(ctx, C.byref(c)), ctx, "ns_surrogate_enable")
+    return c
+
+
+def ns_surrogate_stats(ctx):
+    s = NsSurrogateStats()
+    _check(lib().ns_surrogate_stats(ctx, C.byref(s)), ctx, "ns_surrogate_stats")
+    return {k: getattr(s, k) for k, _ in NsSurrogateStats._fields_}
+
+
+def ns_surrogate_predict(ctx, d_u, d_out):
+    _check(lib().ns_surrogate_predict(ctx, _ptr(d_u), int(d_out.numel()), _ptr(d_out)), ctx,
+           "ns_surrogate_predict")
+
+
 def ns_free(ctx):
     if ctx:
         lib().ns_free(ctx)
@@ -384,6 +428,17 @@ class Sampler:
 
     def stats(self):
         return ns_stats(self.ctx)
+
+    def enable_surrogate(self, **kw):
+        return ns_surrogate_enable(self.ctx, **kw)
+
+    def surrogate_stats(self):
+        return ns_surrogate_stats(self.ctx)
+
+    def timing(self, on=None):
+        if on is not None:
+            ns_set_timing(self.ctx, on)
+        return ns_get_timing(self.ctx)
 
     def close(self):
         if getattr(self, "ctx", None):
