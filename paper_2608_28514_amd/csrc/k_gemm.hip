@@ -37,12 +37,22 @@ __device__ __forceinline__ float act_fwd(int act, float z) {
 __device__ __forceinline__ __bf16 to_bf16(float x) { return static_cast<__bf16>(x); }
 __device__ __forceinline__ float from_bf16(__bf16 x) { return static_cast<float>(x); }
 
+// x = hi + mid + lo, each a bfloat16 (three planes of `plane` elements each).
+__device__ __forceinline__ void store_split(__bf16* out, long plane, long idx, float x) {
+  const __bf16 h = to_bf16(x);
+  const float r1 = x - from_bf16(h);
+  const __bf16 m = to_bf16(r1);
+  out[idx] = h;
+  out[plane + idx] = m;
+  out[2 * plane + idx] = to_bf16(r1 - from_bf16(m));
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(256)
 k_gemm(int M, int N, int K, const float* __restrict__ A, long sar, long sak,
        const float* __restrict__ B, long sbn, long sbk, const float* __restrict__ bias, int act,
        float* __restrict__ C, long ldc, float* __restrict__ Z, long ldz, const int* __restrict__ gate,
-       const int* __restrict__ dM) {
+       const int* __restrict__ dM, __bf16* __restrict__ Csplit, long plane) {
   if (gate && *gate == 0) return;
   if (dM) M = min(M, *dM);              // row count decided on the device
   if (static_cast<int>(blockIdx.y) * kTM >= M) return;
@@ -131,7 +141,9 @@ k_gemm(int M, int N, int K, const float* __restrict__ A, long sar, long sak,
         if (n >= N) continue;
         float z = acc[i][jx] + (bias ? bias[n] : 0.f);
         if (Z) Z[r * ldz + n] = z;
-        C[r * ldc + n] = act_fwd(act, z);
+        const float h = act_fwd(act, z);
+        if (Csplit) store_split(Csplit, plane, r * ldc + n, h);
+        else C[r * ldc + n] = h;
       }
     }
   } else {
@@ -145,25 +157,110 @@ k_gemm(int M, int N, int K, const float* __restrict__ A, long sar, long sak,
           if (r >= M || n >= N) continue;
           float z = macc[tm][tn][i] + (bias ? bias[n] : 0.f);
           if (Z) Z[r * ldz + n] = z;
-          C[r * ldc + n] = act_fwd(act, z);
+          const float h = act_fwd(act, z);
+          if (Csplit) store_split(Csplit, plane, r * ldc + n, h);
+          else C[r * ldc + n] = h;
         }
   }
 }
 
 hipError_t launch_gemm(int mode, int M, int N, int K, const float* A, long sar, long sak,
                        const float* B, long sbn, long sbk, const float* bias, int act, float* C,
-                       long ldc, float* Z, long ldz, const int* gate, hipStream_t s, const int* dM) {
+                       long ldc, float* Z, long ldz, const int* gate, hipStream_t s, const int* dM,
+                       __bf16* Csplit, long plane) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const dim3 grid((N + kTN - 1) / kTN, (M + kTM - 1) / kTM), block(256);
   if (mode == kF32)
     hipLaunchKernelGGL(k_gemm<kF32>, grid, block, 0, s, M, N, K, A, sar, sak, B, sbn, sbk, bias,
-                       act, C, ldc, Z, ldz, gate, dM);
+                       act, C, ldc, Z, ldz, gate, dM, Csplit, plane);
   else if (mode == kBF16S)
     hipLaunchKernelGGL(k_gemm<kBF16S>, grid, block, 0, s, M, N, K, A, sar, sak, B, sbn, sbk, bias,
-                       act, C, ldc, Z, ldz, gate, dM);
+                       act, C, ldc, Z, ldz, gate, dM, Csplit, plane);
   else
     hipLaunchKernelGGL(k_gemm<kBF16>, grid, block, 0, s, M, N, K, A, sar, sak, B, sbn, sbk, bias,
-                       act, C, ldc, Z, ldz, gate, dM);
+                       act, C, ldc, Z, ldz, gate, dM, Csplit, plane);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Dense layer on split-bfloat16 activations (the emulator's layers 2..L):
+//   C = act( (A_hi + A_mid + A_lo) W + b ),  W given transposed as bfloat16
+//   Wt[N][K], activations as three bfloat16 planes [M][K] (K contiguous).
+// Each wave computes a 32 x 32 block as 2 x 2 v_mfma_f32_16x16x32_bf16 tiles;
+// operand fragments (8 consecutive k of one row / column) are 16-byte loads
+// from L2, double-buffered in registers.  For every k-step of 32 the lo, mid
+// and hi products are accumulated in that order, as in k_gemm<kBF16S>.
+// Output: FP32 rows (C) or again three bfloat16 planes (Csplit).
+// Requires K % 32 == 0 and M >= 1.
+__global__ void __launch_bounds__(256)
+k_dense_split(int M, int N, int K, const __bf16* __restrict__ A, long aplane, const __bf16* __restrict__ Wt,
+              const float* __restrict__ bias, int act, float* __restrict__ C, __bf16* __restrict__ Csplit,
+              long cplane, const int* __restrict__ gate, const int* __restrict__ dM) {
+  if (gate && *gate == 0) return;
+  if (dM) M = min(M, *dM);
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  if (m0 >= M) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rq = m0 + (wave >> 1) * 32, cq = n0 + (wave & 1) * 32;
+  const int fr = lane & 15, fk = 8 * (lane >> 4);
+  // row / column of each fragment (clamped rows are computed and discarded)
+  const __bf16* ap[2];
+  const __bf16* bp[2];
+  for (int t = 0; t < 2; ++t) {
+    const int r = min(rq + t * 16 + fr, M - 1);
+    ap[t] = A + static_cast<long>(r) * K + fk;
+    const int cidx = min(cq + t * 16 + fr, N - 1);
+    bp[t] = Wt + static_cast<long>(cidx) * K + fk;
+  }
+  f32x4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int jx = 0; jx < 2; ++jx) acc[i][jx] = f32x4{0.f, 0.f, 0.f, 0.f};
+  bf16x8 a_cur[2][3], b_cur[2], a_nxt[2][3], b_nxt[2];
+  for (int t = 0; t < 2; ++t) {
+    for (int sp = 0; sp < 3; ++sp) a_cur[t][sp] = *reinterpret_cast<const bf16x8*>(ap[t] + sp * aplane);
+    b_cur[t] = *reinterpret_cast<const bf16x8*>(bp[t]);
+  }
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const bool more = k0 + 32 < K;
+    if (more) {
+      for (int t = 0; t < 2; ++t) {
+        for (int sp = 0; sp < 3; ++sp)
+          a_nxt[t][sp] = *reinterpret_cast<const bf16x8*>(ap[t] + sp * aplane + k0 + 32);
+        b_nxt[t] = *reinterpret_cast<const bf16x8*>(bp[t] + k0 + 32);
+      }
+    }
+    for (int tm = 0; tm < 2; ++tm)
+      for (int tn = 0; tn < 2; ++tn) {
+        acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_cur[tm][2], b_cur[tn], acc[tm][tn], 0, 0, 0);
+        acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_cur[tm][1], b_cur[tn], acc[tm][tn], 0, 0, 0);
+        acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_cur[tm][0], b_cur[tn], acc[tm][tn], 0, 0, 0);
+      }
+    if (more) {
+      for (int t = 0; t < 2; ++t) {
+        for (int sp = 0; sp < 3; ++sp) a_cur[t][sp] = a_nxt[t][sp];
+        b_cur[t] = b_nxt[t];
+      }
+    }
+  }
+  for (int tm = 0; tm < 2; ++tm)
+    for (int tn = 0; tn < 2; ++tn)
+      for (int i = 0; i < 4; ++i) {
+        const int r = rq + tm * 16 + 4 * (lane >> 4) + i;
+        const int n = cq + tn * 16 + (lane & 15);
+        if (r >= M || n >= N) continue;
+        const float h = act_fwd(act, acc[tm][tn][i] + (bias ? bias[n] : 0.f));
+        if (Csplit) store_split(Csplit, cplane, static_cast<long>(r) * N + n, h);
+        else C[static_cast<long>(r) * N + n] = h;
+      }
+}
+
+hipError_t launch_dense_split(int M, int N, int K, const __bf16* A, long aplane, const __bf16* Wt,
+                              const float* bias, int act, float* C, __bf16* Csplit, long cplane,
+                              const int* gate, const int* dM, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const dim3 grid((N + 63) / 64, (M + 63) / 64), block(256);
+  hipLaunchKernelGGL(k_dense_split, grid, block, 0, s, M, N, K, A, aplane, Wt, bias, act, C, Csplit, cplane,
+                     gate, dM);
   return hipGetLastError();
 }
 
@@ -247,6 +344,30 @@ namespace ns {
 
 hipError_t net_forward(const NetDev& net, int mode_first, int mode_rest, int M, const float* X,
                        float* H0, float* H1, float* Y, const int* gate, hipStream_t s, const int* dM) {
+  bool split = mode_rest == kBF16S && net.n_layers > 1;
+  for (int l = 1; l < net.n_layers; ++l) split = split && net.Wb[l] != nullptr;
+  if (split) {
+    // first layer in FP32 written as split planes, then split-activation MFMA layers
+    const long plane = static_cast<long>(M) * net.max_width;
+    __bf16* P0 = reinterpret_cast<__bf16*>(H0);
+    __bf16* P1 = reinterpret_cast<__bf16*>(H1);
+    hipError_t e = launch_gemm(mode_first, M, net.widths[1], net.widths[0], X, net.widths[0], 1, net.Wt[0],
+                               net.w_rowmajor ? 1 : net.widths[0], net.w_rowmajor ? net.widths[1] : 1,
+                               net.b[0], net.n_layers > 1 ? net.act : kActNone, nullptr, net.widths[1],
+                               nullptr, 0, gate, s, dM, net.n_layers > 1 ? P0 : nullptr, plane);
+    if (e != hipSuccess || net.n_layers == 1) return e;
+    __bf16* in = P0;
+    __bf16* out = P1;
+    for (int l = 1; l < net.n_layers; ++l) {
+      const bool last = (l == net.n_layers - 1);
+      e = launch_dense_split(M, net.widths[l + 1], net.widths[l], in, plane, net.Wb[l], net.b[l],
+                             last ? kActNone : net.act, last ? Y : nullptr, last ? nullptr : out, plane,
+                             gate, dM, s);
+      if (e != hipSuccess) return e;
+      std::swap(in, out);
+    }
+    return hipSuccess;
+  }
   const float* in = X;
   long ldin = net.widths[0];
   for (int l = 0; l < net.n_layers; ++l) {

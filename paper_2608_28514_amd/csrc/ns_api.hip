@@ -598,6 +598,11 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
       off_b += Nn;
       NS_INIT_TRY(upload(c, wt.data(), wt.size(), &net.Wt[l]));
       NS_INIT_TRY(upload(c, bb.data(), bb.size(), &net.b[l]));
+      if (lik->prec == NS_BF16X3 && l >= 1 && K % 32 == 0) {
+        std::vector<__bf16> wb(wt.size());
+        for (size_t q = 0; q < wt.size(); ++q) wb[q] = static_cast<__bf16>(wt[q]);
+        NS_INIT_TRY(upload(c, wb.data(), wb.size(), &net.Wb[l]));
+      }
     }
     const int nout = lik->widths[lik->n_layers];
     std::vector<double> isig(nout);
@@ -673,8 +678,9 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
     NS_INIT_HIP(dalloc(&rb.gate, rb.gate_cap));
     NS_INIT_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_gate), sizeof(int), hipHostMallocDefault));
     if (c->is_mlp) {
-      NS_INIT_HIP(dalloc(&rb.H0, static_cast<size_t>(rb.rows_cap) * c->net.max_width));
-      NS_INIT_HIP(dalloc(&rb.H1, static_cast<size_t>(rb.rows_cap) * c->net.max_width));
+      // hidden activations: FP32, or three bfloat16 planes (1.5x) on the split path
+      NS_INIT_HIP(dalloc(&rb.H0, static_cast<size_t>(rb.rows_cap) * c->net.max_width * 3 / 2 + 64));
+      NS_INIT_HIP(dalloc(&rb.H1, static_cast<size_t>(rb.rows_cap) * c->net.max_width * 3 / 2 + 64));
       NS_INIT_HIP(dalloc(&rb.Y, static_cast<size_t>(rb.rows_cap) * c->net.widths[c->net.n_layers]));
       NS_INIT_HIP(dalloc(&rb.rthr, rb.rows_cap));
       NS_INIT_HIP(dalloc(&rb.sflag, rb.rows_cap));

@@ -10,10 +10,15 @@ enum GemmMode : int { kF32 = 0, kBF16S = 1, kBF16 = 2 };
 enum Act : int { kActNone = 0, kActTanh = 1, kActSilu = 2 };
 
 // dM (may be null): device-side row count; rows at or beyond it are skipped.
+// Csplit (may be null): write act(z) as three bfloat16 planes of `plane`
+// elements (hi, mid, lo) instead of FP32 C.
 hipError_t launch_gemm(int mode, int M, int N, int K, const float* A, long sar, long sak,
                        const float* B, long sbn, long sbk, const float* bias, int act, float* C,
                        long ldc, float* Z, long ldz, const int* gate, hipStream_t s,
-                       const int* dM = nullptr);
+                       const int* dM = nullptr, __bf16* Csplit = nullptr, long plane = 0);
+hipError_t launch_dense_split(int M, int N, int K, const __bf16* A, long aplane, const __bf16* Wt,
+                              const float* bias, int act, float* C, __bf16* Csplit, long cplane,
+                              const int* gate, const int* dM, hipStream_t s);
 hipError_t launch_act_bwd(long n, int act, const float* Z, const float* dH, float* dZ, hipStream_t s);
 hipError_t launch_colsum(int M, int N, const float* dZ, float* db, hipStream_t s);
 hipError_t launch_chi2(int M, int N, const float* Y, const double* data, const double* isig,
@@ -31,11 +36,14 @@ struct NetDev {
   const float* b[8];
   int max_width;
   int w_rowmajor;
+  const __bf16* Wb[8];  // bfloat16 copies of Wt (layers >= 1) for the split-activation path
 };
 
 // Forward over M rows of X (M x widths[0]); H0/H1 ping-pong buffers of
 // M x max_width floats; output Y (M x widths[L]).  mode_first applies to
-// layer 0, mode_rest to the others.
+// layer 0, mode_rest to the others.  With mode_rest == kBF16S and bfloat16
+// weights present, hidden activations travel as three bfloat16 planes
+// (3 M max_width bf16 = 1.5x the FP32 buffer: H0/H1 must hold that much).
 hipError_t net_forward(const NetDev& net, int mode_first, int mode_rest, int M, const float* X,
                        float* H0, float* H1, float* Y, const int* gate, hipStream_t s,
                        const int* dM = nullptr);
