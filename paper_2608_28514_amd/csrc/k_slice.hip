@@ -1,8 +1,9 @@
 // k_slice.hip -- constrained slice sampling of the m chains of one batch
 // (Sec. 2.2, with the batch thresholds of Sec. 3.1 / Algorithm 2).
 //
-// One wavefront per chain.  The chain's point, direction and Cholesky factor
-// live in LDS; the 64 lanes evaluate the likelihood speculatively:
+// One wavefront per chain.  Every lane holds the chain's point and direction
+// in registers (coordinate loops unrolled to a compile-time bound on d); the
+// Cholesky factor lives in LDS; the 64 lanes evaluate the likelihood speculatively:
 //  * stepping out: lanes 0-31 test the left offsets a0 - k w, lanes 32-63 the
 //    right offsets b0 + k w, k = 32r .. 32r+31, in one round; a ballot finds
 //    the first offset that leaves the slice {L > L_W[0]} (or the box);
@@ -25,13 +26,78 @@
 namespace ns {
 
 constexpr int kShrinkSpec = 16;
-constexpr int kShrinkPre = 32;  // shrink uniforms drawn in the per-iteration pass
+constexpr int kShrinkPre = 32;  // shrink uniforms drawn ahead per iteration
+constexpr int kDrawExtra = 1 + kShrinkPre;  // draw block: d direction entries, a0, U_0..U_31
 
-template <typename T, typename LT>
+template <typename LT>
+struct BoxOf;
+template <>
+struct BoxOf<double> {
+  __device__ static double lo(const LikDev& P, int i) { return P.lo[i]; }
+  __device__ static double span(const LikDev& P, int i) { return P.span[i]; }
+};
+template <>
+struct BoxOf<float> {
+  __device__ static float lo(const LikDev& P, int i) { return P.lo_f[i]; }
+  __device__ static float span(const LikDev& P, int i) { return P.span_f[i]; }
+};
+
+// Draws of every (chain, iteration) of the batch, formed ahead of the
+// sampling kernel: they depend only on their counters and on the chain's
+// Cholesky factor, which stay fixed during the batch.  One wave per (chain j,
+// iteration it) writes the block
+//   [ v_0 .. v_{d-1} | a0 | U_0 .. U_31 ]   (kDrawExtra + d values of T)
+// with v the whitened unit direction, a0 = -w u the left bracket offset and U
+// the first shrink uniforms.  The arithmetic is the one the sampling loop
+// would do in place, so the chains are unchanged.
+template <typename T>
+__global__ void __launch_bounds__(64)
+k_slice_draws(SliceParams p, int d, const T* __restrict__ chol, const int* __restrict__ label,
+              const int* __restrict__ seeds, T* __restrict__ draws, const RunState* __restrict__ st) {
+  if (st->done) return;
+  const int j = blockIdx.x, it = blockIdx.y;
+  const int lane = threadIdx.x;
+  const uint32_t step = static_cast<uint32_t>(st->step);
+  const uint32_t c3 = (kStreamSlice << 24) | static_cast<uint32_t>(it);
+  const int BW = d + kDrawExtra;
+  T* blk = draws + (static_cast<long>(j) * p.n_iter + it) * BW;
+  const T w = static_cast<T>(p.w);
+  __shared__ T zs[kMaxD];
+  if (lane < 16) {
+    if (2 * lane < d) {
+      const Draw2 dr = uniform2(p.seed, kSlotDir0 + lane, static_cast<uint32_t>(j), step, c3);
+      const T r = DirMath<T>::r_of(static_cast<T>(dr.a));
+      const T ang = static_cast<T>(6.283185307179586) * static_cast<T>(dr.b);
+      T sn, cs;
+      DirMath<T>::sc(ang, &sn, &cs);
+      zs[2 * lane] = r * cs;
+      if (2 * lane + 1 < d) zs[2 * lane + 1] = r * sn;
+    }
+  } else if (lane == 16) {
+    const Draw2 d0 = uniform2(p.seed, kSlotStepout, static_cast<uint32_t>(j), step, c3);
+    blk[d] = -w * static_cast<T>(d0.a);
+  } else if (lane >= 32 && lane - 32 < p.max_shrink) {
+    const Draw2 du = uniform2(p.seed, kSlotShrink0 + (lane - 32), static_cast<uint32_t>(j), step, c3);
+    blk[d + 1 + (lane - 32)] = static_cast<T>(du.a);
+  }
+  __syncthreads();
+  // isotropic direction, whitened by the cluster's Cholesky factor
+  if (lane < d) {
+    T nrm = T(0);
+    for (int i = 0; i < d; ++i) nrm += zs[i] * zs[i];
+    nrm = DirMath<T>::sq(nrm);
+    const T* Lr = chol + static_cast<long>(label[seeds[j]]) * kMaxD * kMaxD + lane * kMaxD;
+    T acc = T(0);
+    for (int k = 0; k <= lane; ++k) acc += Lr[k] * (zs[k] / nrm);
+    blk[lane] = acc;
+  }
+}
+
+template <typename T, typename LT, int DM>
 __global__ void __launch_bounds__(64)
 k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
-        const double* __restrict__ logL, const int* __restrict__ label,
-        const T* __restrict__ chol, const int* __restrict__ seeds, const double* __restrict__ tau,
+        const double* __restrict__ logL, const T* __restrict__ draws,
+        const int* __restrict__ seeds, const double* __restrict__ tau,
         const double* __restrict__ LW, T* __restrict__ new_u, double* __restrict__ new_logL,
         int* __restrict__ chain_stat, double* __restrict__ hist_logL, T* __restrict__ hist_u,
         int* __restrict__ hist_n, const RunState* __restrict__ st) {
@@ -41,18 +107,26 @@ k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
   const int m = p.m;
   const uint32_t step = static_cast<uint32_t>(st->step);
 
-  __shared__ T xs[kMaxD];
-  __shared__ T vs[kMaxD];
-  __shared__ T zs[kMaxD];
-  __shared__ T Ls[kMaxD * kMaxD];
-  __shared__ T Us[kShrinkPre + kShrinkSpec];
-  __shared__ T s_a0;
+  __shared__ T blk[kMaxD + kDrawExtra];        // this iteration's draw block
+  __shared__ T Us[kShrinkSpec];                 // shrink uniforms drawn on demand
   __shared__ T br[2];
+  __shared__ LT s_box[2 * kMaxD];
 
+  // chain point and direction: every lane holds all coordinates
+  T x[DM], v[DM];
   const int s = seeds[j];
-  if (lane < d) xs[lane] = u[static_cast<long>(s) * d + lane];
-  const T* Lc = chol + static_cast<long>(label[s]) * kMaxD * kMaxD;
-  for (int q = lane; q < d * kMaxD; q += 64) Ls[q] = Lc[q];
+  const T* xs0 = u + static_cast<long>(s) * d;
+#pragma unroll
+  for (int i = 0; i < DM; ++i) { x[i] = i < d ? xs0[i] : T(0); v[i] = T(0); }
+  const int BW = d + kDrawExtra;
+  const T* gblk = draws + static_cast<long>(j) * p.n_iter * BW;
+  // the draw block of the next iteration is loaded one iteration ahead
+  T pre0 = lane < BW ? gblk[lane] : T(0);
+  T pre1 = lane + 64 < BW ? gblk[lane + 64] : T(0);
+  if (lane < d) {
+    s_box[2 * lane] = BoxOf<LT>::lo(lik, lane);
+    s_box[2 * lane + 1] = BoxOf<LT>::span(lik, lane);
+  }
   double lx = logL[s];
   const double tau_j = tau[j];
   const double tau_e = LW[0];
@@ -64,38 +138,21 @@ k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
   for (int it = 0; it < n_iter; ++it) {
     const uint32_t c3 = (kStreamSlice << 24) | static_cast<uint32_t>(it);
     const bool last = (it == n_iter - 1);
-    // ---- all draws of the iteration in one pass
-    if (lane < 16) {
-      if (2 * lane < d) {
-        const Draw2 dr = uniform2(p.seed, kSlotDir0 + lane, static_cast<uint32_t>(j), step, c3);
-        const T r = DirMath<T>::r_of(static_cast<T>(dr.a));
-        const T ang = static_cast<T>(6.283185307179586) * static_cast<T>(dr.b);
-        T sn, cs;
-        DirMath<T>::sc(ang, &sn, &cs);
-        zs[2 * lane] = r * cs;
-        if (2 * lane + 1 < d) zs[2 * lane + 1] = r * sn;
-      }
-    } else if (lane == 16) {
-      const Draw2 d0 = uniform2(p.seed, kSlotStepout, static_cast<uint32_t>(j), step, c3);
-      s_a0 = -w * static_cast<T>(d0.a);
-    } else if (lane >= 32 && lane - 32 < p.max_shrink) {
-      const Draw2 du = uniform2(p.seed, kSlotShrink0 + (lane - 32), static_cast<uint32_t>(j), step, c3);
-      Us[lane - 32] = static_cast<T>(du.a);
-    }
+    // ---- this iteration's direction, bracket offset and shrink uniforms
+    if (lane < BW) blk[lane] = pre0;
+    if (lane + 64 < BW) blk[lane + 64] = pre1;
     __syncthreads();
-    // ---- isotropic direction, whitened by the cluster's Cholesky factor
-    T nrm = T(0);
-    for (int i = 0; i < d; ++i) nrm += zs[i] * zs[i];
-    nrm = DirMath<T>::sq(nrm);
-    if (lane < d) {
-      T acc = T(0);
-      for (int k = 0; k <= lane; ++k) acc += Ls[lane * kMaxD + k] * (zs[k] / nrm);
-      vs[lane] = acc;
+    if (it + 1 < n_iter) {
+      const T* nb = gblk + static_cast<long>(it + 1) * BW;
+      if (lane < BW) pre0 = nb[lane];
+      if (lane + 64 < BW) pre1 = nb[lane + 64];
     }
-    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < DM; ++i)
+      if (i < d) v[i] = blk[i];
 
     // ---- stepping out against the batch-worst threshold L_W[0]
-    const T a0 = s_a0;
+    const T a0 = blk[d];
     const T b0 = a0 + w;
     int ka = -1, kb = -1;
     for (int base = 0; ka < 0 || kb < 0; base += 32) {
@@ -105,8 +162,8 @@ k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
       bool pass = false, oob = false;
       if (active) {
         const T off = left ? a0 - static_cast<T>(k) * w : b0 + static_cast<T>(k) * w;
-        if (line_in_box(xs, vs, off, d))
-          pass = clean_logL(LikAt<LT>::eval(lik, LineAt<T>{xs, vs, off})) > tau_e;
+        if (reg_line_in_box<T, DM>(x, v, off, d))
+          pass = clean_logL(LikAt<LT>::template eval_theta<DM>(lik, RegLineTheta<T, LT, DM>{x, v, off, s_box})) > tau_e;
         else
           oob = true;
       }
@@ -138,15 +195,15 @@ k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
     bool accepted = false;
     for (int s0 = 0; s0 < p.max_shrink && !accepted; s0 += kShrinkSpec) {
       const int S = min(kShrinkSpec, p.max_shrink - s0);
-      const T* U = Us + s0;
+      const T* U = blk + d + 1 + s0;
       if (s0 + kShrinkSpec > kShrinkPre) {
         // beyond the pre-drawn uniforms: draw this round's on demand
         if (lane < S) {
           const Draw2 du = uniform2(p.seed, kSlotShrink0 + s0 + lane, static_cast<uint32_t>(j), step, c3);
-          Us[kShrinkPre + lane] = static_cast<T>(du.a);
+          Us[lane] = static_cast<T>(du.a);
         }
         __syncthreads();
-        U = Us + kShrinkPre;
+        U = Us;
       }
       bool pass = false, inb = false;
       T aa = a, bb = b, t = T(0);
@@ -159,8 +216,8 @@ k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
             if (t < T(0)) aa = t; else bb = t;
           }
         }
-        inb = line_in_box(xs, vs, t, d);
-        if (inb) l = clean_logL(LikAt<LT>::eval(lik, LineAt<T>{xs, vs, t}));
+        inb = reg_line_in_box<T, DM>(x, v, t, d);
+        if (inb) l = clean_logL(LikAt<LT>::template eval_theta<DM>(lik, RegLineTheta<T, LT, DM>{x, v, t, s_box}));
         pass = l > tau_j;
       }
       const uint64_t mp = __ballot(pass);
@@ -173,30 +230,40 @@ k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
         const int slot = s0 + lane;
         hist_logL[static_cast<long>(slot) * m + j] = l;
         T* hu = hist_u + (static_cast<long>(j) * TH + slot) * d;
-        for (int i = 0; i < d; ++i) hu[i] = xs[i] + t * vs[i];
+#pragma unroll
+        for (int i = 0; i < DM; ++i)
+          if (i < d) hu[i] = x[i] + t * v[i];
       }
       if (last) hn = min(s0 + upto + 1, TH - 1);
       if (mp) {
         accepted = true;
         lx = __shfl(l, upto);
         const T tacc = __shfl(t, upto);
+#pragma unroll
+        for (int i = 0; i < DM; ++i) x[i] = x[i] + tacc * v[i];
+      } else {
+        if (lane == S - 1) {
+          br[0] = aa;
+          br[1] = bb;
+        }
         __syncthreads();
-        if (lane < d) xs[lane] = xs[lane] + tacc * vs[lane];
-      } else if (lane == S - 1) {
-        br[0] = aa;
-        br[1] = bb;
+        a = br[0];
+        b = br[1];
+        __syncthreads();
       }
-      __syncthreads();
-      if (!mp) { a = br[0]; b = br[1]; }
     }
     if (!accepted) n_sh += 1;
     __syncthreads();
   }
 
   // ---- outputs
+  T xo = T(0);
+#pragma unroll
+  for (int i = 0; i < DM; ++i)
+    if (i == lane) xo = x[i];
   if (lane < d) {
-    new_u[static_cast<long>(j) * d + lane] = xs[lane];
-    hist_u[(static_cast<long>(j) * TH + (TH - 1)) * d + lane] = xs[lane];
+    new_u[static_cast<long>(j) * d + lane] = xo;
+    hist_u[(static_cast<long>(j) * TH + (TH - 1)) * d + lane] = xo;
   }
   if (lane == 0) {
     new_logL[j] = lx;
@@ -213,22 +280,44 @@ k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
 hipError_t launch_slice(const Shape& sh, const DevBufs& b, const LikDev& lik, const SliceParams& p,
                         hipStream_t s) {
   const dim3 grid(p.m), block(64);
+  {
+    const dim3 dgrid(p.m, p.n_iter);
+    if (sh.state_f32)
+      hipLaunchKernelGGL(k_slice_draws<float>, dgrid, block, 0, s, p, sh.d, b.chol_f, b.label, b.seeds,
+                         static_cast<float*>(b.draws), b.st);
+    else
+      hipLaunchKernelGGL(k_slice_draws<double>, dgrid, block, 0, s, p, sh.d, b.chol, b.label, b.seeds,
+                         static_cast<double*>(b.draws), b.st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (sh.state_f32) {
-    const float* chol = b.chol_f;
 #define NS_SLICE_ARGS(ST)                                                                        \
-  p, sh.d, sh.T, lik, static_cast<const ST*>(b.u), b.logL, b.label, chol, b.seeds, b.tau, b.LW,  \
+  p, sh.d, sh.T, lik, static_cast<const ST*>(b.u), b.logL, static_cast<const ST*>(b.draws),      \
+      b.seeds, b.tau, b.LW,                                                                        \
       static_cast<ST*>(b.new_u), b.new_logL, b.chain_stat, b.hist_logL, static_cast<ST*>(b.hist_u), \
       b.hist_n, b.st
+#define NS_SLICE_DM(ST, LT)                                                                       \
+  do {                                                                                            \
+    if (sh.d <= 4)                                                                                \
+      hipLaunchKernelGGL((k_slice<ST, LT, 4>), grid, block, 0, s, NS_SLICE_ARGS(ST));             \
+    else if (sh.d <= 8)                                                                           \
+      hipLaunchKernelGGL((k_slice<ST, LT, 8>), grid, block, 0, s, NS_SLICE_ARGS(ST));             \
+    else if (sh.d <= 16)                                                                          \
+      hipLaunchKernelGGL((k_slice<ST, LT, 16>), grid, block, 0, s, NS_SLICE_ARGS(ST));            \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_slice<ST, LT, 32>), grid, block, 0, s, NS_SLICE_ARGS(ST));            \
+  } while (0)
     if (sh.lik_f32)
-      hipLaunchKernelGGL((k_slice<float, float>), grid, block, 0, s, NS_SLICE_ARGS(float));
+      NS_SLICE_DM(float, float);
     else
-      hipLaunchKernelGGL((k_slice<float, double>), grid, block, 0, s, NS_SLICE_ARGS(float));
+      NS_SLICE_DM(float, double);
   } else {
-    const double* chol = b.chol;
     if (sh.lik_f32)
-      hipLaunchKernelGGL((k_slice<double, float>), grid, block, 0, s, NS_SLICE_ARGS(double));
+      NS_SLICE_DM(double, float);
     else
-      hipLaunchKernelGGL((k_slice<double, double>), grid, block, 0, s, NS_SLICE_ARGS(double));
+      NS_SLICE_DM(double, double);
+#undef NS_SLICE_DM
 #undef NS_SLICE_ARGS
   }
   return hipGetLastError();

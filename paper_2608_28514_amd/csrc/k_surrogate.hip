@@ -122,7 +122,9 @@ k_scatter(int d, const int* __restrict__ count, const int* __restrict__ idx, con
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    sc->pairs = base + n;
+    // pairs counts the rows written to the ring (none before the ring exists),
+    // so slots [0, min(pairs, cap)) always hold data
+    if (cap > 0) sc->pairs = base + n;
     sc->emu_rows += n;
     sc->audited += s_aud;
     sc->false_screens += s_fn;

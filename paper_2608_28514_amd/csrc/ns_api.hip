@@ -167,7 +167,7 @@ static ns_status alloc_batch(ns_ctx* c, int M) {
   DevBufs& b = c->b;
   const int d = c->sh.d, T = c->sh.T;
   hfree(b.seeds); hfree(b.tau); hfree(b.LW); hfree(b.new_u); hfree(b.new_logL);
-  hfree(b.chain_stat); hfree(b.hist_logL); hfree(b.hist_u); hfree(b.hist_n);
+  hfree(b.chain_stat); hfree(b.hist_logL); hfree(b.hist_u); hfree(b.hist_n); hfree(b.draws);
   const size_t sb = state_bytes(c);
   NS_TRY(dalloc(&b.seeds, M));
   NS_TRY(dalloc(&b.tau, M));
@@ -178,6 +178,9 @@ static ns_status alloc_batch(ns_ctx* c, int M) {
   NS_TRY(dalloc(&b.hist_logL, static_cast<size_t>(T) * M));
   NS_TRY(hipMalloc(&b.hist_u, sb * static_cast<size_t>(M) * T * d));
   NS_TRY(dalloc(&b.hist_n, M));
+  // draw blocks of the fused slice kernel: M chains x n_iter iterations x (d + 33)
+  const size_t n_iter = static_cast<size_t>(c->cfg.slice_steps_per_dim) * d;
+  NS_TRY(hipMalloc(&b.draws, sb * static_cast<size_t>(M) * n_iter * (d + 33)));
   c->M = M;
   return NS_OK;
 }
@@ -208,7 +211,7 @@ static ns_status grow_dead(ns_ctx* c, long need) {
 static void free_all(ns_ctx* c) {
   DevBufs& b = c->b;
   void* ptrs[] = {b.u, b.logL, b.label, b.order, b.seeds, b.tau, b.LW, b.new_u, b.new_logL,
-                  b.chain_stat, b.hist_logL, b.hist_u, b.hist_n, b.nodeof, b.members, b.count,
+                  b.chain_stat, b.hist_logL, b.hist_u, b.hist_n, b.draws, b.uT, b.nodeof, b.count,
                   b.accepted, b.split_ok, b.logV, b.logV_eff, b.centre, b.cov, b.chol, b.chol_f,
                   b.dead_u, b.dead_logL, b.st, c->d_out3, c->rb.cs, c->rb.pts, c->rb.xin,
                   c->rb.flag, c->rb.rlogL, c->rb.gate, c->rb.H0, c->rb.H1, c->rb.Y, c->rb.rthr,
@@ -622,11 +625,11 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
   const size_t sb = sh.state_f32 ? 4 : 8;
   const size_t N = n_live;
   NS_INIT_HIP(hipMalloc(&b.u, sb * N * d));
+  NS_INIT_HIP(hipMalloc(&b.uT, sb * N * d));
   NS_INIT_HIP(dalloc(&b.logL, N));
   NS_INIT_HIP(dalloc(&b.label, N));
   NS_INIT_HIP(dalloc(&b.order, N));
   NS_INIT_HIP(dalloc(&b.nodeof, N));
-  NS_INIT_HIP(dalloc(&b.members, N * sh.nodes));
   NS_INIT_HIP(dalloc(&b.count, sh.nodes));
   NS_INIT_HIP(dalloc(&b.accepted, sh.nodes));
   NS_INIT_HIP(dalloc(&b.split_ok, sh.nodes));
@@ -644,6 +647,7 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
   NS_INIT_TRY(grow_dead(c, 4096));
   // zero tree buffers once (cov entries beyond d stay zero)
   NS_INIT_HIP(hipMemsetAsync(b.cov, 0, sizeof(double) * sh.nodes * kMaxD * kMaxD, c->stream));
+  NS_INIT_HIP(hipMemsetAsync(b.nodeof, 0, sizeof(int) * N, c->stream));
   NS_INIT_HIP(hipMemsetAsync(b.centre, 0, sizeof(double) * sh.nodes * kMaxD, c->stream));
   RunState s0{};
   s0.logZ = -INFINITY;

@@ -74,31 +74,63 @@ struct LikDev {
 // Analytic families, in the likelihood precision LT (double or float).  The
 // point is read through an accessor y(i) returning unit-cube coordinate i
 // (already known to lie in the box); theta_i = lo_i + span_i y_i is formed on
-// the fly so no per-lane array is materialised.
+// the fly so no per-lane array is materialised (eval_theta takes an accessor
+// that returns theta_i itself, formed the same way).  Coordinate loops run to the
+// compile-time bound DM (>= d) and are unrolled, so an accessor over register
+// arrays is indexed with constants.
 template <typename LT>
 struct LikAt;
 
+// theta_i = lo_i + span_i y_i from a unit-cube accessor and the box of P.
+template <typename LT, typename Y>
+struct UnitTheta;
+template <typename Y>
+struct UnitTheta<double, Y> {
+  const LikDev& P;
+  Y y;
+  __device__ __forceinline__ double operator()(int i) const {
+    return P.lo[i] + P.span[i] * static_cast<double>(y(i));
+  }
+};
+template <typename Y>
+struct UnitTheta<float, Y> {
+  const LikDev& P;
+  Y y;
+  __device__ __forceinline__ float operator()(int i) const {
+    return P.lo_f[i] + P.span_f[i] * static_cast<float>(y(i));
+  }
+};
+
 template <>
 struct LikAt<double> {
-  template <typename Y>
-  __device__ static double eval(const LikDev& P, Y y) {
+  template <int DM = kMaxD, typename Y>
+  __device__ __forceinline__ static double eval(const LikDev& P, Y y) {
+    return eval_theta<DM>(P, UnitTheta<double, Y>{P, y});
+  }
+  // th(i) returns theta_i in double
+  template <int DM, typename TH>
+  __device__ __forceinline__ static double eval_theta(const LikDev& P, TH th) {
     const int d = P.d;
     if (P.kind == kMixture) {
       if (P.n_comp == 1) {
         double q = 0.0;
-        for (int i = 0; i < d; ++i) {
-          const double r = (P.lo[i] + P.span[i] * static_cast<double>(y(i))) - P.mu[i];
-          q += r * r * P.ivar[i];
-        }
+#pragma unroll
+        for (int i = 0; i < DM; ++i)
+          if (i < d) {
+            const double r = th(i) - P.mu[i];
+            q += r * r * P.ivar[i];
+          }
         return P.logw[0] - 0.5 * q;
       }
       double best = -INFINITY;
       for (int k = 0; k < P.n_comp; ++k) {
         double q = 0.0;
-        for (int i = 0; i < d; ++i) {
-          const double r = (P.lo[i] + P.span[i] * static_cast<double>(y(i))) - P.mu[k * d + i];
-          q += r * r * P.ivar[k * d + i];
-        }
+#pragma unroll
+        for (int i = 0; i < DM; ++i)
+          if (i < d) {
+            const double r = th(i) - P.mu[k * d + i];
+            q += r * r * P.ivar[k * d + i];
+          }
         const double e = P.logw[k] - 0.5 * q;
         best = e > best ? e : best;
       }
@@ -106,31 +138,37 @@ struct LikAt<double> {
       double s = 0.0;
       for (int k = 0; k < P.n_comp; ++k) {
         double q = 0.0;
-        for (int i = 0; i < d; ++i) {
-          const double r = (P.lo[i] + P.span[i] * static_cast<double>(y(i))) - P.mu[k * d + i];
-          q += r * r * P.ivar[k * d + i];
-        }
+#pragma unroll
+        for (int i = 0; i < DM; ++i)
+          if (i < d) {
+            const double r = th(i) - P.mu[k * d + i];
+            q += r * r * P.ivar[k * d + i];
+          }
         s += exp((P.logw[k] - 0.5 * q) - best);
       }
       return best + log(s);
     }
     if (P.kind == kRosenbrock) {
       double s = 0.0;
-      double prev = P.lo[0] + P.span[0] * static_cast<double>(y(0));
-      for (int i = 0; i + 1 < d; ++i) {
-        const double next = P.lo[i + 1] + P.span[i + 1] * static_cast<double>(y(i + 1));
-        const double t = next - prev * prev;
-        const double r = P.ros_a - prev;
-        s += P.ros_b * t * t + r * r;
-        prev = next;
-      }
+      double prev = th(0);
+#pragma unroll
+      for (int i = 0; i + 1 < DM; ++i)
+        if (i + 1 < d) {
+          const double next = th(i + 1);
+          const double t = next - prev * prev;
+          const double r = P.ros_a - prev;
+          s += P.ros_b * t * t + r * r;
+          prev = next;
+        }
       return -s;
     }
     double s = 0.0;
-    for (int i = 0; i < d; ++i) {
-      const double th = P.lo[i] + P.span[i] * static_cast<double>(y(i));
-      s += th * th;
-    }
+#pragma unroll
+    for (int i = 0; i < DM; ++i)
+      if (i < d) {
+        const double ti = th(i);
+        s += ti * ti;
+      }
     const double r = (sqrt(s) - P.shell_r0) / P.shell_w;
     return -0.5 * r * r;
   }
@@ -138,25 +176,34 @@ struct LikAt<double> {
 
 template <>
 struct LikAt<float> {
-  template <typename Y>
-  __device__ static double eval(const LikDev& P, Y y) {
+  template <int DM = kMaxD, typename Y>
+  __device__ __forceinline__ static double eval(const LikDev& P, Y y) {
+    return eval_theta<DM>(P, UnitTheta<float, Y>{P, y});
+  }
+  // th(i) returns theta_i in float
+  template <int DM, typename TH>
+  __device__ __forceinline__ static double eval_theta(const LikDev& P, TH th) {
     const int d = P.d;
     if (P.kind == kMixture) {
       if (P.n_comp == 1) {
         float q = 0.0f;
-        for (int i = 0; i < d; ++i) {
-          const float r = (P.lo_f[i] + P.span_f[i] * static_cast<float>(y(i))) - P.mu_f[i];
-          q += r * r * P.ivar_f[i];
-        }
+#pragma unroll
+        for (int i = 0; i < DM; ++i)
+          if (i < d) {
+            const float r = th(i) - P.mu_f[i];
+            q += r * r * P.ivar_f[i];
+          }
         return static_cast<double>(P.logw_f[0] - 0.5f * q);
       }
       float best = -INFINITY;
       for (int k = 0; k < P.n_comp; ++k) {
         float q = 0.0f;
-        for (int i = 0; i < d; ++i) {
-          const float r = (P.lo_f[i] + P.span_f[i] * static_cast<float>(y(i))) - P.mu_f[k * d + i];
-          q += r * r * P.ivar_f[k * d + i];
-        }
+#pragma unroll
+        for (int i = 0; i < DM; ++i)
+          if (i < d) {
+            const float r = th(i) - P.mu_f[k * d + i];
+            q += r * r * P.ivar_f[k * d + i];
+          }
         const float e = P.logw_f[k] - 0.5f * q;
         best = e > best ? e : best;
       }
@@ -164,10 +211,12 @@ struct LikAt<float> {
       float s = 0.0f;
       for (int k = 0; k < P.n_comp; ++k) {
         float q = 0.0f;
-        for (int i = 0; i < d; ++i) {
-          const float r = (P.lo_f[i] + P.span_f[i] * static_cast<float>(y(i))) - P.mu_f[k * d + i];
-          q += r * r * P.ivar_f[k * d + i];
-        }
+#pragma unroll
+        for (int i = 0; i < DM; ++i)
+          if (i < d) {
+            const float r = th(i) - P.mu_f[k * d + i];
+            q += r * r * P.ivar_f[k * d + i];
+          }
         s += expf((P.logw_f[k] - 0.5f * q) - best);
       }
       return static_cast<double>(best + logf(s));
@@ -175,21 +224,25 @@ struct LikAt<float> {
     if (P.kind == kRosenbrock) {
       float s = 0.0f;
       const float a = static_cast<float>(P.ros_a), b = static_cast<float>(P.ros_b);
-      float prev = P.lo_f[0] + P.span_f[0] * static_cast<float>(y(0));
-      for (int i = 0; i + 1 < d; ++i) {
-        const float next = P.lo_f[i + 1] + P.span_f[i + 1] * static_cast<float>(y(i + 1));
-        const float t = next - prev * prev;
-        const float r = a - prev;
-        s += b * t * t + r * r;
-        prev = next;
-      }
+      float prev = th(0);
+#pragma unroll
+      for (int i = 0; i + 1 < DM; ++i)
+        if (i + 1 < d) {
+          const float next = th(i + 1);
+          const float t = next - prev * prev;
+          const float r = a - prev;
+          s += b * t * t + r * r;
+          prev = next;
+        }
       return static_cast<double>(-s);
     }
     float s = 0.0f;
-    for (int i = 0; i < d; ++i) {
-      const float th = P.lo_f[i] + P.span_f[i] * static_cast<float>(y(i));
-      s += th * th;
-    }
+#pragma unroll
+    for (int i = 0; i < DM; ++i)
+      if (i < d) {
+        const float ti = th(i);
+        s += ti * ti;
+      }
     const float r = (sqrtf(s) - static_cast<float>(P.shell_r0)) / static_cast<float>(P.shell_w);
     return static_cast<double>(-0.5f * r * r);
   }
@@ -215,6 +268,30 @@ struct LineAt {
   T t;
   __device__ T operator()(int i) const { return x[i] + t * v[i]; }
 };
+// theta_i = lo_i + span_i (x_i + t v_i) over per-lane register arrays
+// (constant indices after unrolling); the box (lo_i, span_i) pairs are read
+// from LDS, so they occupy neither scalar nor vector registers.
+template <typename T, typename LT, int DM>
+struct RegLineTheta {
+  const T (&x)[DM];
+  const T (&v)[DM];
+  T t;
+  const LT* box;   // LDS: lo_0, span_0, lo_1, span_1, ...
+  __device__ __forceinline__ LT operator()(int i) const {
+    return box[2 * i] + box[2 * i + 1] * static_cast<LT>(x[i] + t * v[i]);
+  }
+};
+template <typename T, int DM>
+__device__ __forceinline__ bool reg_line_in_box(const T (&x)[DM], const T (&v)[DM], T t, int d) {
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < DM; ++i)
+    if (i < d) {
+      const T yi = x[i] + t * v[i];
+      ok = ok && (yi >= T(0) && yi <= T(1));
+    }
+  return ok;
+}
 template <typename T>
 __device__ __forceinline__ bool line_in_box(const T* x, const T* v, T t, int d) {
   bool ok = true;

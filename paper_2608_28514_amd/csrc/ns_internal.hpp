@@ -22,9 +22,10 @@ struct DevBufs {
   double* hist_logL;    // T x M (row t, column chain)
   void* hist_u;         // M x T x d
   int* hist_n;          // M
+  void* draws;          // M x n_iter x (d + 33): per-iteration draw blocks of the slice kernel
   // cluster tree
+  void* uT;             // d x N transposed copy of u (cluster passes)
   int* nodeof;          // N: deepest tree node of each point
-  int* members;         // nodes x N scratch
   int* count;           // nodes
   int* accepted;        // nodes
   int* split_ok;        // nodes

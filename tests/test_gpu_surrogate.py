@@ -58,14 +58,26 @@ def _small_emulator():
     return W.emulator(seed=3, widths=(5, 32, 32, 32, 16), noise_frac=0.05)
 
 
+def _dirty_device_memory(mib=512):
+    """Fill a block of device memory with NaN and hand it back to the driver,
+    so that buffers allocated next are likely to start as NaN: a kernel that
+    reads a slot nobody wrote then shows up as a non-finite result."""
+    x = torch.full((mib << 18,), float("nan"), dtype=torch.float32, device=DEV)
+    torch.cuda.synchronize()
+    del x
+    torch.cuda.empty_cache()
+
+
 def test_screened_sampler_matches_plain_and_saves_evaluations():
     spec = _small_emulator()
     plain, scr = [], []
     stats = []
     for seed in range(3):
+        _dirty_device_memory()
         s = native.Sampler(spec, 200, prec="f32", state="f32", seed=seed, tree_depth=1)
         s.run(20)
         plain.append((s.logZ(), s.stats()))
+        _dirty_device_memory()
         t = native.Sampler(spec, 200, prec="f32", state="f32", seed=seed, tree_depth=1)
         t.enable_surrogate(hidden=64, batch=512, train_iters=10, min_pairs=4096, replay_cap=32768,
                            margin=3.0, floor_below=20.0, prec="f32")
@@ -115,3 +127,27 @@ def test_surrogate_training_reduces_loss_and_predicts():
     # minibatch error in nats is below half the margin)
     span = live["logL"].max() - live["logL"].min()
     assert np.median(np.abs(err)) < 0.25 * span
+
+
+def test_surrogate_enabled_mid_run_trains_on_written_pairs_only():
+    """Rows evaluated before the surrogate exists are not in the replay ring:
+    the ring count starts at zero when it is enabled, and training on it
+    stays finite even when its memory starts as NaN."""
+    spec = _small_emulator()
+    _dirty_device_memory()
+    t = native.Sampler(spec, 200, prec="f32", state="f32", seed=11, tree_depth=1)
+    t.step(20)
+    t.step(20)
+    rows_before = t.stats()["net_rows"]
+    assert rows_before > 0
+    _dirty_device_memory()
+    t.enable_surrogate(hidden=32, batch=256, train_iters=4, min_pairs=1024, replay_cap=8192,
+                       margin=3.0, floor_below=20.0, prec="f32")
+    assert t.surrogate_stats()["pairs"] == 0
+    for _ in range(6):
+        t.step(20)
+    st = t.surrogate_stats()
+    print("mid-run surrogate:", st, "rows before", rows_before)
+    assert st["train_calls"] > 0
+    assert math.isfinite(st["last_loss"])
+    assert st["pairs"] == t.stats()["net_rows"] - rows_before
