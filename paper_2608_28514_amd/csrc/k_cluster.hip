@@ -108,15 +108,14 @@ __device__ __forceinline__ double sqdist_lds(const T* pts, int cs, int r, const 
 
 // One node per workgroup: ordered gather, mean, unbiased covariance, and
 // above the last level the 2-means split.  The member list, the side of each
-// member and the member points (in coordinate-major chunks loaded from the
-// transposed copy uT, d x N) stay in LDS; a node that fits in one chunk is
-// loaded once.  Distance and covariance passes take one point per lane;
+// member and the member points (in coordinate-major chunks) stay in LDS; a
+// node that fits in one chunk is loaded once.  Distance and covariance passes take one point per lane;
 // coordinate sums take one coordinate per lane over groups of P lanes, so a
 // thread carries two accumulators whatever d is.
 template <typename T, int P>
 __global__ void __launch_bounds__(kCT)
 k_cluster_level(int level, int depth, int N, int d, int iters, const T* __restrict__ u,
-                const T* __restrict__ uT, int* __restrict__ nodeof, int* __restrict__ count,
+                int* __restrict__ nodeof, int* __restrict__ count,
                 double* __restrict__ centre, double* __restrict__ cov, const RunState* __restrict__ st) {
   if (st->done) return;
   constexpr int G = kCT / P;                   // point groups of the sum passes
@@ -161,11 +160,13 @@ k_cluster_level(int level, int depth, int N, int d, int iters, const T* __restri
   const int nchunk = (cnt + cs - 1) / cs;
   const bool resident = nchunk == 1;
   // chunk ch -> pts; returns its point count
+  // consecutive threads read consecutive coordinates of a member's row
   auto load_chunk = [&](int ch) -> int {
     const int r0 = ch * cs, n = min(cs, cnt - r0);
-    for (int i = 0; i < d; ++i)
-      for (int rl = threadIdx.x; rl < n; rl += kCT)
-        pts[i * cs + rl] = uT[static_cast<long>(i) * N + s_mem[r0 + rl]];
+    for (int e = threadIdx.x; e < n * d; e += kCT) {
+      const int rl = e / d, i = e - rl * d;
+      pts[i * cs + rl] = u[static_cast<long>(s_mem[r0 + rl]) * d + i];
+    }
     return n;
   };
   if (resident) {
@@ -179,6 +180,7 @@ k_cluster_level(int level, int depth, int N, int d, int iters, const T* __restri
       int n = cnt;
       if (!resident) { __syncthreads(); n = load_chunk(ch); __syncthreads(); }
       if (c < d)
+#pragma unroll 8
         for (int rl = g; rl < n; rl += G) sa += static_cast<double>(pts[c * cs + rl]);
     }
     group_reduce2<P>(sa, sb, red);
@@ -214,6 +216,7 @@ k_cluster_level(int level, int depth, int N, int d, int iters, const T* __restri
       int n = cnt;
       if (!resident) { __syncthreads(); n = load_chunk(ch); __syncthreads(); }
       if (blk < NB)
+#pragma unroll 2
         for (int rl = gc; rl < n; rl += GC) {
           double xi[4], xj[4];
 #pragma unroll
@@ -295,6 +298,7 @@ k_cluster_level(int level, int depth, int N, int d, int iters, const T* __restri
       }
       __syncthreads();
       if (c < d)
+#pragma unroll 8
         for (int rl = g; rl < n; rl += G) {
           const double x = static_cast<double>(pts[c * cs + rl]);
           if (s_side[r0 + rl]) sb += x; else sa += x;
@@ -566,38 +570,13 @@ k_cluster_prune(int nodes, int depth, int N, double log_keep, int nmin, const in
   }
 }
 
-// uT[i N + k] = u[k d + i]
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_transpose_points(int N, int d, const T* __restrict__ u, T* __restrict__ uT,
-                   const RunState* __restrict__ st) {
-  if (st->done) return;
-  const long e = static_cast<long>(blockIdx.x) * 256 + threadIdx.x;
-  if (e >= static_cast<long>(N) * d) return;
-  const long k = e / d, i = e % d;
-  uT[i * N + k] = u[e];
-}
-
 hipError_t launch_cluster(const Shape& sh, const DevBufs& b, double p, int nmin, int iters,
                           double eps, hipStream_t s) {
-  {
-    const long n = static_cast<long>(sh.N) * sh.d;
-    const dim3 grid(static_cast<unsigned>((n + 255) / 256)), block(256);
-    if (sh.state_f32)
-      hipLaunchKernelGGL(k_transpose_points<float>, grid, block, 0, s, sh.N, sh.d,
-                         static_cast<const float*>(b.u), static_cast<float*>(b.uT), b.st);
-    else
-      hipLaunchKernelGGL(k_transpose_points<double>, grid, block, 0, s, sh.N, sh.d,
-                         static_cast<const double*>(b.u), static_cast<double*>(b.uT), b.st);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
   for (int level = 0; level <= sh.depth; ++level) {
     const dim3 grid(1u << level), block(kCT);
 #define NS_LEVEL(T, DM)                                                                        \
   hipLaunchKernelGGL((k_cluster_level<T, DM>), grid, block, 0, s, level, sh.depth, sh.N, sh.d,  \
-                     iters, static_cast<const T*>(b.u), static_cast<const T*>(b.uT), b.nodeof,     \
-                     b.count, b.centre, b.cov, b.st)
+                     iters, static_cast<const T*>(b.u), b.nodeof, b.count, b.centre, b.cov, b.st)
     if (sh.state_f32) {
       if (sh.d <= 4) NS_LEVEL(float, 4); else if (sh.d <= 8) NS_LEVEL(float, 8);
       else if (sh.d <= 16) NS_LEVEL(float, 16); else NS_LEVEL(float, 32);

@@ -25,7 +25,7 @@ struct CorrLds {
   int tmpi[kMaxC];
   int list[kMaxC];
   double listv[kMaxC];
-  double red[kCorrT];
+  double red[16 * 8];
   int wave_tot[16];
   int s_total;
 };
@@ -59,21 +59,22 @@ __device__ void rank_sort(CorrLds& S, int n) {
     S.rank[q] = r;
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < n; q += blockDim.x) S.tmpd[S.rank[q]] = S.logL[q];
+  // scatter every field to its rank (list / listv serve as scratch here),
+  // then copy back
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    const int r = S.rank[q];
+    S.tmpd[r] = S.logL[q];
+    S.listv[r] = S.P[q];
+    S.tmpi[r] = S.code[q];
+    S.list[r] = S.hslot[q];
+  }
   __syncthreads();
-  for (int q = threadIdx.x; q < n; q += blockDim.x) S.logL[q] = S.tmpd[q];
-  __syncthreads();
-  for (int q = threadIdx.x; q < n; q += blockDim.x) S.tmpd[S.rank[q]] = S.P[q];
-  __syncthreads();
-  for (int q = threadIdx.x; q < n; q += blockDim.x) S.P[q] = S.tmpd[q];
-  __syncthreads();
-  for (int q = threadIdx.x; q < n; q += blockDim.x) S.tmpi[S.rank[q]] = S.code[q];
-  __syncthreads();
-  for (int q = threadIdx.x; q < n; q += blockDim.x) S.code[q] = S.tmpi[q];
-  __syncthreads();
-  for (int q = threadIdx.x; q < n; q += blockDim.x) S.tmpi[S.rank[q]] = S.hslot[q];
-  __syncthreads();
-  for (int q = threadIdx.x; q < n; q += blockDim.x) S.hslot[q] = S.tmpi[q];
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    S.logL[q] = S.tmpd[q];
+    S.P[q] = S.listv[q];
+    S.code[q] = S.tmpi[q];
+    S.hslot[q] = S.list[q];
+  }
   __syncthreads();
 }
 
@@ -148,19 +149,38 @@ k_correct_arrays(int m, int corr, int K, int TH, const double* __restrict__ wlog
   }
 }
 
-__device__ double block_reduce(double v, double* red, bool is_max) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int off = blockDim.x >> 1; off > 0; off >>= 1) {
-    if (threadIdx.x < off) {
-      const double a = red[threadIdx.x], b = red[threadIdx.x + off];
-      red[threadIdx.x] = is_max ? (b > a ? b : a) : a + b;
+// NV sums (or maxima) over the workgroup: xor butterfly inside each wave
+// (every lane ends with the same value, each step combining the same two
+// operands), then the wave results in wave order.  Deterministic.
+template <int NV, bool MAX>
+__device__ void block_reduce_n(double (&v)[NV], double* red /* 16 x NV */) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i)
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(v[i], off);
+      v[i] = MAX ? (o > v[i] ? o : v[i]) : v[i] + o;
     }
-    __syncthreads();
-  }
-  const double r = red[0];
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[wv * NV + i] = v[i];
   __syncthreads();
-  return r;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double t = red[i];
+    for (int q = 1; q < nw; ++q) {
+      const double o = red[q * NV + i];
+      t = MAX ? (o > t ? o : t) : t + o;
+    }
+    v[i] = t;
+  }
+  __syncthreads();
+}
+
+__device__ double block_reduce(double v, double* red, bool is_max) {
+  double a[1] = {v};
+  if (is_max) block_reduce_n<1, true>(a, red); else block_reduce_n<1, false>(a, red);
+  return a[0];
 }
 
 template <typename T>
@@ -172,7 +192,8 @@ k_correct(int m, int corr, int K, int TH, int N, int d, int nodes, double stop_f
           const int* __restrict__ chain_stat, const double* __restrict__ hist_logL,
           const T* __restrict__ hist_u, const int* __restrict__ hist_n,
           const int* __restrict__ accepted, const double* __restrict__ centre,
-          double* __restrict__ dead_u, double* __restrict__ dead_logL, RunState* __restrict__ st) {
+          double* __restrict__ dead_u, double* __restrict__ dead_logL, RunState* __restrict__ st,
+          HostProgress* prog) {
   if (st->done) return;
   __shared__ CorrLds S;
   correct_core(S, m, corr, K, TH, LW, new_logL, tau, hist_logL, hist_n);
@@ -237,40 +258,36 @@ k_correct(int m, int corr, int K, int TH, int N, int d, int nodes, double stop_f
     label[slot] = best;
   }
   __syncthreads();
-  // ---- evidence of the m dead rows
+  // ---- evidence of the m dead rows, with the best live likelihood (stop test)
   const double Nd = static_cast<double>(N);
   const double lw0 = log(-expm1(-1.0 / Nd));
-  double lwq = -INFINITY, lq = 0.0;
-  double mx_local = -INFINITY;
+  double mm[2] = {-INFINITY, -INFINITY};
   for (int q = threadIdx.x; q < m; q += blockDim.x) {
     const double i = static_cast<double>(base_dead + q + 1);
     const double lw = (S.logL[q] - (i - 1.0) / Nd) + lw0;
-    mx_local = lw > mx_local ? lw : mx_local;
+    mm[0] = lw > mm[0] ? lw : mm[0];
   }
-  const double mx = block_reduce(mx_local, S.red, true);
-  double s1 = 0.0, s2 = 0.0;
+  for (int k = threadIdx.x; k < N; k += blockDim.x) mm[1] = logL[k] > mm[1] ? logL[k] : mm[1];
+  block_reduce_n<2, true>(mm, S.red);
+  const double mx = mm[0], lmax = mm[1];
+  // sums: s1, s2 and the five chain counters
+  double sv[7] = {0, 0, 0, 0, 0, 0, 0};
   if (mx > -INFINITY) {
     for (int q = threadIdx.x; q < m; q += blockDim.x) {
       const double i = static_cast<double>(base_dead + q + 1);
-      lwq = (S.logL[q] - (i - 1.0) / Nd) + lw0;
-      lq = S.logL[q];
+      const double lwq = (S.logL[q] - (i - 1.0) / Nd) + lw0;
+      const double lq = S.logL[q];
       if (lwq == -INFINITY) continue;
       const double e = exp(lwq - mx);
-      s1 += e;
-      s2 += lq * e;
+      sv[0] += e;
+      sv[1] += lq * e;
     }
   }
-  s1 = block_reduce(s1, S.red, false);
-  s2 = block_reduce(s2, S.red, false);
-  // ---- stop test needs the best live likelihood
-  double lmax = -INFINITY;
-  for (int k = threadIdx.x; k < N; k += blockDim.x) lmax = logL[k] > lmax ? logL[k] : lmax;
-  lmax = block_reduce(lmax, S.red, true);
-  // ---- counters
-  double ce[5] = {0, 0, 0, 0, 0};
   for (int j = threadIdx.x; j < m; j += blockDim.x)
-    for (int c = 0; c < 5; ++c) ce[c] += static_cast<double>(chain_stat[kStatW * j + c]);
-  for (int c = 0; c < 5; ++c) ce[c] = block_reduce(ce[c], S.red, false);
+    for (int c = 0; c < 5; ++c) sv[2 + c] += static_cast<double>(chain_stat[kStatW * j + c]);
+  block_reduce_n<7, false>(sv, S.red);
+  const double s1 = sv[0], s2 = sv[1];
+  const double* ce = sv + 2;
   if (threadIdx.x == 0) {
     double lz = st->logZ, A = st->A;
     if (mx > -INFINITY) {
@@ -290,7 +307,14 @@ k_correct(int m, int corr, int K, int TH, int N, int d, int nodes, double stop_f
     st->so_caps += static_cast<unsigned long long>(ce[2]);
     st->sh_caps += static_cast<unsigned long long>(ce[3]);
     st->screened += static_cast<unsigned long long>(ce[4]);
-    if (-static_cast<double>(base_dead + m) / Nd + lmax - lz < log(stop_frac)) st->done = 1;
+    const int done = -static_cast<double>(base_dead + m) / Nd + lmax - lz < log(stop_frac);
+    if (done) st->done = 1;
+    if (prog) {
+      volatile HostProgress* hp = prog;
+      hp->step = st->step;
+      hp->done = done;
+      __threadfence_system();
+    }
   }
 }
 
@@ -334,20 +358,26 @@ k_final_logZ(int N, const double* __restrict__ logL, const RunState* __restrict_
   }
 }
 
+// One thread per entry of C (2m), in whole waves, at least two waves.
+static int corr_threads(int m) {
+  const int t = ((2 * m + 63) / 64) * 64;
+  return t < 128 ? 128 : (t > kCorrT ? kCorrT : t);
+}
+
 hipError_t launch_correct(const Shape& sh, const DevBufs& b, int m, int corr, int K,
                           double stop_frac, hipStream_t s) {
   if (sh.state_f32)
-    hipLaunchKernelGGL(k_correct<float>, dim3(1), dim3(kCorrT), 0, s, m, corr, K, sh.T, sh.N, sh.d,
+    hipLaunchKernelGGL(k_correct<float>, dim3(1), dim3(corr_threads(m)), 0, s, m, corr, K, sh.T, sh.N, sh.d,
                        sh.nodes, stop_frac, static_cast<float*>(b.u), b.logL, b.label, b.order, b.LW,
                        b.tau, static_cast<const float*>(b.new_u), b.new_logL, b.chain_stat,
                        b.hist_logL, static_cast<const float*>(b.hist_u), b.hist_n, b.accepted,
-                       b.centre, b.dead_u, b.dead_logL, b.st);
+                       b.centre, b.dead_u, b.dead_logL, b.st, b.prog);
   else
-    hipLaunchKernelGGL(k_correct<double>, dim3(1), dim3(kCorrT), 0, s, m, corr, K, sh.T, sh.N, sh.d,
+    hipLaunchKernelGGL(k_correct<double>, dim3(1), dim3(corr_threads(m)), 0, s, m, corr, K, sh.T, sh.N, sh.d,
                        sh.nodes, stop_frac, static_cast<double*>(b.u), b.logL, b.label, b.order, b.LW,
                        b.tau, static_cast<const double*>(b.new_u), b.new_logL, b.chain_stat,
                        b.hist_logL, static_cast<const double*>(b.hist_u), b.hist_n, b.accepted,
-                       b.centre, b.dead_u, b.dead_logL, b.st);
+                       b.centre, b.dead_u, b.dead_logL, b.st, b.prog);
   return hipGetLastError();
 }
 
@@ -355,7 +385,7 @@ hipError_t launch_correct_arrays(int m, int corr, int K, int T, const double* wl
                                  const double* nlogL, const double* P, const double* hist,
                                  const int* hist_n, int* acc_code, int* acc_hslot, double* acc_logL,
                                  int* rej_code, int* rej_hslot, double* rej_logL, hipStream_t s) {
-  hipLaunchKernelGGL(k_correct_arrays, dim3(1), dim3(kCorrT), 0, s, m, corr, K, T, wlogL, nlogL, P,
+  hipLaunchKernelGGL(k_correct_arrays, dim3(1), dim3(corr_threads(m)), 0, s, m, corr, K, T, wlogL, nlogL, P,
                      hist, hist_n, acc_code, acc_hslot, acc_logL, rej_code, rej_hslot, rej_logL);
   return hipGetLastError();
 }

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <string>
 #include <vector>
+#include <thread>
 #include "../../include/ns.h"
 #include "ns_internal.hpp"
 #include "ns_gemm.hpp"
@@ -34,6 +35,8 @@ struct ns_ctx {
   RunState* h_st = nullptr;   // pinned
   hipEvent_t poll_ev = nullptr;
   bool poll_pending = false;
+  HostProgress* h_prog = nullptr;  // coherent pinned, written by the device
+  int64_t issued = 0;              // steps enqueued (device step count when in sync)
   bool known_done = false;
   double* d_out3 = nullptr;
   // likelihood parameter arrays (device)
@@ -77,7 +80,7 @@ struct ns_ctx {
   double s_rmse = 0.0;
   std::string err;
   // optional per-kernel-class timing with events on the context's stream
-  bool timing = false;
+  int timing = 0;        // bitmask of timed classes
   struct Pending { int cls; hipEvent_t a, b; };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> ev_pool;
@@ -116,13 +119,13 @@ struct TimeScope {
   int cls;
   hipEvent_t a = nullptr;
   TimeScope(ns_ctx* c_, int cls_) : c(c_), cls(cls_) {
-    if (c->timing) {
+    if ((c->timing >> cls) & 1) {
       a = take_event(c);
       if (a) (void)hipEventRecord(a, c->stream);
     }
   }
   ~TimeScope() {
-    if (c->timing && a) {
+    if (a) {
       hipEvent_t b = take_event(c);
       if (b) {
         (void)hipEventRecord(b, c->stream);
@@ -211,7 +214,7 @@ static ns_status grow_dead(ns_ctx* c, long need) {
 static void free_all(ns_ctx* c) {
   DevBufs& b = c->b;
   void* ptrs[] = {b.u, b.logL, b.label, b.order, b.seeds, b.tau, b.LW, b.new_u, b.new_logL,
-                  b.chain_stat, b.hist_logL, b.hist_u, b.hist_n, b.draws, b.uT, b.nodeof, b.count,
+                  b.chain_stat, b.hist_logL, b.hist_u, b.hist_n, b.draws, b.nodeof, b.count,
                   b.accepted, b.split_ok, b.logV, b.logV_eff, b.centre, b.cov, b.chol, b.chol_f,
                   b.dead_u, b.dead_logL, b.st, c->d_out3, c->rb.cs, c->rb.pts, c->rb.xin,
                   c->rb.flag, c->rb.rlogL, c->rb.gate, c->rb.H0, c->rb.H1, c->rb.Y, c->rb.rthr,
@@ -222,6 +225,7 @@ static void free_all(ns_ctx* c) {
   for (void* p : ptrs) hfree(p);
   for (void* p : c->lik_bufs) hfree(p);
   if (c->h_st) (void)hipHostFree(c->h_st);
+  if (c->h_prog) (void)hipHostFree(c->h_prog);
   if (c->h_gate) (void)hipHostFree(c->h_gate);
   if (c->h_sc) (void)hipHostFree(c->h_sc);
   if (c->poll_ev) (void)hipEventDestroy(c->poll_ev);
@@ -625,7 +629,6 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
   const size_t sb = sh.state_f32 ? 4 : 8;
   const size_t N = n_live;
   NS_INIT_HIP(hipMalloc(&b.u, sb * N * d));
-  NS_INIT_HIP(hipMalloc(&b.uT, sb * N * d));
   NS_INIT_HIP(dalloc(&b.logL, N));
   NS_INIT_HIP(dalloc(&b.label, N));
   NS_INIT_HIP(dalloc(&b.order, N));
@@ -643,6 +646,21 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
   NS_INIT_HIP(dalloc(&c->d_out3, 3));
   NS_INIT_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_st), sizeof(RunState), hipHostMallocDefault));
   NS_INIT_HIP(hipEventCreateWithFlags(&c->poll_ev, hipEventDisableTiming));
+  // progress word: without a mapped coherent host allocation the host falls
+  // back to copying the run state
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_prog), sizeof(HostProgress),
+                    hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess) {
+    c->h_prog->step = 0;
+    c->h_prog->done = 0;
+    if (hipHostGetDevicePointer(reinterpret_cast<void**>(&b.prog), c->h_prog, 0) != hipSuccess) {
+      (void)hipHostFree(c->h_prog);
+      c->h_prog = nullptr;
+      b.prog = nullptr;
+    }
+  } else {
+    c->h_prog = nullptr;
+    (void)hipGetLastError();
+  }
   NS_INIT_TRY(alloc_batch(c, 16));
   NS_INIT_TRY(grow_dead(c, 4096));
   // zero tree buffers once (cov entries beyond d stay zero)
@@ -716,7 +734,22 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
   return NS_OK;
 }
 
+// Steps the host may enqueue ahead of the device.
+constexpr int64_t kStepsAhead = 8;
+
+// Follow the device after enqueueing a step: read the progress word (no
+// stream operation) and wait while more than kStepsAhead steps are in flight,
+// so that few empty steps are enqueued once the stopping rule fires.  Without
+// the progress word, copy the run state behind an event.
 static void poll(ns_ctx* c) {
+  if (c->h_prog) {
+    volatile HostProgress* hp = c->h_prog;
+    for (;;) {
+      if (hp->done) { c->known_done = true; return; }
+      if (c->issued - hp->step <= kStepsAhead) return;
+      std::this_thread::yield();
+    }
+  }
   if (c->poll_pending) {
     if (hipEventQuery(c->poll_ev) == hipSuccess) {
       c->poll_pending = false;
@@ -779,6 +812,7 @@ ns_status ns_step_batch(ns_ctx* c, int m) {
   c->since_cluster += m;
   c->dead_ub += m;
   c->last_m = m;
+  c->issued += 1;
   if (c->surr) {
     ns_status r = surr_after_step(c);
     if (r != NS_OK) return r;
@@ -793,14 +827,21 @@ ns_status ns_sync(ns_ctx* c) {
   drain_timing(c);
   NS_TRY(hipMemcpy(c->h_st, c->b.st, sizeof(RunState), hipMemcpyDeviceToHost));
   c->poll_pending = false;
+  c->issued = c->h_st->step;
+  if (c->h_prog) {
+    c->h_prog->step = c->h_st->step;
+    c->h_prog->done = c->h_st->done;
+  }
   if (c->h_st->done) c->known_done = true;
   return NS_OK;
 }
 
 ns_status ns_run(ns_ctx* c, int m, int64_t max_steps, int64_t* steps) {
   if (!c) return NS_EINVAL;
-  NS_TRY(hipStreamSynchronize(c->stream));
-  NS_TRY(hipMemcpy(c->h_st, c->b.st, sizeof(RunState), hipMemcpyDeviceToHost));
+  {
+    ns_status r = ns_sync(c);
+    if (r != NS_OK) return r;
+  }
   const int64_t s0 = c->h_st->step;
   c->known_done = c->h_st->done != 0;
   for (int64_t k = 0; k < max_steps && !c->known_done; ++k) {
@@ -1024,11 +1065,11 @@ ns_status ns_philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32
   return NS_OK;
 }
 
-ns_status ns_set_timing(ns_ctx* c, int on) {
+ns_status ns_set_timing(ns_ctx* c, int mask) {
   if (!c) return NS_EINVAL;
   ns_status r = ns_sync(c);
   if (r != NS_OK) return r;
-  c->timing = on != 0;
+  c->timing = mask & NS_TIMING_ALL;
   for (int k = 0; k < NS_TIMING_CLASSES; ++k) { c->t_ms[k] = 0.0; c->t_n[k] = 0; }
   return NS_OK;
 }

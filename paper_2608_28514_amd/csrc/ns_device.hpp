@@ -344,6 +344,14 @@ struct RunState {
   unsigned long long evals, oob, so_caps, sh_caps, nan_logL, clusterings, screened;
 };
 
+// Progress word in coherent pinned host memory, written by the last kernel of
+// every step so the host can follow the run without stream operations.
+struct HostProgress {
+  int64_t step;
+  int32_t done;
+  int32_t pad;
+};
+
 __device__ __forceinline__ double logaddexp(double a, double b) {
   if (a == -INFINITY) return b;
   if (b == -INFINITY) return a;

@@ -24,7 +24,6 @@ struct DevBufs {
   int* hist_n;          // M
   void* draws;          // M x n_iter x (d + 33): per-iteration draw blocks of the slice kernel
   // cluster tree
-  void* uT;             // d x N transposed copy of u (cluster passes)
   int* nodeof;          // N: deepest tree node of each point
   int* count;           // nodes
   int* accepted;        // nodes
@@ -39,6 +38,7 @@ struct DevBufs {
   double* dead_u;       // cap x d
   double* dead_logL;    // cap
   RunState* st;
+  HostProgress* prog;   // device view of the host progress word (may be null)
 };
 
 constexpr int kStatW = 8;  // ints per chain in chain_stat

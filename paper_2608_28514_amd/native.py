@@ -311,8 +311,13 @@ def ns_philox(seed, c0, c1, c2, c3, n, d_out, stream=None):
 TIMING_CLASSES = ("select", "slice", "correct", "cluster", "lik")
 
 
+TIMING_ALL = 0x1F
+
+
 def ns_set_timing(ctx, on=True):
-    _check(lib().ns_set_timing(ctx, 1 if on else 0), ctx, "ns_set_timing")
+    """on: True (every class), False (none), or a bitmask of 1 << class index."""
+    mask = TIMING_ALL if on is True else (0 if on is False else int(on))
+    _check(lib().ns_set_timing(ctx, mask), ctx, "ns_set_timing")
 
 
 def ns_get_timing(ctx):
