@@ -217,7 +217,10 @@ __global__ void k_loglike_points(int d, LikDev lik, const double* __restrict__ u
   if (k >= n) return;
   const CvtAt<T> y{u + k * d};
   bool ok = true;
-  for (int i = 0; i < d; ++i) ok = ok && (y(i) >= T(0) && y(i) <= T(1));
+  for (int i = 0; i < d; ++i) {
+    const T yi = y(i);
+    ok &= (yi >= T(0)) & (yi <= T(1));
+  }
   out[k] = ok ? clean_logL(LikAt<LT>::eval(lik, y)) : -INFINITY;
 }
 

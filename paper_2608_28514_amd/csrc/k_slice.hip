@@ -93,15 +93,19 @@ k_slice_draws(SliceParams p, int d, const T* __restrict__ chol, const int* __res
   }
 }
 
-template <typename T, typename LT, int DM>
+template <typename T, typename LT, int DM, bool EXACT>
 __global__ void __launch_bounds__(64)
-k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
+k_slice(SliceParams p, int d_arg, int TH, LikDev lik, const T* __restrict__ u,
         const double* __restrict__ logL, const T* __restrict__ draws,
         const int* __restrict__ seeds, const double* __restrict__ tau,
         const double* __restrict__ LW, T* __restrict__ new_u, double* __restrict__ new_logL,
         int* __restrict__ chain_stat, double* __restrict__ hist_logL, T* __restrict__ hist_u,
         int* __restrict__ hist_n, const RunState* __restrict__ st) {
   if (st->done) return;
+  // exact instantiations fix the dimension at compile time, so the unrolled
+  // coordinate loops carry no guards (straight-line code the scheduler can
+  // interleave); the others bound it by DM
+  const int d = EXACT ? DM : d_arg;
   const int j = blockIdx.x;
   const int lane = threadIdx.x;
   const int m = p.m;
@@ -109,7 +113,6 @@ k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
 
   __shared__ T blk[kMaxD + kDrawExtra];        // this iteration's draw block
   __shared__ T Us[kShrinkSpec];                 // shrink uniforms drawn on demand
-  __shared__ T br[2];
   __shared__ LT s_box[2 * kMaxD];
 
   // chain point and direction: every lane holds all coordinates
@@ -126,6 +129,13 @@ k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
   if (lane < d) {
     s_box[2 * lane] = BoxOf<LT>::lo(lik, lane);
     s_box[2 * lane + 1] = BoxOf<LT>::span(lik, lane);
+  }
+  __syncthreads();
+  LT blo[DM], bsp[DM];   // the box, in registers
+#pragma unroll
+  for (int i = 0; i < DM; ++i) {
+    blo[i] = i < d ? s_box[2 * i] : LT(0);
+    bsp[i] = i < d ? s_box[2 * i + 1] : LT(0);
   }
   double lx = logL[s];
   const double tau_j = tau[j];
@@ -163,7 +173,7 @@ k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
       if (active) {
         const T off = left ? a0 - static_cast<T>(k) * w : b0 + static_cast<T>(k) * w;
         if (reg_line_in_box<T, DM>(x, v, off, d))
-          pass = clean_logL(LikAt<LT>::template eval_theta<DM>(lik, RegLineTheta<T, LT, DM>{x, v, off, s_box})) > tau_e;
+          pass = clean_logL(LikAt<LT>::template eval_theta<DM, RegLineTheta<T, LT, DM>, EXACT>(lik, RegLineTheta<T, LT, DM>{x, v, off, blo, bsp})) > tau_e;
         else
           oob = true;
       }
@@ -205,19 +215,25 @@ k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
         __syncthreads();
         U = Us;
       }
+      // the rejection recurrence is the same for every lane: run it once on
+      // register copies of the uniforms; lane s takes proposal s, and the
+      // bracket after S rejections is kept for the next round
+      T Ur[kShrinkSpec];
+#pragma unroll
+      for (int q = 0; q < kShrinkSpec; ++q) Ur[q] = U[q];
+      T aa = a, bb = b, t = T(0), aS = a, bS = b;
+#pragma unroll
+      for (int q = 0; q < kShrinkSpec; ++q) {
+        const T tq = aa + Ur[q] * (bb - aa);
+        if (tq < T(0)) aa = tq; else bb = tq;
+        if (q == lane) t = tq;
+        if (q == S - 1) { aS = aa; bS = bb; }
+      }
       bool pass = false, inb = false;
-      T aa = a, bb = b, t = T(0);
       double l = -INFINITY;
       if (lane < S) {
-#pragma unroll
-        for (int q = 0; q < kShrinkSpec; ++q) {
-          if (q <= lane) {
-            t = aa + U[q] * (bb - aa);
-            if (t < T(0)) aa = t; else bb = t;
-          }
-        }
         inb = reg_line_in_box<T, DM>(x, v, t, d);
-        if (inb) l = clean_logL(LikAt<LT>::template eval_theta<DM>(lik, RegLineTheta<T, LT, DM>{x, v, t, s_box}));
+        if (inb) l = clean_logL(LikAt<LT>::template eval_theta<DM, RegLineTheta<T, LT, DM>, EXACT>(lik, RegLineTheta<T, LT, DM>{x, v, t, blo, bsp}));
         pass = l > tau_j;
       }
       const uint64_t mp = __ballot(pass);
@@ -242,14 +258,8 @@ k_slice(SliceParams p, int d, int TH, LikDev lik, const T* __restrict__ u,
 #pragma unroll
         for (int i = 0; i < DM; ++i) x[i] = x[i] + tacc * v[i];
       } else {
-        if (lane == S - 1) {
-          br[0] = aa;
-          br[1] = bb;
-        }
-        __syncthreads();
-        a = br[0];
-        b = br[1];
-        __syncthreads();
+        a = aS;
+        b = bS;
       }
     }
     if (!accepted) n_sh += 1;
@@ -297,16 +307,21 @@ hipError_t launch_slice(const Shape& sh, const DevBufs& b, const LikDev& lik, co
       b.seeds, b.tau, b.LW,                                                                        \
       static_cast<ST*>(b.new_u), b.new_logL, b.chain_stat, b.hist_logL, static_cast<ST*>(b.hist_u), \
       b.hist_n, b.st
-#define NS_SLICE_DM(ST, LT)                                                                       \
-  do {                                                                                            \
-    if (sh.d <= 4)                                                                                \
-      hipLaunchKernelGGL((k_slice<ST, LT, 4>), grid, block, 0, s, NS_SLICE_ARGS(ST));             \
-    else if (sh.d <= 8)                                                                           \
-      hipLaunchKernelGGL((k_slice<ST, LT, 8>), grid, block, 0, s, NS_SLICE_ARGS(ST));             \
-    else if (sh.d <= 16)                                                                          \
-      hipLaunchKernelGGL((k_slice<ST, LT, 16>), grid, block, 0, s, NS_SLICE_ARGS(ST));            \
-    else                                                                                          \
-      hipLaunchKernelGGL((k_slice<ST, LT, 32>), grid, block, 0, s, NS_SLICE_ARGS(ST));            \
+#define NS_SLICE_K(ST, LT, DM, EX) \
+  hipLaunchKernelGGL((k_slice<ST, LT, DM, EX>), grid, block, 0, s, NS_SLICE_ARGS(ST))
+#define NS_SLICE_DM(ST, LT)                                             \
+  do {                                                                  \
+    switch (sh.d) {                                                     \
+      case 2: NS_SLICE_K(ST, LT, 2, true); break;                       \
+      case 3: NS_SLICE_K(ST, LT, 3, true); break;                       \
+      case 5: NS_SLICE_K(ST, LT, 5, true); break;                       \
+      case 10: NS_SLICE_K(ST, LT, 10, true); break;                     \
+      default:                                                          \
+        if (sh.d <= 4) NS_SLICE_K(ST, LT, 4, false);                    \
+        else if (sh.d <= 8) NS_SLICE_K(ST, LT, 8, false);               \
+        else if (sh.d <= 16) NS_SLICE_K(ST, LT, 16, false);             \
+        else NS_SLICE_K(ST, LT, 32, false);                             \
+    }                                                                   \
   } while (0)
     if (sh.lik_f32)
       NS_SLICE_DM(float, float);
@@ -318,6 +333,7 @@ hipError_t launch_slice(const Shape& sh, const DevBufs& b, const LikDev& lik, co
     else
       NS_SLICE_DM(double, double);
 #undef NS_SLICE_DM
+#undef NS_SLICE_K
 #undef NS_SLICE_ARGS
   }
   return hipGetLastError();

@@ -107,10 +107,10 @@ struct LikAt<double> {
   __device__ __forceinline__ static double eval(const LikDev& P, Y y) {
     return eval_theta<DM>(P, UnitTheta<double, Y>{P, y});
   }
-  // th(i) returns theta_i in double
-  template <int DM, typename TH>
+  // th(i) returns theta_i in double; EXACT: the dimension is DM itself
+  template <int DM, typename TH, bool EXACT = false>
   __device__ __forceinline__ static double eval_theta(const LikDev& P, TH th) {
-    const int d = P.d;
+    const int d = EXACT ? DM : P.d;
     if (P.kind == kMixture) {
       if (P.n_comp == 1) {
         double q = 0.0;
@@ -180,10 +180,10 @@ struct LikAt<float> {
   __device__ __forceinline__ static double eval(const LikDev& P, Y y) {
     return eval_theta<DM>(P, UnitTheta<float, Y>{P, y});
   }
-  // th(i) returns theta_i in float
-  template <int DM, typename TH>
+  // th(i) returns theta_i in float; EXACT: the dimension is DM itself
+  template <int DM, typename TH, bool EXACT = false>
   __device__ __forceinline__ static double eval_theta(const LikDev& P, TH th) {
-    const int d = P.d;
+    const int d = EXACT ? DM : P.d;
     if (P.kind == kMixture) {
       if (P.n_comp == 1) {
         float q = 0.0f;
@@ -248,10 +248,11 @@ struct LikAt<float> {
   }
 };
 
+// Box tests combine the comparisons with & (no short-circuit branches).
 template <typename T>
 __device__ __forceinline__ bool in_box(const T* y, int d) {
   bool ok = true;
-  for (int i = 0; i < d; ++i) ok = ok && (y[i] >= T(0) && y[i] <= T(1));
+  for (int i = 0; i < d; ++i) ok &= (y[i] >= T(0)) & (y[i] <= T(1));
   return ok;
 }
 
@@ -269,26 +270,27 @@ struct LineAt {
   __device__ T operator()(int i) const { return x[i] + t * v[i]; }
 };
 // theta_i = lo_i + span_i (x_i + t v_i) over per-lane register arrays
-// (constant indices after unrolling); the box (lo_i, span_i) pairs are read
-// from LDS, so they occupy neither scalar nor vector registers.
+// (constant indices after unrolling), the box included.
 template <typename T, typename LT, int DM>
 struct RegLineTheta {
   const T (&x)[DM];
   const T (&v)[DM];
   T t;
-  const LT* box;   // LDS: lo_0, span_0, lo_1, span_1, ...
+  const LT (&lo)[DM];
+  const LT (&span)[DM];
   __device__ __forceinline__ LT operator()(int i) const {
-    return box[2 * i] + box[2 * i + 1] * static_cast<LT>(x[i] + t * v[i]);
+    return lo[i] + span[i] * static_cast<LT>(x[i] + t * v[i]);
   }
 };
 template <typename T, int DM>
 __device__ __forceinline__ bool reg_line_in_box(const T (&x)[DM], const T (&v)[DM], T t, int d) {
+  // (d is DM itself in the exact instantiations, and the guards fold away)
   bool ok = true;
 #pragma unroll
   for (int i = 0; i < DM; ++i)
     if (i < d) {
       const T yi = x[i] + t * v[i];
-      ok = ok && (yi >= T(0) && yi <= T(1));
+      ok &= (yi >= T(0)) & (yi <= T(1));
     }
   return ok;
 }
@@ -297,7 +299,7 @@ __device__ __forceinline__ bool line_in_box(const T* x, const T* v, T t, int d) 
   bool ok = true;
   for (int i = 0; i < d; ++i) {
     const T yi = x[i] + t * v[i];
-    ok = ok && (yi >= T(0) && yi <= T(1));
+    ok &= (yi >= T(0)) & (yi <= T(1));
   }
   return ok;
 }

@@ -84,6 +84,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise NsError("libns.so is not built: run __graft_entry__.build() "
                           "(there is no CPU fallback)")
+        # PyTorch first: the library then binds to the HIP runtime torch has
+        # loaded (same soname), so device memory, streams and kernels share
+        # one runtime in the process
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
         sigs = {
