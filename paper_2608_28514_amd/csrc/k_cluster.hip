@@ -112,12 +112,14 @@ __device__ __forceinline__ double sqdist_lds(const T* pts, int cs, int r, const 
 // node that fits in one chunk is loaded once.  Distance and covariance passes take one point per lane;
 // coordinate sums take one coordinate per lane over groups of P lanes, so a
 // thread carries two accumulators whatever d is.
-template <typename T, int P>
+template <typename T, int P, int XD>
 __global__ void __launch_bounds__(kCT)
-k_cluster_level(int level, int depth, int N, int d, int iters, const T* __restrict__ u,
+k_cluster_level(int level, int depth, int N, int d_arg, int iters, const T* __restrict__ u,
                 int* __restrict__ nodeof, int* __restrict__ count,
                 double* __restrict__ centre, double* __restrict__ cov, const RunState* __restrict__ st) {
   if (st->done) return;
+  // XD > 0: the dimension is fixed at compile time (unrolled loops without guards)
+  const int d = XD > 0 ? XD : d_arg;
   constexpr int G = kCT / P;                   // point groups of the sum passes
   const int node = (1 << level) - 1 + blockIdx.x;
   __shared__ int s_mem[kMaxN];
@@ -352,13 +354,21 @@ __device__ void chol_wave(const double* S, double* L, int d, int lane, int* flag
 // 1 / ||L^-1||_2^2 >= 1 / ||L^-1||_F^2, and lambda_max(C) <= trace(C); when
 // 1 / ||L^-1||_F^2 exceeds 2 eps trace(C), every eigenvalue that any backward
 // stable eigen solver returns stays above eps times the largest one.
+//
+// Only the root and nodes with more than n_min points can become clusters (a
+// split is kept only when both children exceed n_min), so with `full` unset
+// the other nodes are skipped and keep their previous factors; `full`
+// regularises every node with at least two points.  st may be null (no
+// early exit).
 __global__ void __launch_bounds__(64)
-k_cluster_regularise(int d, double eps, const int* __restrict__ count, const double* __restrict__ cov,
-                     double* __restrict__ chol, float* __restrict__ chol_f, double* __restrict__ logV,
+k_cluster_regularise(int d, double eps, int nmin, int full, const int* __restrict__ count,
+                     const double* __restrict__ cov, double* __restrict__ chol,
+                     float* __restrict__ chol_f, double* __restrict__ logV,
                      const RunState* __restrict__ st) {
-  if (st->done) return;
+  if (st && st->done) return;
   const int node = blockIdx.x;
   const int lane = threadIdx.x;
+  if (!full && node != 0 && count[node] <= nmin && count[node] >= 2) return;
   __shared__ double a[kMaxD * kMaxD];
   __shared__ double Q[kMaxD * kMaxD];
   __shared__ double S[kMaxD * kMaxD];
@@ -574,27 +584,44 @@ hipError_t launch_cluster(const Shape& sh, const DevBufs& b, double p, int nmin,
                           double eps, hipStream_t s) {
   for (int level = 0; level <= sh.depth; ++level) {
     const dim3 grid(1u << level), block(kCT);
-#define NS_LEVEL(T, DM)                                                                        \
-  hipLaunchKernelGGL((k_cluster_level<T, DM>), grid, block, 0, s, level, sh.depth, sh.N, sh.d,  \
+#define NS_LEVEL_K(T, DM, XD)                                                                  \
+  hipLaunchKernelGGL((k_cluster_level<T, DM, XD>), grid, block, 0, s, level, sh.depth, sh.N, sh.d, \
                      iters, static_cast<const T*>(b.u), b.nodeof, b.count, b.centre, b.cov, b.st)
+#define NS_LEVEL(T)                                                   \
+  switch (sh.d) {                                                     \
+    case 2: NS_LEVEL_K(T, 4, 2); break;                               \
+    case 3: NS_LEVEL_K(T, 4, 3); break;                               \
+    case 5: NS_LEVEL_K(T, 8, 5); break;                               \
+    case 10: NS_LEVEL_K(T, 16, 10); break;                            \
+    default:                                                          \
+      if (sh.d <= 4) NS_LEVEL_K(T, 4, 0);                             \
+      else if (sh.d <= 8) NS_LEVEL_K(T, 8, 0);                        \
+      else if (sh.d <= 16) NS_LEVEL_K(T, 16, 0);                      \
+      else NS_LEVEL_K(T, 32, 0);                                      \
+  }
     if (sh.state_f32) {
-      if (sh.d <= 4) NS_LEVEL(float, 4); else if (sh.d <= 8) NS_LEVEL(float, 8);
-      else if (sh.d <= 16) NS_LEVEL(float, 16); else NS_LEVEL(float, 32);
+      NS_LEVEL(float);
     } else {
-      if (sh.d <= 4) NS_LEVEL(double, 4); else if (sh.d <= 8) NS_LEVEL(double, 8);
-      else if (sh.d <= 16) NS_LEVEL(double, 16); else NS_LEVEL(double, 32);
+      NS_LEVEL(double);
     }
 #undef NS_LEVEL
+#undef NS_LEVEL_K
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_cluster_regularise, dim3(sh.nodes), dim3(64), 0, s, sh.d, eps, b.count, b.cov,
-                     b.chol, b.chol_f, b.logV, b.st);
+  hipLaunchKernelGGL(k_cluster_regularise, dim3(sh.nodes), dim3(64), 0, s, sh.d, eps, nmin, 0, b.count,
+                     b.cov, b.chol, b.chol_f, b.logV, b.st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_cluster_prune, dim3(1), dim3(256), 0, s, sh.nodes, sh.depth, sh.N,
                      log(1.0 - p), nmin, b.count, b.logV, b.logV_eff, b.split_ok, b.accepted,
                      b.nodeof, b.label, b.st);
+  return hipGetLastError();
+}
+
+hipError_t launch_regularise_all(const Shape& sh, const DevBufs& b, int nmin, double eps, hipStream_t s) {
+  hipLaunchKernelGGL(k_cluster_regularise, dim3(sh.nodes), dim3(64), 0, s, sh.d, eps, nmin, 1, b.count,
+                     b.cov, b.chol, b.chol_f, b.logV, nullptr);
   return hipGetLastError();
 }
 

@@ -37,6 +37,7 @@ struct ns_ctx {
   bool poll_pending = false;
   HostProgress* h_prog = nullptr;  // coherent pinned, written by the device
   int64_t issued = 0;              // steps enqueued (device step count when in sync)
+  bool tree_partial = false;       // nodes that cannot become clusters not regularised
   bool known_done = false;
   double* d_out3 = nullptr;
   // likelihood parameter arrays (device)
@@ -250,6 +251,7 @@ static ns_status enqueue_cluster(ns_ctx* c) {
   NS_TRY(launch_cluster(c->sh, c->b, c->cfg.split_vol_frac, nmin, c->cfg.kmeans_iters,
                         c->cfg.eig_floor, c->stream));
   c->since_cluster = 0;
+  c->tree_partial = true;
   return NS_OK;
 }
 
@@ -928,6 +930,11 @@ ns_status ns_set_live(ns_ctx* c, const double* u, const double* logL, const int*
 ns_status ns_get_tree(ns_ctx* c, int* n_nodes, int* count, int* accepted, int* split_ok,
                       double* logV, double* centre, double* chol) {
   if (!c) return NS_EINVAL;
+  if (c->tree_partial) {
+    // factors of the nodes too small to become clusters are filled in now
+    NS_TRY(launch_regularise_all(c->sh, c->b, c->nmin, c->cfg.eig_floor, c->stream));
+    c->tree_partial = false;
+  }
   ns_status r = ns_sync(c);
   if (r != NS_OK) return r;
   const int nodes = c->sh.nodes, d = c->sh.d;

@@ -77,6 +77,8 @@ hipError_t launch_correct_arrays(int m, int corr, int K, int T, const double* wl
                                  int* rej_code, int* rej_hslot, double* rej_logL, hipStream_t s);
 hipError_t launch_cluster(const Shape& sh, const DevBufs& b, double p, int nmin, int iters,
                           double eps, hipStream_t s);
+// Regularise every node with at least two points (the tree as a whole).
+hipError_t launch_regularise_all(const Shape& sh, const DevBufs& b, int nmin, double eps, hipStream_t s);
 hipError_t launch_final_logZ(const Shape& sh, const DevBufs& b, double* out3, hipStream_t s);
 hipError_t launch_philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, long n,
                          uint32_t* out, hipStream_t s);
