@@ -213,10 +213,19 @@ def bench_emulator(args, np, torch, native, workloads):
         native.ns_sync(s.ctx)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        if args.max_steps:
-            s.run(m, max_steps=args.max_steps)
-        else:
-            s.run(m)
+        # chunks of 100 steps with a progress line each (a full run takes minutes)
+        left = args.max_steps if args.max_steps else None
+        while True:
+            chunk = 100 if left is None else min(100, left)
+            rc, _ = s.run(m, max_steps=chunk)
+            done = rc == native.NS_DONE
+            if left is not None:
+                left -= chunk
+            st_p = s.stats()
+            print(f"[bench] workload {wl} run {k}: {st_p['steps']} steps, {st_p['dead']} dead, "
+                  f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+            if done or (left is not None and left <= 0):
+                break
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         print(f"[bench] workload {wl} run {k} ({'timed' if timed else 'warm-up'}): {t1 - t0:.1f} s",

@@ -52,9 +52,10 @@ __device__ void rank_sort(CorrLds& S, int n) {
   for (int q = threadIdx.x; q < n; q += blockDim.x) {
     const double lq = S.logL[q];
     int r = 0;
+#pragma unroll 8
     for (int p = 0; p < n; ++p) {
       const double lp = S.logL[p];
-      r += (lp < lq) || (lp == lq && p < q);
+      r += static_cast<int>(lp < lq) | static_cast<int>((lp == lq) & (p < q));
     }
     S.rank[q] = r;
   }
@@ -79,17 +80,12 @@ __device__ void rank_sort(CorrLds& S, int n) {
 }
 
 // Build C and apply the correction; afterwards positions [0, m) hold the
-// rejected entries and [m, 2m) the accepted ones.
-__device__ void correct_core(CorrLds& S, int m, int corr, int K, int TH, const double* wlogL,
-                             const double* nlogL, const double* Pn, const double* hist,
+// rejected entries and [m, 2m) the accepted ones.  correct_rest expects C in
+// S (entry q < m: worst point q with P = -1; entry m + j: new point j with
+// its threshold as P) and begins with a barrier.
+__device__ void correct_rest(CorrLds& S, int m, int corr, int K, int TH, const double* hist,
                              const int* hist_n) {
   const int n2 = 2 * m;
-  for (int q = threadIdx.x; q < n2; q += blockDim.x) {
-    if (q < m) { S.logL[q] = canon(wlogL[q]); S.P[q] = -1.0; }
-    else { S.logL[q] = canon(nlogL[q - m]); S.P[q] = Pn[q - m]; }
-    S.code[q] = q;
-    S.hslot[q] = -1;
-  }
   __syncthreads();
   if (corr != kSort && corr != kHistory) return;
   rank_sort(S, n2);
@@ -122,10 +118,18 @@ __device__ void correct_core(CorrLds& S, int m, int corr, int K, int TH, const d
       const int pos = S.list[i];
       const int col = S.code[pos] - m;
       const double thr = S.listv[i];
+      // first history entry above thr; loads issued eight at a time
       int hit = TH - 1;
       const int hn = min(hist_n[col], TH - 1);
-      for (int t = 0; t < hn; ++t)
-        if (hist[static_cast<long>(t) * m + col] > thr) { hit = t; break; }
+      for (int t0 = 0; t0 < hn && hit == TH - 1; t0 += 8) {
+        double hv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          hv[k] = t0 + k < hn ? hist[static_cast<long>(t0 + k) * m + col] : -INFINITY;
+#pragma unroll
+        for (int k = 7; k >= 0; --k)
+          if (hv[k] > thr) hit = t0 + k;
+      }
       S.logL[pos] = canon(hist[static_cast<long>(hit) * m + col]);
       S.hslot[pos] = hit;
       S.P[pos] = thr;
@@ -133,6 +137,18 @@ __device__ void correct_core(CorrLds& S, int m, int corr, int K, int TH, const d
     __syncthreads();
     rank_sort(S, n2);   // re-sort [rejected, accepted]
   }
+}
+
+__device__ void correct_core(CorrLds& S, int m, int corr, int K, int TH, const double* wlogL,
+                             const double* nlogL, const double* Pn, const double* hist,
+                             const int* hist_n) {
+  for (int q = threadIdx.x; q < 2 * m; q += blockDim.x) {
+    if (q < m) { S.logL[q] = canon(wlogL[q]); S.P[q] = -1.0; }
+    else { S.logL[q] = canon(nlogL[q - m]); S.P[q] = Pn[q - m]; }
+    S.code[q] = q;
+    S.hslot[q] = -1;
+  }
+  correct_rest(S, m, corr, K, TH, hist, hist_n);
 }
 
 __global__ void __launch_bounds__(kCorrT)
@@ -196,30 +212,74 @@ k_correct(int m, int corr, int K, int TH, int N, int d, int nodes, double stop_f
           HostProgress* prog) {
   if (st->done) return;
   __shared__ CorrLds S;
-  correct_core(S, m, corr, K, TH, LW, new_logL, tau, hist_logL, hist_n);
-  const long base_dead = st->n_dead;
+  __shared__ int s_order[kMaxC / 2];
+  __shared__ int s_hn[kMaxC / 2];
+  __shared__ int s_accf[kMaxNodes];
+  __shared__ int s_acc[kMaxNodes];
+  __shared__ int s_nacc;
+  __shared__ double s_cen[kMaxNodes * kMaxD];
+  __shared__ long long s_base;
+  __shared__ double s_lz, s_A;
+  // ---- every input of the step in one round of loads (blockDim >= 2m, so a
+  // thread holds at most one entry of W and one of N); the writes to LDS
+  // follow once all loads are in flight
+  const int tq = threadIdx.x;
+  double c_log = 0.0, c_P = -1.0;
+  int c_order = 0, c_hn = 0;
+  double cs[5] = {0, 0, 0, 0, 0};
+  if (tq < m) {
+    c_log = LW[tq];
+    c_order = order[tq];
+    c_hn = hist_n[tq];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) cs[c] = static_cast<double>(chain_stat[kStatW * tq + c]);
+  } else if (tq < 2 * m) {
+    c_log = new_logL[tq - m];
+    c_P = tau[tq - m];
+  }
+  int c_accf = 0;
+  if (tq < nodes) c_accf = accepted[tq];
+  // best live likelihood before the update: the slots the step frees hold
+  // the m worst points, so the new best is max(this, accepted new points)
+  double lmax_old = -INFINITY;
+#pragma unroll 8
+  for (int k = tq; k < N; k += blockDim.x) lmax_old = logL[k] > lmax_old ? logL[k] : lmax_old;
+  for (int e = tq; e < nodes * d; e += blockDim.x) {
+    const int n = e / d, i = e - n * d;
+    s_cen[n * kMaxD + i] = centre[static_cast<long>(n) * kMaxD + i];
+  }
+  if (tq == 0) { s_base = st->n_dead; s_lz = st->logZ; s_A = st->A; }
+  if (tq < 2 * m) {
+    S.logL[tq] = canon(c_log);
+    S.P[tq] = c_P;
+    S.code[tq] = tq;
+    S.hslot[tq] = -1;
+  }
+  // new points beyond one per thread (m > blockDim / 2)
+  for (int q = tq + blockDim.x; q < 2 * m; q += blockDim.x) {
+    S.logL[q] = canon(new_logL[q - m]);
+    S.P[q] = tau[q - m];
+    S.code[q] = q;
+    S.hslot[q] = -1;
+  }
+  if (tq < m) { s_order[tq] = c_order; s_hn[tq] = c_hn; }
+  if (tq < nodes) s_accf[tq] = c_accf;
+  correct_rest(S, m, corr, K, TH, hist_logL, s_hn);
+  const long base_dead = s_base;
   auto src_point = [&](int code, int hs) -> const T* {
-    if (code < m) return u + static_cast<long>(order[code]) * d;
+    if (code < m) return u + static_cast<long>(s_order[code]) * d;
     if (hs < 0) return new_u + static_cast<long>(code - m) * d;
     return hist_u + (static_cast<long>(code - m) * TH + hs) * d;
   };
-  // ---- dead rows (read before any live slot is overwritten)
-  for (int q = threadIdx.x; q < m; q += blockDim.x) {
-    const T* x = src_point(S.code[q], S.hslot[q]);
-    double* o = dead_u + (base_dead + q) * d;
-    for (int i = 0; i < d; ++i) o[i] = static_cast<double>(x[i]);
-    dead_logL[base_dead + q] = S.logL[q];
-  }
-  __syncthreads();
   // ---- rejected worst points in W order, accepted new points in order
-  for (int k = threadIdx.x; k < m; k += blockDim.x) S.tmpi[k] = 0;
+  for (int k = tq; k < m; k += blockDim.x) S.tmpi[k] = 0;
   __syncthreads();
-  for (int q = threadIdx.x; q < m; q += blockDim.x)
+  for (int q = tq; q < m; q += blockDim.x)
     if (S.code[q] < m) S.tmpi[S.code[q]] = 1;
   __syncthreads();
   int nrw = 0;
   for (int b0 = 0; b0 < m; b0 += blockDim.x) {
-    const int k = b0 + threadIdx.x;
+    const int k = b0 + tq;
     const int flag = k < m && S.tmpi[k];
     const int off = scan_flag(flag, S.wave_tot, &S.s_total);
     if (flag) S.list[nrw + off] = k;
@@ -228,36 +288,61 @@ k_correct(int m, int corr, int K, int TH, int N, int d, int nodes, double stop_f
   }
   int nan = 0;
   for (int b0 = 0; b0 < m; b0 += blockDim.x) {
-    const int q = b0 + threadIdx.x;
+    const int q = b0 + tq;
     const int flag = q < m && S.code[m + q] >= m;
     const int off = scan_flag(flag, S.wave_tot, &S.s_total);
     if (flag) S.rank[nan + off] = m + q;
     nan += S.s_total;
     __syncthreads();
   }
-  // nrw == nan: every new point that lives takes the slot of a dead worst point
-  for (int r = threadIdx.x; r < nrw; r += blockDim.x) {
-    const int slot = order[S.list[r]];
-    const int pos = S.rank[r];
+  if (tq == 0) {
+    int na = 0;
+    for (int n = 0; n < nodes; ++n)
+      if (s_accf[n]) s_acc[na++] = n;
+    s_nacc = na;
+  }
+  // ---- dead row q goes to the dead store, and the source of live update q
+  // is read into registers, before the barrier after which live slots are
+  // written (a freed slot can be a dead row's source)
+  T xn[kMaxD];   // constant indices (unrolled loops): registers
+  const bool has_dead = tq < m, has_new = tq < nrw;
+  if (has_new) {
+    const int pos = S.rank[tq];
     const T* x = src_point(S.code[pos], S.hslot[pos]);
+#pragma unroll
+    for (int i = 0; i < kMaxD; ++i) xn[i] = i < d ? x[i] : T(0);
+  }
+  if (has_dead) {
+    const T* x = src_point(S.code[tq], S.hslot[tq]);
+    double* o = dead_u + (base_dead + tq) * d;
+    for (int i = 0; i < d; ++i) o[i] = static_cast<double>(x[i]);
+    dead_logL[base_dead + tq] = S.logL[tq];
+  }
+  __syncthreads();
+  // nrw == nan: every new point that lives takes the slot of a dead worst point
+  if (has_new) {
+    const int slot = s_order[S.list[tq]];
+    const int pos = S.rank[tq];
     T* xv = u + static_cast<long>(slot) * d;
-    for (int i = 0; i < d; ++i) xv[i] = x[i];
+#pragma unroll
+    for (int i = 0; i < kMaxD; ++i)
+      if (i < d) xv[i] = xn[i];
     logL[slot] = S.logL[pos];
     int best = -1;
     double bd = INFINITY;
-    for (int n = 0; n < nodes; ++n) {
-      if (!accepted[n]) continue;
-      const double* c = centre + static_cast<long>(n) * kMaxD;
-      double s = 0.0;
-      for (int i = 0; i < d; ++i) {
-        const double rr = static_cast<double>(xv[i]) - c[i];
-        s += rr * rr;
-      }
-      if (best < 0 || s < bd) { bd = s; best = n; }
+    for (int a = 0; a < s_nacc; ++a) {
+      const double* c = s_cen + s_acc[a] * kMaxD;
+      double sq = 0.0;
+#pragma unroll
+      for (int i = 0; i < kMaxD; ++i)
+        if (i < d) {
+          const double rr = static_cast<double>(xn[i]) - c[i];
+          sq += rr * rr;
+        }
+      if (best < 0 || sq < bd) { bd = sq; best = s_acc[a]; }
     }
     label[slot] = best;
   }
-  __syncthreads();
   // ---- evidence of the m dead rows, with the best live likelihood (stop test)
   const double Nd = static_cast<double>(N);
   const double lw0 = log(-expm1(-1.0 / Nd));
@@ -267,11 +352,13 @@ k_correct(int m, int corr, int K, int TH, int N, int d, int nodes, double stop_f
     const double lw = (S.logL[q] - (i - 1.0) / Nd) + lw0;
     mm[0] = lw > mm[0] ? lw : mm[0];
   }
-  for (int k = threadIdx.x; k < N; k += blockDim.x) mm[1] = logL[k] > mm[1] ? logL[k] : mm[1];
+  mm[1] = lmax_old;
+  for (int q = threadIdx.x; q < m; q += blockDim.x)
+    if (S.code[m + q] >= m) mm[1] = S.logL[m + q] > mm[1] ? S.logL[m + q] : mm[1];
   block_reduce_n<2, true>(mm, S.red);
   const double mx = mm[0], lmax = mm[1];
   // sums: s1, s2 and the five chain counters
-  double sv[7] = {0, 0, 0, 0, 0, 0, 0};
+  double sv[7] = {0, 0, cs[0], cs[1], cs[2], cs[3], cs[4]};
   if (mx > -INFINITY) {
     for (int q = threadIdx.x; q < m; q += blockDim.x) {
       const double i = static_cast<double>(base_dead + q + 1);
@@ -283,13 +370,11 @@ k_correct(int m, int corr, int K, int TH, int N, int d, int nodes, double stop_f
       sv[1] += lq * e;
     }
   }
-  for (int j = threadIdx.x; j < m; j += blockDim.x)
-    for (int c = 0; c < 5; ++c) sv[2 + c] += static_cast<double>(chain_stat[kStatW * j + c]);
   block_reduce_n<7, false>(sv, S.red);
   const double s1 = sv[0], s2 = sv[1];
   const double* ce = sv + 2;
   if (threadIdx.x == 0) {
-    double lz = st->logZ, A = st->A;
+    double lz = s_lz, A = s_A;
     if (mx > -INFINITY) {
       const double Sb = mx + log(s1);
       const double nz = logaddexp(lz, Sb);

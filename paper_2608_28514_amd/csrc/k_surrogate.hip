@@ -39,59 +39,128 @@ __device__ int scan_flag_s(int flag, int* wave_tot, int* total) {
   return off;
 }
 
-__global__ void __launch_bounds__(kST)
-k_screen(int M, int d, int screening, double margin, int audit_period, const int* __restrict__ flag,
-         const double* __restrict__ rthr, const float* __restrict__ yhat, const float* __restrict__ norm,
-         const float* __restrict__ xin, int* __restrict__ sflag, int* __restrict__ idx,
-         int* __restrict__ aud, float* __restrict__ xc, int* __restrict__ count,
-         double* __restrict__ rlogL, SurrCounters* __restrict__ sc, const int* __restrict__ gate) {
+// Row screening and order-preserving compaction in two passes over chunks of
+// kSC rows.  Pass 1 counts, per chunk, the in-box rows and the rows the
+// surrogate places below threshold - margin.  Pass 2 gives every chunk its
+// offsets: the screened rows before it (prefix of the counts), hence its
+// audits in closed form (screened rows whose running index, counted from the
+// rows screened in earlier calls, is a multiple of audit_period), hence the
+// evaluated rows before it; then each chunk writes its rows in order.  The
+// result is the one a single sequential pass gives.
+constexpr int kSC = 256;
+
+__device__ __forceinline__ bool screened_row(int r, int M, int screening, double margin, const int* flag,
+                                             const double* rthr, const float* yhat, float mu, float sd,
+                                             bool* inb) {
+  *inb = r < M && flag[r] != 0;
+  if (!*inb || !screening) return false;
+  const double lhat = static_cast<double>(mu) + static_cast<double>(sd) * static_cast<double>(yhat[r]);
+  return lhat < rthr[r] - margin;
+}
+
+// number of k in [a, a + n) with (base + k) % period == 0
+__device__ __forceinline__ long long audits_in(unsigned long long base, long long a, long long n, long long period) {
+  if (n <= 0) return 0;
+  const unsigned long long lo = base + static_cast<unsigned long long>(a);
+  const unsigned long long hi = lo + static_cast<unsigned long long>(n);   // exclusive
+  const unsigned long long P = static_cast<unsigned long long>(period);
+  return static_cast<long long>((hi + P - 1) / P - (lo + P - 1) / P);
+}
+
+__global__ void __launch_bounds__(kSC)
+k_screen_count(int M, int screening, double margin, const int* __restrict__ flag,
+               const double* __restrict__ rthr, const float* __restrict__ yhat,
+               const float* __restrict__ norm, int* __restrict__ chunk_cnt, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
-  __shared__ int wave_tot[kST / 64];
-  __shared__ int s_total;
-  const float mu = norm[0], sd = norm[1];
-  const unsigned long long sbase = sc->screened_seen;
-  int n_eval = 0, n_scr = 0;
-  for (int base = 0; base < M; base += kST) {
-    const int r = base + threadIdx.x;
-    const bool inb = r < M && flag[r] != 0;
-    bool scr = false;
-    if (inb && screening) {
-      const double lhat = static_cast<double>(mu) + static_cast<double>(sd) * static_cast<double>(yhat[r]);
-      scr = lhat < rthr[r] - margin;
-    }
-    // running index of screened rows decides the audits
-    const int so = scan_flag_s(scr ? 1 : 0, wave_tot, &s_total);
-    const int nscr_chunk = s_total;
-    const bool audit = scr && ((sbase + n_scr + so) % static_cast<unsigned long long>(audit_period) == 0);
-    const bool eval = inb && (!scr || audit);
-    const int eo = scan_flag_s(eval ? 1 : 0, wave_tot, &s_total);
-    if (r < M) {
-      sflag[r] = (scr && !audit) ? 1 : 0;
-      if (scr && !audit) rlogL[r] = -INFINITY;
-      if (!inb) rlogL[r] = -INFINITY;
-    }
-    if (eval) {
-      const int i = n_eval + eo;
-      idx[i] = r;
-      aud[i] = audit ? 1 : 0;
-      for (int q = 0; q < d; ++q) xc[static_cast<long>(i) * d + q] = xin[static_cast<long>(r) * d + q];
-    }
-    n_eval += s_total;
-    n_scr += nscr_chunk;
-    __syncthreads();
-  }
+  __shared__ int red[2 * (kSC / 64)];
+  const int r = blockIdx.x * kSC + threadIdx.x;
+  bool inb;
+  const bool scr = screened_row(r, M, screening, margin, flag, rthr, yhat, norm[0], norm[1], &inb);
+  const int ni = __popcll(__ballot(inb)), ns = __popcll(__ballot(scr));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) { red[2 * wv] = ni; red[2 * wv + 1] = ns; }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    *count = n_eval;
-    sc->screened_seen = sbase + n_scr;
+    int ti = 0, ts = 0;
+    for (int q = 0; q < kSC / 64; ++q) { ti += red[2 * q]; ts += red[2 * q + 1]; }
+    chunk_cnt[2 * blockIdx.x] = ti;
+    chunk_cnt[2 * blockIdx.x + 1] = ts;
+  }
+}
+
+__global__ void __launch_bounds__(kSC)
+k_screen_write(int M, int d, int screening, double margin, int audit_period, const int* __restrict__ flag,
+               const double* __restrict__ rthr, const float* __restrict__ yhat, const float* __restrict__ norm,
+               const float* __restrict__ xin, const int* __restrict__ chunk_cnt, int* __restrict__ sflag,
+               int* __restrict__ idx, int* __restrict__ aud, float* __restrict__ xc, int* __restrict__ count,
+               double* __restrict__ rlogL, SurrCounters* __restrict__ sc, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  __shared__ int wave_tot[kSC / 64];
+  __shared__ int s_total;
+  __shared__ long long s_off[2];     // screened and evaluated rows before this chunk
+  __shared__ int s_rows[kSC];
+  const int nchunk = (M + kSC - 1) / kSC;
+  const unsigned long long sbase = sc->screened_seen;
+  const long long period = audit_period;
+  if (threadIdx.x == 0) {
+    long long ps = 0, pe = 0, ts = 0, te = 0;
+    for (int c = 0; c < nchunk; ++c) {
+      const int ni = chunk_cnt[2 * c], ns = chunk_cnt[2 * c + 1];
+      const long long ev = (ni - ns) + audits_in(sbase, ts, ns, period);
+      if (c == static_cast<int>(blockIdx.x)) { ps = ts; pe = te; }
+      ts += ns;
+      te += ev;
+    }
+    s_off[0] = ps;
+    s_off[1] = pe;
+    // count[0]: rows to evaluate; count[1]: rows screened by this call (added
+    // to the running total by k_scatter, after every chunk has read it)
+    if (blockIdx.x == 0) {
+      count[0] = static_cast<int>(te);
+      count[1] = static_cast<int>(ts);
+    }
+  }
+  __syncthreads();
+  const int r = blockIdx.x * kSC + threadIdx.x;
+  bool inb;
+  const bool scr = screened_row(r, M, screening, margin, flag, rthr, yhat, norm[0], norm[1], &inb);
+  const int so = scan_flag_s(scr ? 1 : 0, wave_tot, &s_total);
+  const bool audit = scr && ((sbase + static_cast<unsigned long long>(s_off[0] + so)) %
+                             static_cast<unsigned long long>(period) == 0);
+  const bool eval = inb && (!scr || audit);
+  const int eo = scan_flag_s(eval ? 1 : 0, wave_tot, &s_total);
+  const int n_eval = s_total;
+  if (r < M) {
+    sflag[r] = (scr && !audit) ? 1 : 0;
+    if ((scr && !audit) || !inb) rlogL[r] = -INFINITY;
+  }
+  const long long base = s_off[1];
+  if (eval) {
+    idx[base + eo] = r;
+    aud[base + eo] = audit ? 1 : 0;
+    s_rows[eo] = r;
+  }
+  __syncthreads();
+  // the chunk's evaluated rows, coordinates in order (consecutive threads read
+  // consecutive coordinates of a row)
+  for (int e = threadIdx.x; e < n_eval * d; e += kSC) {
+    const int k = e / d, q = e - k * d;
+    xc[(base + k) * d + q] = xin[static_cast<long>(s_rows[k]) * d + q];
   }
 }
 
 hipError_t launch_screen(int M, int d, int screening, double margin, int audit_period, const int* flag,
                          const double* rthr, const float* yhat, const float* norm, const float* xin,
                          int* sflag, int* idx, int* aud, float* xc, int* count, double* rlogL,
-                         SurrCounters* sc, const int* gate, hipStream_t s) {
-  hipLaunchKernelGGL(k_screen, dim3(1), dim3(kST), 0, s, M, d, screening, margin, audit_period, flag,
-                     rthr, yhat, norm, xin, sflag, idx, aud, xc, count, rlogL, sc, gate);
+                         SurrCounters* sc, int* chunk_cnt, const int* gate, hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  const int nchunk = (M + kSC - 1) / kSC;
+  hipLaunchKernelGGL(k_screen_count, dim3(nchunk), dim3(kSC), 0, s, M, screening, margin, flag, rthr, yhat,
+                     norm, chunk_cnt, gate);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_screen_write, dim3(nchunk), dim3(kSC), 0, s, M, d, screening, margin, audit_period,
+                     flag, rthr, yhat, norm, xin, chunk_cnt, sflag, idx, aud, xc, count, rlogL, sc, gate);
   return hipGetLastError();
 }
 
@@ -122,6 +191,7 @@ k_scatter(int d, const int* __restrict__ count, const int* __restrict__ idx, con
   }
   __syncthreads();
   if (threadIdx.x == 0) {
+    sc->screened_seen += static_cast<unsigned long long>(count[1]);
     // pairs counts the rows written to the ring (none before the ring exists),
     // so slots [0, min(pairs, cap)) always hold data
     if (cap > 0) sc->pairs = base + n;

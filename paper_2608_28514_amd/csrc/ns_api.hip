@@ -56,6 +56,7 @@ struct ns_ctx {
   SurrCounters* d_sc = nullptr;
   SurrCounters* h_sc = nullptr;   // pinned
   int* d_count = nullptr;
+  int* d_chunk = nullptr;   // per-chunk counts of the screening passes
   int* d_idx = nullptr;
   int* d_aud = nullptr;
   float* d_xc = nullptr;
@@ -219,7 +220,7 @@ static void free_all(ns_ctx* c) {
                   b.accepted, b.split_ok, b.logV, b.logV_eff, b.centre, b.cov, b.chol, b.chol_f,
                   b.dead_u, b.dead_logL, b.st, c->d_out3, c->rb.cs, c->rb.pts, c->rb.xin,
                   c->rb.flag, c->rb.rlogL, c->rb.gate, c->rb.H0, c->rb.H1, c->rb.Y, c->rb.rthr,
-                  c->rb.sflag, c->d_sc, c->d_count, c->d_idx, c->d_aud, c->d_xc, c->d_clogL,
+                  c->rb.sflag, c->d_sc, c->d_count, c->d_chunk, c->d_idx, c->d_aud, c->d_xc, c->d_clogL,
                   c->d_yhat, c->sP, c->sG, c->sM, c->sV, c->s_norm, c->s_loss, c->s_Xb, c->s_yb,
                   c->s_Yb, c->s_Z, c->s_H, c->s_dY, c->s_work, c->s_H0, c->s_H1, c->rep_x, c->rep_y,
                   c->s_xs, c->d_lo_box, c->d_span_box};
@@ -350,7 +351,7 @@ static ns_status eval_rows(ns_ctx* c, long n, const int* gate, bool allow_screen
     }
     NS_TRY(launch_screen(static_cast<int>(n), d, screening, c->scfg.margin, std::max(1, c->scfg.audit_period),
                          c->rb.flag, c->rb.rthr, c->d_yhat, c->s_norm, c->rb.xin, c->rb.sflag, c->d_idx,
-                         c->d_aud, c->d_xc, c->d_count, c->rb.rlogL, c->d_sc, gate, c->stream));
+                         c->d_aud, c->d_xc, c->d_count, c->rb.rlogL, c->d_sc, c->d_chunk, gate, c->stream));
     NS_TRY(net_forward(c->net, c->mode_first, c->mode_rest, static_cast<int>(n), c->d_xc, c->rb.H0,
                        c->rb.H1, c->rb.Y, gate, c->stream, c->d_count));
     NS_TRY(launch_chi2(static_cast<int>(n), c->net.widths[c->net.n_layers], c->rb.Y, c->mlp_data,
@@ -710,7 +711,8 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
       NS_INIT_HIP(dalloc(&rb.sflag, rb.rows_cap));
       NS_INIT_HIP(dalloc(&c->d_sc, 1));
       NS_INIT_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_sc), sizeof(SurrCounters), hipHostMallocDefault));
-      NS_INIT_HIP(dalloc(&c->d_count, 1));
+      NS_INIT_HIP(dalloc(&c->d_count, 2));
+      NS_INIT_HIP(dalloc(&c->d_chunk, 2 * ((rb.rows_cap + 255) / 256)));
       NS_INIT_HIP(dalloc(&c->d_idx, rb.rows_cap));
       NS_INIT_HIP(dalloc(&c->d_aud, rb.rows_cap));
       NS_INIT_HIP(dalloc(&c->d_xc, static_cast<size_t>(rb.rows_cap) * d));

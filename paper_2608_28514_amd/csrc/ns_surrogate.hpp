@@ -18,10 +18,11 @@ struct SurrCounters {
   unsigned long long false_screens;  // audited rows that cleared their threshold
 };
 
+// chunk_cnt: 2 ints per chunk of 256 rows (scratch shared by the two passes)
 hipError_t launch_screen(int M, int d, int screening, double margin, int audit_period, const int* flag,
                          const double* rthr, const float* yhat, const float* norm, const float* xin,
                          int* sflag, int* idx, int* aud, float* xc, int* count, double* rlogL,
-                         SurrCounters* sc, const int* gate, hipStream_t s);
+                         SurrCounters* sc, int* chunk_cnt, const int* gate, hipStream_t s);
 hipError_t launch_scatter(int d, const int* count, const int* idx, const int* aud, const double* clogL,
                           const double* rthr, const float* xc, double* rlogL, float* rep_x, double* rep_y,
                           long cap, SurrCounters* sc, const int* gate, hipStream_t s);
