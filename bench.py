@@ -31,17 +31,37 @@ FP64_PEAK = 78.6e12                 # MI355X FP64 vector FLOP/s
 
 EMU_FLOPS = 2 * (27 * 512 + 512 * 512 * 2 + 512 * 1024)   # one emulator evaluation
 BF16_PEAK = 2.5e15                                          # MI355X dense BF16 MFMA FLOP/s
+
+# HBM bytes per launch of the fused slice kernel on this workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled
+# by what the counter reads for a 256 MiB device copy (FETCH_SIZE reads half the
+# bytes moved: x2.0; WRITE_SIZE: x1.0).  Valid only for the kernel sources they
+# were taken with: reported as null once those sources change.
+SLICE_TRAFFIC = {
+    "sources": ["paper_2608_28514_amd/csrc/k_slice.hip", "paper_2608_28514_amd/csrc/ns_device.hpp",
+                "paper_2608_28514_amd/csrc/ns_internal.hpp"],
+    "sha256": "ce169e143eb6491e301d50d8e4e993a4ec35fec080297cd2abaea0308a6dbadb",
+    "fetch_kib": 317.3, "fetch_scale": 2.0, "write_kib": 18.19, "write_scale": 1.0,
+}
+
+
+def slice_traffic_bytes():
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in SLICE_TRAFFIC["sources"]:
+        with open(os.path.join(here, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != SLICE_TRAFFIC["sha256"]:
+        return None
+    t = SLICE_TRAFFIC
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 FP32_PEAK = 157.3e12                                        # MI355X FP32 vector FLOP/s
 
 
 def rosen_flops_per_eval(d):
     # theta = lo + span*u (2d) + 9 terms of 8 flops + proposal x + t v (2d)
     return 2 * d + 8 * (d - 1) + 2 * d
-
-
-def dir_flops_per_iter(d):
-    # |z|^2 (2d), z/|z| (d), v = L zhat (d(d+1))
-    return 3 * d + d * (d + 1)
 
 
 def main():
@@ -84,7 +104,6 @@ def main():
         return bench_emulator(args, np, torch, native, workloads)
     spec = workloads.likelihood(2)
     N, m, d, depth = 500, args.m or 50, 10, 2
-    n_iter = 5 * d
     kw = dict(prec="f64", state="f32", tree_depth=depth)
 
     for k in range(args.warmup):
@@ -126,11 +145,14 @@ def main():
     # dominant kernel class and its roofline (ALU bound: FP64 likelihood arithmetic)
     dom = "slice"
     slice_ms, slice_n = kern["slice"]
-    flops = evals * rosen_flops_per_eval(d) + steps_sum * m * n_iter * dir_flops_per_iter(d)
+    # useful work of the slice kernel: the counted likelihood calls (the
+    # directions are formed by the separate draw kernel)
+    flops = evals * rosen_flops_per_eval(d)
     achieved = flops / (slice_ms * 1e-3) if slice_ms > 0 else 0.0
-    roof = {"kernel": "k_slice<float,double>", "bound": "alu", "achieved": achieved / 1e12,
+    roof = {"kernel": "k_slice<float,double,10>", "bound": "alu", "achieved": achieved / 1e12,
             "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK,
-            "traffic": None, "avg_launch_us": 1e3 * slice_ms / max(slice_n, 1),
+            "traffic": slice_traffic_bytes(), "traffic_unit": "bytes per launch",
+            "avg_launch_us": 1e3 * slice_ms / max(slice_n, 1),
             "flops_per_launch": flops / max(slice_n, 1), "dominant_class": dom}
 
     out = {

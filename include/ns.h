@@ -151,8 +151,10 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
 /* One batched update of m live points (Sec. 3; Algorithms 1 and 2): select the
  * m worst, run m constrained slice-sampling chains, correct, update the live
  * set, append m dead rows and accumulate the evidence.  Enqueued without
- * synchronising.  Returns NS_DONE once the stopping rule is known to hold
- * (the device checks it after every step; steps after it are no-ops). */
+ * synchronising; the host follows the device through a progress word in
+ * pinned host memory and waits only while more than eight steps are in
+ * flight.  Returns NS_DONE once the stopping rule is known to hold (the device
+ * checks it after every step; steps after it are no-ops). */
 ns_status ns_step_batch(ns_ctx* c, int m);
 
 /* Repeat ns_step_batch(m) until the stopping rule holds or max_steps steps

@@ -165,6 +165,7 @@ k_cluster_level(int level, int depth, int N, int d_arg, int iters, const T* __re
   // consecutive threads read consecutive coordinates of a member's row
   auto load_chunk = [&](int ch) -> int {
     const int r0 = ch * cs, n = min(cs, cnt - r0);
+#pragma unroll 8
     for (int e = threadIdx.x; e < n * d; e += kCT) {
       const int rl = e / d, i = e - rl * d;
       pts[i * cs + rl] = u[static_cast<long>(s_mem[r0 + rl]) * d + i];
@@ -238,6 +239,16 @@ k_cluster_level(int level, int depth, int N, int d_arg, int iters, const T* __re
 #pragma unroll
       for (int b2 = 0; b2 < 4; ++b2) cpart[(a * 4 + b2) * kCT + threadIdx.x] = c4[a][b2];
     __syncthreads();
+    // partials of a block summed over its point groups by a fixed binary tree
+    int span = 1;
+    while (span < GC) span <<= 1;
+    for (int off = span >> 1; off > 0; off >>= 1) {
+      if (blk < NB && gc < off && gc + off < GC) {
+#pragma unroll
+        for (int ab = 0; ab < 16; ++ab) cpart[ab * kCT + threadIdx.x] += cpart[ab * kCT + threadIdx.x + off];
+      }
+      __syncthreads();
+    }
     double* C = cov + static_cast<long>(node) * kMaxD * kMaxD;
     for (int e = threadIdx.x; e < NB * 16; e += kCT) {
       const int b = e / 16, ab = e % 16;
@@ -245,9 +256,7 @@ k_cluster_level(int level, int depth, int N, int d_arg, int iters, const T* __re
       while (rem2 > bi2) { rem2 -= bi2 + 1; ++bi2; }
       const int ii = bi2 * 4 + ab / 4, jj = rem2 * 4 + ab % 4;
       if (ii >= d || jj >= d || jj > ii) continue;
-      double t = 0.0;
-      for (int q = 0; q < GC; ++q) t += cpart[ab * kCT + b * GC + q];
-      t /= static_cast<double>(cnt - 1);
+      const double t = cpart[ab * kCT + b * GC] / static_cast<double>(cnt - 1);
       C[ii * kMaxD + jj] = t;
       C[jj * kMaxD + ii] = t;
     }

@@ -93,7 +93,7 @@ k_slice_draws(SliceParams p, int d, const T* __restrict__ chol, const int* __res
   }
 }
 
-template <typename T, typename LT, int DM, bool EXACT>
+template <typename T, typename LT, int DM, bool EXACT, int KIND>
 __global__ void __launch_bounds__(64)
 k_slice(SliceParams p, int d_arg, int TH, LikDev lik, const T* __restrict__ u,
         const double* __restrict__ logL, const T* __restrict__ draws,
@@ -141,7 +141,10 @@ k_slice(SliceParams p, int d_arg, int TH, LikDev lik, const T* __restrict__ u,
   const double tau_j = tau[j];
   const double tau_e = LW[0];
   const T w = static_cast<T>(p.w);
+  // chain counters: uniform values, kept in lane 0 only (lane-dependent
+  // selects put them in vector registers, which relieves the scalar file)
   int n_evals = 0, n_oob = 0, n_so = 0, n_sh = 0, hn = 0;
+  const int l0 = lane == 0 ? 1 : 0;
   __syncthreads();
 
   const int n_iter = p.n_iter;
@@ -173,7 +176,7 @@ k_slice(SliceParams p, int d_arg, int TH, LikDev lik, const T* __restrict__ u,
       if (active) {
         const T off = left ? a0 - static_cast<T>(k) * w : b0 + static_cast<T>(k) * w;
         if (reg_line_in_box<T, DM>(x, v, off, d))
-          pass = clean_logL(LikAt<LT>::template eval_theta<DM, RegLineTheta<T, LT, DM>, EXACT>(lik, RegLineTheta<T, LT, DM>{x, v, off, blo, bsp})) > tau_e;
+          pass = clean_logL(LikAt<LT>::template eval_theta<DM, RegLineTheta<T, LT, DM>, EXACT, KIND>(lik, RegLineTheta<T, LT, DM>{x, v, off, blo, bsp})) > tau_e;
         else
           oob = true;
       }
@@ -186,15 +189,15 @@ k_slice(SliceParams p, int d_arg, int TH, LikDev lik, const T* __restrict__ u,
         const uint32_t obits = static_cast<uint32_t>(mo >> (32 * side));
         const int kf = (bits == 0xffffffffu) ? 32 : __builtin_ctz(~bits);
         if (base + kf >= p.max_stepout) {          // cap: k == E_max is never evaluated
-          n_evals += p.max_stepout - base;
-          n_so += 1;
+          n_evals += l0 * (p.max_stepout - base);
+          n_so += l0;
           kk = p.max_stepout;
         } else if (kf < 32) {
-          n_evals += kf + (((obits >> kf) & 1u) ? 0 : 1);
-          n_oob += (obits >> kf) & 1u;
+          n_evals += l0 * (kf + (((obits >> kf) & 1u) ? 0 : 1));
+          n_oob += l0 * static_cast<int>((obits >> kf) & 1u);
           kk = base + kf;
         } else {
-          n_evals += 32;
+          n_evals += l0 * 32;
         }
       }
     }
@@ -233,15 +236,15 @@ k_slice(SliceParams p, int d_arg, int TH, LikDev lik, const T* __restrict__ u,
       double l = -INFINITY;
       if (lane < S) {
         inb = reg_line_in_box<T, DM>(x, v, t, d);
-        if (inb) l = clean_logL(LikAt<LT>::template eval_theta<DM, RegLineTheta<T, LT, DM>, EXACT>(lik, RegLineTheta<T, LT, DM>{x, v, t, blo, bsp}));
+        if (inb) l = clean_logL(LikAt<LT>::template eval_theta<DM, RegLineTheta<T, LT, DM>, EXACT, KIND>(lik, RegLineTheta<T, LT, DM>{x, v, t, blo, bsp}));
         pass = l > tau_j;
       }
       const uint64_t mp = __ballot(pass);
       const uint64_t mi = __ballot(inb);
       const int upto = mp ? __builtin_ctzll(mp) : S - 1;   // last proposal taken
       const uint64_t taken = (upto >= 63) ? ~0ull : ((2ull << upto) - 1ull);
-      n_evals += __popcll(mi & taken);
-      n_oob += (upto + 1) - __popcll(mi & taken);
+      n_evals += l0 * __popcll(mi & taken);
+      n_oob += l0 * ((upto + 1) - __popcll(mi & taken));
       if (last && lane <= upto && s0 + lane < TH - 1) {
         const int slot = s0 + lane;
         hist_logL[static_cast<long>(slot) * m + j] = l;
@@ -250,7 +253,7 @@ k_slice(SliceParams p, int d_arg, int TH, LikDev lik, const T* __restrict__ u,
         for (int i = 0; i < DM; ++i)
           if (i < d) hu[i] = x[i] + t * v[i];
       }
-      if (last) hn = min(s0 + upto + 1, TH - 1);
+      if (last) hn = l0 * min(s0 + upto + 1, TH - 1);
       if (mp) {
         accepted = true;
         lx = __shfl(l, upto);
@@ -262,7 +265,7 @@ k_slice(SliceParams p, int d_arg, int TH, LikDev lik, const T* __restrict__ u,
         b = bS;
       }
     }
-    if (!accepted) n_sh += 1;
+    if (!accepted) n_sh += l0;
     __syncthreads();
   }
 
@@ -307,20 +310,27 @@ hipError_t launch_slice(const Shape& sh, const DevBufs& b, const LikDev& lik, co
       b.seeds, b.tau, b.LW,                                                                        \
       static_cast<ST*>(b.new_u), b.new_logL, b.chain_stat, b.hist_logL, static_cast<ST*>(b.hist_u), \
       b.hist_n, b.st
-#define NS_SLICE_K(ST, LT, DM, EX) \
-  hipLaunchKernelGGL((k_slice<ST, LT, DM, EX>), grid, block, 0, s, NS_SLICE_ARGS(ST))
+#define NS_SLICE_K(ST, LT, DM, EX, KD) \
+  hipLaunchKernelGGL((k_slice<ST, LT, DM, EX, KD>), grid, block, 0, s, NS_SLICE_ARGS(ST))
+  // exact dimensions also fix the likelihood family
+#define NS_SLICE_X(ST, LT, DM)                                                        \
+  do {                                                                                \
+    if (lik.kind == kMixture) NS_SLICE_K(ST, LT, DM, true, kMixture);                 \
+    else if (lik.kind == kRosenbrock) NS_SLICE_K(ST, LT, DM, true, kRosenbrock);      \
+    else NS_SLICE_K(ST, LT, DM, true, kShell);                                        \
+  } while (0)
 #define NS_SLICE_DM(ST, LT)                                             \
   do {                                                                  \
     switch (sh.d) {                                                     \
-      case 2: NS_SLICE_K(ST, LT, 2, true); break;                       \
-      case 3: NS_SLICE_K(ST, LT, 3, true); break;                       \
-      case 5: NS_SLICE_K(ST, LT, 5, true); break;                       \
-      case 10: NS_SLICE_K(ST, LT, 10, true); break;                     \
+      case 2: NS_SLICE_X(ST, LT, 2); break;                             \
+      case 3: NS_SLICE_X(ST, LT, 3); break;                             \
+      case 5: NS_SLICE_X(ST, LT, 5); break;                             \
+      case 10: NS_SLICE_X(ST, LT, 10); break;                           \
       default:                                                          \
-        if (sh.d <= 4) NS_SLICE_K(ST, LT, 4, false);                    \
-        else if (sh.d <= 8) NS_SLICE_K(ST, LT, 8, false);               \
-        else if (sh.d <= 16) NS_SLICE_K(ST, LT, 16, false);             \
-        else NS_SLICE_K(ST, LT, 32, false);                             \
+        if (sh.d <= 4) NS_SLICE_K(ST, LT, 4, false, -1);                \
+        else if (sh.d <= 8) NS_SLICE_K(ST, LT, 8, false, -1);           \
+        else if (sh.d <= 16) NS_SLICE_K(ST, LT, 16, false, -1);         \
+        else NS_SLICE_K(ST, LT, 32, false, -1);                         \
     }                                                                   \
   } while (0)
     if (sh.lik_f32)
@@ -334,6 +344,7 @@ hipError_t launch_slice(const Shape& sh, const DevBufs& b, const LikDev& lik, co
       NS_SLICE_DM(double, double);
 #undef NS_SLICE_DM
 #undef NS_SLICE_K
+#undef NS_SLICE_X
 #undef NS_SLICE_ARGS
   }
   return hipGetLastError();

@@ -108,10 +108,12 @@ struct LikAt<double> {
     return eval_theta<DM>(P, UnitTheta<double, Y>{P, y});
   }
   // th(i) returns theta_i in double; EXACT: the dimension is DM itself
-  template <int DM, typename TH, bool EXACT = false>
+  // KIND >= 0 fixes the family at compile time
+  template <int DM, typename TH, bool EXACT = false, int KIND = -1>
   __device__ __forceinline__ static double eval_theta(const LikDev& P, TH th) {
     const int d = EXACT ? DM : P.d;
-    if (P.kind == kMixture) {
+    const int kind = KIND >= 0 ? KIND : P.kind;
+    if (kind == kMixture) {
       if (P.n_comp == 1) {
         double q = 0.0;
 #pragma unroll
@@ -148,7 +150,7 @@ struct LikAt<double> {
       }
       return best + log(s);
     }
-    if (P.kind == kRosenbrock) {
+    if (kind == kRosenbrock) {
       double s = 0.0;
       double prev = th(0);
 #pragma unroll
@@ -181,10 +183,12 @@ struct LikAt<float> {
     return eval_theta<DM>(P, UnitTheta<float, Y>{P, y});
   }
   // th(i) returns theta_i in float; EXACT: the dimension is DM itself
-  template <int DM, typename TH, bool EXACT = false>
+  // KIND >= 0 fixes the family at compile time
+  template <int DM, typename TH, bool EXACT = false, int KIND = -1>
   __device__ __forceinline__ static double eval_theta(const LikDev& P, TH th) {
     const int d = EXACT ? DM : P.d;
-    if (P.kind == kMixture) {
+    const int kind = KIND >= 0 ? KIND : P.kind;
+    if (kind == kMixture) {
       if (P.n_comp == 1) {
         float q = 0.0f;
 #pragma unroll
@@ -221,7 +225,7 @@ struct LikAt<float> {
       }
       return static_cast<double>(best + logf(s));
     }
-    if (P.kind == kRosenbrock) {
+    if (kind == kRosenbrock) {
       float s = 0.0f;
       const float a = static_cast<float>(P.ros_a), b = static_cast<float>(P.ros_b);
       float prev = th(0);
