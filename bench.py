@@ -76,6 +76,14 @@ def main():
     ap.add_argument("--max-steps", type=int, default=0,
                     help="emulator workloads: stop each run after this many batched steps (timing probe)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stepout-spec", type=int, default=None,
+                    help="batched rounds: stepping-out offsets per side evaluated per round")
+    ap.add_argument("--shrink-spec", type=int, default=None,
+                    help="batched rounds: shrink proposals evaluated per round")
+    ap.add_argument("--screen", default="",
+                    help="workload 5: surrogate settings as k=v pairs, e.g. margin=3,train_every=4")
+    ap.add_argument("--no-screen", action="store_true",
+                    help="workload 5 without the learned pre-screen (the plain sampler)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
@@ -223,12 +231,20 @@ def bench_emulator(args, np, torch, native, workloads):
     m = args.m or m
     spec = workloads.likelihood(wl, seed=0)
     kw = dict(prec=prec, state="f32", tree_depth=1)
+    if args.stepout_spec:
+        kw["stepout_spec"] = args.stepout_spec
+    if args.shrink_spec:
+        kw["shrink_spec"] = args.shrink_spec
+    screen_kw = {"prec": "bf16"}
+    for item in filter(None, args.screen.split(",")):
+        k, v = item.split("=")
+        screen_kw[k] = float(v) if "." in v or "e" in v else int(v)
     runs, t_total = [], 0.0
     kern = {c: [0.0, 0] for c in native.TIMING_CLASSES}
     for k in range(args.warmup + args.steps):
         s = native.Sampler(spec, N, seed=(999 + k) if k < args.warmup else k - args.warmup, **kw)
-        if wl == 5:
-            s.enable_surrogate(prec="bf16")
+        if wl == 5 and not args.no_screen:
+            s.enable_surrogate(**screen_kw)
         timed = k >= args.warmup
         if timed:
             native.ns_set_timing(s.ctx, True)
@@ -264,7 +280,7 @@ def bench_emulator(args, np, torch, native, workloads):
         r = {"seed": k - args.warmup, "time_s": t1 - t0, "dead": st["dead"], "steps": st["steps"],
              "evals": st["evals"] - N, "net_rows": st["net_rows"], "screened": st["screened"],
              "logZ": lz, "sigma": sig, "H": H}
-        if wl == 5:
+        if wl == 5 and not args.no_screen:
             r["surrogate"] = s.surrogate_stats()
         runs.append(r)
         s.close()
@@ -282,7 +298,8 @@ def bench_emulator(args, np, torch, native, workloads):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16" if prec.startswith("bf16") else "f32", "data": "synthetic",
         "config": {"workload": f"emulator27d MLP 27-512-512-512-1024 N_live={N} m={m} depth=1 "
-                               f"layers={prec}{' +learned-screen' if wl == 5 else ''}"
+                               f"spec={kw.get('stepout_spec', 4)}/{kw.get('shrink_spec', 8)} "
+                               f"layers={prec}{' +learned-screen' if wl == 5 and not args.no_screen else ''}"
                                f"{f' PARTIAL first {args.max_steps} steps' if args.max_steps else ''}",
                    "n_live": N, "m": m, "d": 27},
         "evals_per_s": evals / t_total, "net_rows_per_s": rows / t_total,

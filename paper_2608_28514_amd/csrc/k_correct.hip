@@ -9,6 +9,7 @@
 // rank counting on the total order (logL, position), which is exact and
 // deterministic.
 #include "ns_internal.hpp"
+#include "ns_sort.hpp"
 
 namespace ns {
 
@@ -199,17 +200,30 @@ __device__ double block_reduce(double v, double* red, bool is_max) {
   return a[0];
 }
 
+// Sort key of live point i, keeping a copy of its likelihood.
+struct CopyKey {
+  const double* logL;
+  int n;
+  double* copy;
+  __device__ __forceinline__ uint64_t operator()(int i) const {
+    const double v = logL[i];
+    copy[i] = v;
+    return order_key(v);
+  }
+};
+
 template <typename T>
 __global__ void __launch_bounds__(kCorrT)
 k_correct(int m, int corr, int K, int TH, int N, int d, int nodes, double stop_frac,
           T* __restrict__ u, double* __restrict__ logL, int* __restrict__ label,
-          const int* __restrict__ order, const double* __restrict__ LW, const double* __restrict__ tau,
+          int* __restrict__ order, const double* __restrict__ LW, const double* __restrict__ tau,
           const T* __restrict__ new_u, const double* __restrict__ new_logL,
           const int* __restrict__ chain_stat, const double* __restrict__ hist_logL,
           const T* __restrict__ hist_u, const int* __restrict__ hist_n,
           const int* __restrict__ accepted, const double* __restrict__ centre,
           double* __restrict__ dead_u, double* __restrict__ dead_logL, RunState* __restrict__ st,
-          HostProgress* prog) {
+          HostProgress* prog, int sel_m, uint64_t seed, double* __restrict__ LW2,
+          double* __restrict__ tau2, int* __restrict__ seeds2) {
   if (st->done) return;
   __shared__ CorrLds S;
   __shared__ int s_order[kMaxC / 2];
@@ -220,6 +234,7 @@ k_correct(int m, int corr, int K, int TH, int N, int d, int nodes, double stop_f
   __shared__ double s_cen[kMaxNodes * kMaxD];
   __shared__ long long s_base;
   __shared__ double s_lz, s_A;
+  __shared__ int s_next[2];     // step counter after this step, stop flag
   // ---- every input of the step in one round of loads (blockDim >= 2m, so a
   // thread holds at most one entry of W and one of N); the writes to LDS
   // follow once all loads are in flight
@@ -394,12 +409,36 @@ k_correct(int m, int corr, int K, int TH, int N, int d, int nodes, double stop_f
     st->screened += static_cast<unsigned long long>(ce[4]);
     const int done = -static_cast<double>(base_dead + m) / Nd + lmax - lz < log(stop_frac);
     if (done) st->done = 1;
+    s_next[0] = static_cast<int>(st->step);
+    s_next[1] = done;
     if (prog) {
       volatile HostProgress* hp = prog;
       hp->step = st->step;
       hp->done = done;
       __threadfence_system();
     }
+  }
+  // ---- selection for the next step (Algorithm 1 "sorted", S_W, RNG.choose)
+  // on the updated live set: the same sort and draws as the selection kernel,
+  // written to the second set of batch buffers.  The barrier also makes this
+  // workgroup's writes of logL visible to its own reads below.
+  if (sel_m <= 0) return;
+  __syncthreads();
+  if (s_next[1]) return;
+  const int step_next = s_next[0];
+  uint64_t* keys = reinterpret_cast<uint64_t*>(S.tmpd);
+  sort_small(CopyKey{logL, N, S.listv}, sort_width(N), keys, S.tmpi);
+  for (int i = tq; i < N; i += blockDim.x) order[i] = S.tmpi[i];
+  const double lw_last = canon(S.listv[S.tmpi[sel_m - 1]]);
+  for (int j = tq; j < sel_m; j += blockDim.x) {
+    const double lw = canon(S.listv[S.tmpi[j]]);
+    LW2[j] = lw;
+    tau2[j] = (corr == kBestOfWorst) ? lw_last : lw;
+    const Draw2 dr = uniform2(seed, 0u, static_cast<uint32_t>(j), static_cast<uint32_t>(step_next),
+                              kStreamSeed << 24);
+    int r = j + 1 + static_cast<int>(floor(dr.a * static_cast<double>(N - j - 1)));
+    if (r > N - 1) r = N - 1;
+    seeds2[j] = S.tmpi[r];
   }
 }
 
@@ -449,20 +488,29 @@ static int corr_threads(int m) {
   return t < 128 ? 128 : (t > kCorrT ? kCorrT : t);
 }
 
+bool correct_selects_next(const Shape& sh) { return sh.N <= kSmallSort; }
+
 hipError_t launch_correct(const Shape& sh, const DevBufs& b, int m, int corr, int K,
-                          double stop_frac, hipStream_t s) {
+                          double stop_frac, int sel_m, uint64_t seed, hipStream_t s) {
+  // the next step's selection needs the register sort (N <= 2048) and at
+  // least P/2 threads
+  if (sh.N > kSmallSort) sel_m = 0;
+  int threads = corr_threads(m);
+  if (sel_m > 0 && sort_width(sh.N) / 2 > threads) threads = sort_width(sh.N) / 2;
   if (sh.state_f32)
-    hipLaunchKernelGGL(k_correct<float>, dim3(1), dim3(corr_threads(m)), 0, s, m, corr, K, sh.T, sh.N, sh.d,
+    hipLaunchKernelGGL(k_correct<float>, dim3(1), dim3(threads), 0, s, m, corr, K, sh.T, sh.N, sh.d,
                        sh.nodes, stop_frac, static_cast<float*>(b.u), b.logL, b.label, b.order, b.LW,
                        b.tau, static_cast<const float*>(b.new_u), b.new_logL, b.chain_stat,
                        b.hist_logL, static_cast<const float*>(b.hist_u), b.hist_n, b.accepted,
-                       b.centre, b.dead_u, b.dead_logL, b.st, b.prog);
+                       b.centre, b.dead_u, b.dead_logL, b.st, b.prog, sel_m, seed, b.LW2, b.tau2,
+                       b.seeds2);
   else
-    hipLaunchKernelGGL(k_correct<double>, dim3(1), dim3(corr_threads(m)), 0, s, m, corr, K, sh.T, sh.N, sh.d,
+    hipLaunchKernelGGL(k_correct<double>, dim3(1), dim3(threads), 0, s, m, corr, K, sh.T, sh.N, sh.d,
                        sh.nodes, stop_frac, static_cast<double*>(b.u), b.logL, b.label, b.order, b.LW,
                        b.tau, static_cast<const double*>(b.new_u), b.new_logL, b.chain_stat,
                        b.hist_logL, static_cast<const double*>(b.hist_u), b.hist_n, b.accepted,
-                       b.centre, b.dead_u, b.dead_logL, b.st, b.prog);
+                       b.centre, b.dead_u, b.dead_logL, b.st, b.prog, sel_m, seed, b.LW2, b.tau2,
+                       b.seeds2);
   return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ struct ns_ctx {
   HostProgress* h_prog = nullptr;  // coherent pinned, written by the device
   int64_t issued = 0;              // steps enqueued (device step count when in sync)
   bool tree_partial = false;       // nodes that cannot become clusters not regularised
+  int sel_ready_m = 0;             // > 0: the last step selected the next one for this m
   bool known_done = false;
   double* d_out3 = nullptr;
   // likelihood parameter arrays (device)
@@ -172,11 +173,16 @@ static ns_status alloc_batch(ns_ctx* c, int M) {
   DevBufs& b = c->b;
   const int d = c->sh.d, T = c->sh.T;
   hfree(b.seeds); hfree(b.tau); hfree(b.LW); hfree(b.new_u); hfree(b.new_logL);
+  hfree(b.seeds2); hfree(b.tau2); hfree(b.LW2);
   hfree(b.chain_stat); hfree(b.hist_logL); hfree(b.hist_u); hfree(b.hist_n); hfree(b.draws);
   const size_t sb = state_bytes(c);
   NS_TRY(dalloc(&b.seeds, M));
   NS_TRY(dalloc(&b.tau, M));
   NS_TRY(dalloc(&b.LW, M));
+  NS_TRY(dalloc(&b.seeds2, M));
+  NS_TRY(dalloc(&b.tau2, M));
+  NS_TRY(dalloc(&b.LW2, M));
+  c->sel_ready_m = 0;
   NS_TRY(hipMalloc(&b.new_u, sb * M * d));
   NS_TRY(dalloc(&b.new_logL, M));
   NS_TRY(dalloc(&b.chain_stat, kStatW * M));
@@ -215,7 +221,8 @@ static ns_status grow_dead(ns_ctx* c, long need) {
 
 static void free_all(ns_ctx* c) {
   DevBufs& b = c->b;
-  void* ptrs[] = {b.u, b.logL, b.label, b.order, b.seeds, b.tau, b.LW, b.new_u, b.new_logL,
+  void* ptrs[] = {b.u, b.logL, b.label, b.order, b.seeds, b.tau, b.LW, b.seeds2, b.tau2, b.LW2,
+                  b.new_u, b.new_logL,
                   b.chain_stat, b.hist_logL, b.hist_u, b.hist_n, b.draws, b.nodeof, b.count,
                   b.accepted, b.split_ok, b.logV, b.logV_eff, b.centre, b.cov, b.chol, b.chol_f,
                   b.dead_u, b.dead_logL, b.st, c->d_out3, c->rb.cs, c->rb.pts, c->rb.xin,
@@ -786,7 +793,12 @@ ns_status ns_step_batch(ns_ctx* c, int m) {
     if (r != NS_OK) return r;
   }
   const int corr = static_cast<int>(c->cfg.correction);
-  {
+  if (c->sel_ready_m == m) {
+    // the previous step's end-of-step kernel already selected this batch
+    std::swap(c->b.seeds, c->b.seeds2);
+    std::swap(c->b.tau, c->b.tau2);
+    std::swap(c->b.LW, c->b.LW2);
+  } else {
     TimeScope ts(c, NS_TIME_SELECT);
     NS_TRY(launch_select(c->sh, c->b, m, corr, c->cfg.seed, c->stream));
   }
@@ -807,7 +819,9 @@ ns_status ns_step_batch(ns_ctx* c, int m) {
   }
   {
     TimeScope ts(c, NS_TIME_CORRECT);
-    NS_TRY(launch_correct(c->sh, c->b, m, corr, c->cfg.history_iters, c->cfg.stop_frac, c->stream));
+    NS_TRY(launch_correct(c->sh, c->b, m, corr, c->cfg.history_iters, c->cfg.stop_frac, m,
+                          c->cfg.seed, c->stream));
+    c->sel_ready_m = correct_selects_next(c->sh) ? m : 0;
   }
   if (c->pending.size() > 4096) {
     NS_TRY(hipStreamSynchronize(c->stream));
@@ -926,6 +940,7 @@ ns_status ns_set_live(ns_ctx* c, const double* u, const double* logL, const int*
   }
   if (logL) NS_TRY(hipMemcpy(c->b.logL, logL, sizeof(double) * N, hipMemcpyHostToDevice));
   if (label) NS_TRY(hipMemcpy(c->b.label, label, sizeof(int) * N, hipMemcpyHostToDevice));
+  c->sel_ready_m = 0;   // a selection made from the previous live set is stale
   return NS_OK;
 }
 

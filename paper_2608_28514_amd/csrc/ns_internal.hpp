@@ -14,8 +14,11 @@ struct DevBufs {
   int* label;           // N (cluster node)
   int* order;           // N (ascending (logL, slot))
   int* seeds;           // M
+  int* seeds2;          // M: seeds of the next step, written by the end-of-step kernel
   double* tau;          // M (shrink thresholds)
+  double* tau2;         // M (next step)
   double* LW;           // M (logL of the m worst, ascending)
+  double* LW2;          // M (next step)
   void* new_u;          // M x d
   double* new_logL;     // M
   int* chain_stat;      // M x kStatW: evals, oob, stepout caps, shrink caps, screened
@@ -69,8 +72,11 @@ hipError_t launch_select(const Shape& sh, const DevBufs& b, int m, int corr, uin
 hipError_t launch_select_order(const double* logL, int N, int* order, hipStream_t s);
 hipError_t launch_slice(const Shape& sh, const DevBufs& b, const LikDev& lik, const SliceParams& p,
                         hipStream_t s);
+// sel_m > 0: also select the next step's m worst points and seeds into
+// seeds2 / tau2 / LW2 (and order); ignored unless correct_selects_next(sh).
 hipError_t launch_correct(const Shape& sh, const DevBufs& b, int m, int corr, int K,
-                          double stop_frac, hipStream_t s);
+                          double stop_frac, int sel_m, uint64_t seed, hipStream_t s);
+bool correct_selects_next(const Shape& sh);
 hipError_t launch_correct_arrays(int m, int corr, int K, int T, const double* wlogL,
                                  const double* nlogL, const double* P, const double* hist,
                                  const int* hist_n, int* acc_code, int* acc_hslot, double* acc_logL,
