@@ -52,10 +52,17 @@ __global__ void __launch_bounds__(256)
 k_gemm(int M, int N, int K, const float* __restrict__ A, long sar, long sak,
        const float* __restrict__ B, long sbn, long sbk, const float* __restrict__ bias, int act,
        float* __restrict__ C, long ldc, float* __restrict__ Z, long ldz, const int* __restrict__ gate,
-       const int* __restrict__ dM, __bf16* __restrict__ Csplit, long plane) {
+       const int* __restrict__ dM, __bf16* __restrict__ Csplit, long plane, int kchunk) {
   if (gate && *gate == 0) return;
   if (dM) M = min(M, *dM);              // row count decided on the device
   if (static_cast<int>(blockIdx.y) * kTM >= M) return;
+  // split K: block z sums k in [z kchunk, (z+1) kchunk) into plane z of C
+  int k_begin = 0, k_end = K;
+  if (kchunk > 0) {
+    k_begin = static_cast<int>(blockIdx.z) * kchunk;
+    k_end = min(K, k_begin + kchunk);
+    C += static_cast<long>(blockIdx.z) * M * ldc;
+  }
   __shared__ float As[kTM * kLdsK];
   __shared__ float Bs[kTN * kLdsK];
   const int tid = threadIdx.x;
@@ -71,20 +78,20 @@ k_gemm(int M, int N, int K, const float* __restrict__ A, long sar, long sak,
     for (int jx = 0; jx < 2; ++jx) macc[i][jx] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   const int wave = tid >> 6, lane = tid & 63;
-  for (int k0 = 0; k0 < K; k0 += kTK) {
+  for (int k0 = k_begin; k0 < k_end; k0 += kTK) {
     // stage A (64 x 32) and B^T (64 x 32) as FP32
     // the unit-stride index runs fastest across threads (coalesced loads)
     for (int q = tid; q < kTM * kTK; q += 256) {
       const int r = (sak == 1) ? q / kTK : q % kTM;
       const int k = (sak == 1) ? q % kTK : q / kTM;
       const int gr = m0 + r, gk = k0 + k;
-      As[r * kLdsK + k] = (gr < M && gk < K) ? A[gr * sar + gk * sak] : 0.f;
+      As[r * kLdsK + k] = (gr < M && gk < k_end) ? A[gr * sar + gk * sak] : 0.f;
     }
     for (int q = tid; q < kTN * kTK; q += 256) {
       const int r = (sbk == 1) ? q / kTK : q % kTN;
       const int k = (sbk == 1) ? q % kTK : q / kTN;
       const int gn = n0 + r, gk = k0 + k;
-      Bs[r * kLdsK + k] = (gn < N && gk < K) ? B[gn * sbn + gk * sbk] : 0.f;
+      Bs[r * kLdsK + k] = (gn < N && gk < k_end) ? B[gn * sbn + gk * sbk] : 0.f;
     }
     __syncthreads();
     if (MODE == kF32) {
@@ -164,21 +171,60 @@ k_gemm(int M, int N, int K, const float* __restrict__ A, long sar, long sak,
   }
 }
 
+static hipError_t gemm_grid(int mode, dim3 grid, int M, int N, int K, const float* A, long sar, long sak,
+                            const float* B, long sbn, long sbk, const float* bias, int act, float* C,
+                            long ldc, float* Z, long ldz, const int* gate, hipStream_t s, const int* dM,
+                            __bf16* Csplit, long plane, int kchunk) {
+  const dim3 block(256);
+  if (mode == kF32)
+    hipLaunchKernelGGL(k_gemm<kF32>, grid, block, 0, s, M, N, K, A, sar, sak, B, sbn, sbk, bias,
+                       act, C, ldc, Z, ldz, gate, dM, Csplit, plane, kchunk);
+  else if (mode == kBF16S)
+    hipLaunchKernelGGL(k_gemm<kBF16S>, grid, block, 0, s, M, N, K, A, sar, sak, B, sbn, sbk, bias,
+                       act, C, ldc, Z, ldz, gate, dM, Csplit, plane, kchunk);
+  else
+    hipLaunchKernelGGL(k_gemm<kBF16>, grid, block, 0, s, M, N, K, A, sar, sak, B, sbn, sbk, bias,
+                       act, C, ldc, Z, ldz, gate, dM, Csplit, plane, kchunk);
+  return hipGetLastError();
+}
+
 hipError_t launch_gemm(int mode, int M, int N, int K, const float* A, long sar, long sak,
                        const float* B, long sbn, long sbk, const float* bias, int act, float* C,
                        long ldc, float* Z, long ldz, const int* gate, hipStream_t s, const int* dM,
                        __bf16* Csplit, long plane) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  const dim3 grid((N + kTN - 1) / kTN, (M + kTM - 1) / kTM), block(256);
-  if (mode == kF32)
-    hipLaunchKernelGGL(k_gemm<kF32>, grid, block, 0, s, M, N, K, A, sar, sak, B, sbn, sbk, bias,
-                       act, C, ldc, Z, ldz, gate, dM, Csplit, plane);
-  else if (mode == kBF16S)
-    hipLaunchKernelGGL(k_gemm<kBF16S>, grid, block, 0, s, M, N, K, A, sar, sak, B, sbn, sbk, bias,
-                       act, C, ldc, Z, ldz, gate, dM, Csplit, plane);
-  else
-    hipLaunchKernelGGL(k_gemm<kBF16>, grid, block, 0, s, M, N, K, A, sar, sak, B, sbn, sbk, bias,
-                       act, C, ldc, Z, ldz, gate, dM, Csplit, plane);
+  const dim3 grid((N + kTN - 1) / kTN, (M + kTM - 1) / kTM);
+  return gemm_grid(mode, grid, M, N, K, A, sar, sak, B, sbn, sbk, bias, act, C, ldc, Z, ldz, gate, s, dM,
+                   Csplit, plane, 0);
+}
+
+// out[i] = sum_z part[z n + i], z = 0..S-1 in order
+__global__ void k_sum_planes(int S, long n, const float* __restrict__ part, float* __restrict__ out) {
+  const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float t = 0.f;
+  for (int z = 0; z < S; ++z) t += part[z * n + i];
+  out[i] = t;
+}
+
+hipError_t launch_gemm_splitk(int mode, int M, int N, int K, const float* A, long sar, long sak,
+                              const float* B, long sbn, long sbk, float* C, float* work, long work_elems,
+                              hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int tiles = ((N + kTN - 1) / kTN) * ((M + kTM - 1) / kTM);
+  int S = 1;
+  while (tiles * S < 256 && K / (S * 2) >= 256 && static_cast<long>(2 * S) * M * N <= work_elems) S *= 2;
+  if (S == 1)
+    return launch_gemm(mode, M, N, K, A, sar, sak, B, sbn, sbk, nullptr, kActNone, C, N, nullptr, 0,
+                       nullptr, s);
+  const int kchunk = ((K + S - 1) / S + kTK - 1) / kTK * kTK;
+  const dim3 grid((N + kTN - 1) / kTN, (M + kTM - 1) / kTM, (K + kchunk - 1) / kchunk);
+  hipError_t e = gemm_grid(mode, grid, M, N, K, A, sar, sak, B, sbn, sbk, nullptr, kActNone, work, N,
+                           nullptr, 0, nullptr, s, nullptr, nullptr, 0, kchunk);
+  if (e != hipSuccess) return e;
+  const long n = static_cast<long>(M) * N;
+  hipLaunchKernelGGL(k_sum_planes, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s,
+                     static_cast<int>(grid.z), n, work, C);
   return hipGetLastError();
 }
 
@@ -291,7 +337,9 @@ hipError_t launch_act_bwd(long n, int act, const float* Z, const float* dH, floa
   return hipGetLastError();
 }
 
-// db[n] = sum_r dZ[r, n] (fixed order: one thread per column)
+// db[n] = sum_r dZ[r, n] in a fixed order.  With a workspace: chunks of 256
+// rows, each summed by 4 row groups of one workgroup (64 columns per
+// workgroup, coalesced), then the chunk partials in chunk order.
 __global__ void k_colsum(int M, int N, const float* __restrict__ dZ, float* __restrict__ db) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
@@ -300,8 +348,35 @@ __global__ void k_colsum(int M, int N, const float* __restrict__ dZ, float* __re
   db[n] = s;
 }
 
-hipError_t launch_colsum(int M, int N, const float* dZ, float* db, hipStream_t s) {
+__global__ void __launch_bounds__(256)
+k_colsum_part(int M, int N, const float* __restrict__ dZ, float* __restrict__ part) {
+  __shared__ float red[256];
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + c;
+  const int r0 = blockIdx.y * 256, r1 = min(M, r0 + 256);
+  float s = 0.f;
+  if (n < N) {
+#pragma unroll 8
+    for (int r = r0 + g; r < r1; r += 4) s += dZ[static_cast<long>(r) * N + n];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (g == 0 && n < N)
+    part[static_cast<long>(blockIdx.y) * N + n] = ((red[c] + red[64 + c]) + red[128 + c]) + red[192 + c];
+}
+
+hipError_t launch_colsum(int M, int N, const float* dZ, float* db, hipStream_t s, float* work,
+                         long work_elems) {
   if (N <= 0) return hipSuccess;
+  const int chunks = (M + 255) / 256;
+  if (work && chunks > 1 && static_cast<long>(chunks) * N <= work_elems) {
+    hipLaunchKernelGGL(k_colsum_part, dim3((N + 63) / 64, chunks), dim3(256), 0, s, M, N, dZ, work);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_planes, dim3((N + 255) / 256), dim3(256), 0, s, chunks, static_cast<long>(N),
+                       work, db);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_colsum, dim3((N + 255) / 256), dim3(256), 0, s, M, N, dZ, db);
   return hipGetLastError();
 }

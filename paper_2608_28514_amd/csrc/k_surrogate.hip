@@ -10,7 +10,8 @@
 //   (emulator on the compacted rows)
 //   k_scatter  : true logL back to the rows; audited rows that clear their
 //                threshold count as false screens; every evaluated pair is
-//                appended to the replay ring.
+//                appended to the replay ring (k_scatter_final then advances
+//                the counters).
 // Between steps, training: minibatches drawn (Philox) from the ring, targets
 // max(logL, L_W[0] - floor_below) mapped to (t - mu)/s, MSE, the hand-written
 // backward of k_gemm.hip, Adam.  Accepted points always carry their true logL.
@@ -20,7 +21,6 @@
 
 namespace ns {
 
-constexpr int kST = 1024;
 
 __device__ int scan_flag_s(int flag, int* wave_tot, int* total) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -164,18 +164,25 @@ hipError_t launch_screen(int M, int d, int screening, double margin, int audit_p
   return hipGetLastError();
 }
 
-__global__ void __launch_bounds__(kST)
+// True logL back to the rows, audits, and the replay-ring append, over
+// chunks of 256 compacted rows (count[0] of them); every chunk reads the ring
+// position sc->pairs, which k_scatter_final advances afterwards.
+__global__ void __launch_bounds__(kSC)
 k_scatter(int d, const int* __restrict__ count, const int* __restrict__ idx, const int* __restrict__ aud,
           const double* __restrict__ clogL, const double* __restrict__ rthr, const float* __restrict__ xc,
           double* __restrict__ rlogL, float* __restrict__ rep_x, double* __restrict__ rep_y, long cap,
           SurrCounters* __restrict__ sc, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
+  const int n = count[0];
+  const int i0 = blockIdx.x * kSC;
+  if (i0 >= n) return;
+  const int i1 = min(n, i0 + kSC);
   __shared__ int s_fn, s_aud;
   if (threadIdx.x == 0) { s_fn = 0; s_aud = 0; }
   __syncthreads();
-  const int n = *count;
   const unsigned long long base = sc->pairs;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  const int i = i0 + threadIdx.x;
+  if (i < i1) {
     const int r = idx[i];
     const double l = clogL[i];
     rlogL[r] = l;
@@ -183,29 +190,41 @@ k_scatter(int d, const int* __restrict__ count, const int* __restrict__ idx, con
       atomicAdd(&s_aud, 1);
       if (l > rthr[r]) atomicAdd(&s_fn, 1);
     }
-    if (cap > 0) {
-      const long pos = static_cast<long>((base + i) % static_cast<unsigned long long>(cap));
-      for (int q = 0; q < d; ++q) rep_x[pos * d + q] = xc[static_cast<long>(i) * d + q];
-      rep_y[pos] = l;
+    if (cap > 0) rep_y[static_cast<long>((base + i) % static_cast<unsigned long long>(cap))] = l;
+  }
+  if (cap > 0)
+    for (int e = threadIdx.x; e < (i1 - i0) * d; e += kSC) {
+      const int k = e / d, q = e - k * d;
+      const long pos = static_cast<long>((base + i0 + k) % static_cast<unsigned long long>(cap));
+      rep_x[pos * d + q] = xc[static_cast<long>(i0 + k) * d + q];
     }
-  }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    sc->screened_seen += static_cast<unsigned long long>(count[1]);
-    // pairs counts the rows written to the ring (none before the ring exists),
-    // so slots [0, min(pairs, cap)) always hold data
-    if (cap > 0) sc->pairs = base + n;
-    sc->emu_rows += n;
-    sc->audited += s_aud;
-    sc->false_screens += s_fn;
-  }
+  // integer counts: the same totals whatever the order of the chunks
+  if (threadIdx.x == 0 && s_aud) atomicAdd(&sc->audited, static_cast<unsigned long long>(s_aud));
+  if (threadIdx.x == 0 && s_fn) atomicAdd(&sc->false_screens, static_cast<unsigned long long>(s_fn));
 }
 
-hipError_t launch_scatter(int d, const int* count, const int* idx, const int* aud, const double* clogL,
+__global__ void k_scatter_final(const int* __restrict__ count, long cap, SurrCounters* __restrict__ sc,
+                                const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  if (threadIdx.x != 0) return;
+  const int n = count[0];
+  sc->screened_seen += static_cast<unsigned long long>(count[1]);
+  // pairs counts the rows written to the ring (none before the ring exists),
+  // so slots [0, min(pairs, cap)) always hold data
+  if (cap > 0) sc->pairs += static_cast<unsigned long long>(n);
+  sc->emu_rows += static_cast<unsigned long long>(n);
+}
+
+hipError_t launch_scatter(int M, int d, const int* count, const int* idx, const int* aud, const double* clogL,
                           const double* rthr, const float* xc, double* rlogL, float* rep_x, double* rep_y,
                           long cap, SurrCounters* sc, const int* gate, hipStream_t s) {
-  hipLaunchKernelGGL(k_scatter, dim3(1), dim3(kST), 0, s, d, count, idx, aud, clogL, rthr, xc, rlogL, rep_x,
-                     rep_y, cap, sc, gate);
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter, dim3((M + kSC - 1) / kSC), dim3(kSC), 0, s, d, count, idx, aud, clogL, rthr,
+                     xc, rlogL, rep_x, rep_y, cap, sc, gate);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scatter_final, dim3(1), dim3(64), 0, s, count, cap, sc, gate);
   return hipGetLastError();
 }
 

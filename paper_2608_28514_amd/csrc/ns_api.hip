@@ -76,6 +76,8 @@ struct ns_ctx {
   double* rep_y = nullptr;
   long rep_cap = 0;
   float* s_xs = nullptr;          // standardised surrogate input of the rows
+  float* s_red = nullptr;         // split-K / column-sum workspace of the training step
+  long s_red_n = 0;
   double* d_lo_box = nullptr;     // prior box (device) for the input standardisation
   double* d_span_box = nullptr;
   int s_cooldown = 0;
@@ -229,7 +231,7 @@ static void free_all(ns_ctx* c) {
                   c->rb.flag, c->rb.rlogL, c->rb.gate, c->rb.H0, c->rb.H1, c->rb.Y, c->rb.rthr,
                   c->rb.sflag, c->d_sc, c->d_count, c->d_chunk, c->d_idx, c->d_aud, c->d_xc, c->d_clogL,
                   c->d_yhat, c->sP, c->sG, c->sM, c->sV, c->s_norm, c->s_loss, c->s_Xb, c->s_yb,
-                  c->s_Yb, c->s_Z, c->s_H, c->s_dY, c->s_work, c->s_H0, c->s_H1, c->rep_x, c->rep_y,
+                  c->s_Yb, c->s_Z, c->s_H, c->s_dY, c->s_work, c->s_red, c->s_H0, c->s_H1, c->rep_x, c->rep_y,
                   c->s_xs, c->d_lo_box, c->d_span_box};
   for (void* p : ptrs) hfree(p);
   for (void* p : c->lik_bufs) hfree(p);
@@ -288,9 +290,12 @@ static hipError_t mlp_fwd_impl(const ns_mlp_desc* net, int mode, const float* X,
   return hipSuccess;
 }
 
+// red_work (may be null): workspace for split-K weight gradients and chunked
+// bias sums (red_elems floats); without it the plain kernels run.
 static hipError_t mlp_bwd_impl(const ns_mlp_desc* net, int mode, const float* X, long B, const float* Zs,
                                const float* Hs, const float* dY, float* const* dW, float* const* db,
-                               float* dX, float* work, hipStream_t s) {
+                               float* dX, float* work, hipStream_t s, float* red_work = nullptr,
+                               long red_elems = 0) {
   const int L = net->n_layers;
   int maxw = 0;
   for (int l = 0; l <= L; ++l) maxw = std::max(maxw, net->widths[l]);
@@ -310,10 +315,14 @@ static hipError_t mlp_bwd_impl(const ns_mlp_desc* net, int mode, const float* X,
     }
     const float* hin = (l == 0) ? X : Hs + off[l - 1];
     // dW = H^T dZ
-    e = launch_gemm(mode, K, N, static_cast<int>(B), hin, 1, K, dz, 1, N, nullptr, kActNone, dW[l], N,
-                    nullptr, 0, nullptr, s);
+    if (red_work)
+      e = launch_gemm_splitk(mode, K, N, static_cast<int>(B), hin, 1, K, dz, 1, N, dW[l], red_work,
+                             red_elems, s);
+    else
+      e = launch_gemm(mode, K, N, static_cast<int>(B), hin, 1, K, dz, 1, N, nullptr, kActNone, dW[l], N,
+                      nullptr, 0, nullptr, s);
     if (e != hipSuccess) return e;
-    e = launch_colsum(static_cast<int>(B), N, dz, db[l], s);
+    e = launch_colsum(static_cast<int>(B), N, dz, db[l], s, red_work, red_elems);
     if (e != hipSuccess) return e;
     if (l > 0 || dX) {
       float* out = (l == 0) ? dX : dH;
@@ -363,7 +372,7 @@ static ns_status eval_rows(ns_ctx* c, long n, const int* gate, bool allow_screen
                        c->rb.H1, c->rb.Y, gate, c->stream, c->d_count));
     NS_TRY(launch_chi2(static_cast<int>(n), c->net.widths[c->net.n_layers], c->rb.Y, c->mlp_data,
                        c->mlp_isig, nullptr, c->d_clogL, gate, c->stream, c->d_count));
-    NS_TRY(launch_scatter(d, c->d_count, c->d_idx, c->d_aud, c->d_clogL, c->rb.rthr, c->d_xc, c->rb.rlogL,
+    NS_TRY(launch_scatter(static_cast<int>(n), d, c->d_count, c->d_idx, c->d_aud, c->d_clogL, c->rb.rthr, c->d_xc, c->rb.rlogL,
                           c->rep_x, c->rep_y, c->surr ? c->rep_cap : 0, c->d_sc, gate, c->stream));
   } else {
     NS_TRY(launch_rows_loglike(c->sh, c->lik, n, c->rb.pts, c->rb.flag, c->rb.rlogL, gate, c->stream));
@@ -421,7 +430,7 @@ static ns_status surr_train(ns_ctx* c) {
       db[l] = const_cast<float*>(c->s_grad.b[l]);
     }
     NS_TRY(mlp_bwd_impl(&c->s_net, mode, c->s_Xb, B, c->s_Z, c->s_H, c->s_dY, dW, db, nullptr, c->s_work,
-                        c->stream));
+                        c->stream, c->s_red, c->s_red_n));
     NS_TRY(launch_adam(c->s_np, sc.lr, 0.9f, 0.999f, 1e-8f, ++c->s_adam_t, c->sP, c->sG, c->sM, c->sV,
                        c->stream));
   }
@@ -1221,6 +1230,10 @@ ns_status ns_surrogate_enable(ns_ctx* c, const ns_surrogate_config* sc) {
   NS_TRY(dalloc(&c->s_Z, static_cast<size_t>(B) * (2 * H + 1)));
   NS_TRY(dalloc(&c->s_H, static_cast<size_t>(B) * (2 * H + 1)));
   NS_TRY(dalloc(&c->s_work, static_cast<size_t>(2) * B * std::max(H, d)));
+  // split-K partials of the weight gradients (up to 8 planes of H x H) and
+  // the chunked bias sums
+  c->s_red_n = std::max<long>(8L * H * std::max(H, d), ((B + 255) / 256) * static_cast<long>(H));
+  NS_TRY(dalloc(&c->s_red, static_cast<size_t>(c->s_red_n)));
   NS_TRY(dalloc(&c->s_H0, static_cast<size_t>(c->rb.rows_cap) * H));
   NS_TRY(dalloc(&c->s_H1, static_cast<size_t>(c->rb.rows_cap) * H));
   NS_TRY(dalloc(&c->d_yhat, c->rb.rows_cap));

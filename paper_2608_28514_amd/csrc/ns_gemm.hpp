@@ -20,7 +20,15 @@ hipError_t launch_dense_split(int M, int N, int K, const __bf16* A, long aplane,
                               const float* bias, int act, float* C, __bf16* Csplit, long cplane,
                               const int* gate, const int* dM, hipStream_t s);
 hipError_t launch_act_bwd(long n, int act, const float* Z, const float* dH, float* dZ, hipStream_t s);
-hipError_t launch_colsum(int M, int N, const float* dZ, float* db, hipStream_t s);
+// work (may be null): workspace for the chunked column sum (>= ceil(M/256) * N floats)
+hipError_t launch_colsum(int M, int N, const float* dZ, float* db, hipStream_t s, float* work = nullptr,
+                         long work_elems = 0);
+// C (M x N, ld N) = A B without bias or activation, splitting K across
+// workgroups when the output has few tiles; partial products go to work
+// (work_elems floats) and are added in a fixed order.
+hipError_t launch_gemm_splitk(int mode, int M, int N, int K, const float* A, long sar, long sak,
+                              const float* B, long sbn, long sbk, float* C, float* work, long work_elems,
+                              hipStream_t s);
 hipError_t launch_chi2(int M, int N, const float* Y, const double* data, const double* isig,
                        const int* flag, double* logL, const int* gate, hipStream_t s,
                        const int* dM = nullptr);

@@ -23,7 +23,8 @@ hipError_t launch_screen(int M, int d, int screening, double margin, int audit_p
                          const double* rthr, const float* yhat, const float* norm, const float* xin,
                          int* sflag, int* idx, int* aud, float* xc, int* count, double* rlogL,
                          SurrCounters* sc, int* chunk_cnt, const int* gate, hipStream_t s);
-hipError_t launch_scatter(int d, const int* count, const int* idx, const int* aud, const double* clogL,
+// M: rows of the round (upper bound of count[0])
+hipError_t launch_scatter(int M, int d, const int* count, const int* idx, const int* aud, const double* clogL,
                           const double* rthr, const float* xc, double* rlogL, float* rep_x, double* rep_y,
                           long cap, SurrCounters* sc, const int* gate, hipStream_t s);
 hipError_t launch_sample_batch(int B, int d, uint64_t seed, uint32_t call, uint32_t iter, const float* rep_x,
