@@ -53,6 +53,7 @@ struct ns_ctx {
   int mode_first = kF32, mode_rest = kF32;
   double* mlp_data = nullptr;
   double* mlp_isig = nullptr;
+  bool emu_frag = false;      // emulator likelihood on the fragment-major path (emu_forward_logL)
   // compaction of the rows to evaluate (network likelihoods) + learned screen
   SurrCounters* d_sc = nullptr;
   SurrCounters* h_sc = nullptr;   // pinned
@@ -368,10 +369,17 @@ static ns_status eval_rows(ns_ctx* c, long n, const int* gate, bool allow_screen
     NS_TRY(launch_screen(static_cast<int>(n), d, screening, c->scfg.margin, std::max(1, c->scfg.audit_period),
                          c->rb.flag, c->rb.rthr, c->d_yhat, c->s_norm, c->rb.xin, c->rb.sflag, c->d_idx,
                          c->d_aud, c->d_xc, c->d_count, c->rb.rlogL, c->d_sc, c->d_chunk, gate, c->stream));
-    NS_TRY(net_forward(c->net, c->mode_first, c->mode_rest, static_cast<int>(n), c->d_xc, c->rb.H0,
-                       c->rb.H1, c->rb.Y, gate, c->stream, c->d_count));
-    NS_TRY(launch_chi2(static_cast<int>(n), c->net.widths[c->net.n_layers], c->rb.Y, c->mlp_data,
-                       c->mlp_isig, nullptr, c->d_clogL, gate, c->stream, c->d_count));
+    if (c->emu_frag) {
+      // the chi^2 partials (n x widths[L]/32 doubles) reuse the output buffer
+      NS_TRY(emu_forward_logL(c->net, static_cast<int>(n), c->d_xc, reinterpret_cast<__bf16*>(c->rb.H0),
+                              reinterpret_cast<__bf16*>(c->rb.H1), reinterpret_cast<double*>(c->rb.Y),
+                              c->mlp_data, c->mlp_isig, c->d_clogL, gate, c->d_count, c->stream));
+    } else {
+      NS_TRY(net_forward(c->net, c->mode_first, c->mode_rest, static_cast<int>(n), c->d_xc, c->rb.H0,
+                         c->rb.H1, c->rb.Y, gate, c->stream, c->d_count));
+      NS_TRY(launch_chi2(static_cast<int>(n), c->net.widths[c->net.n_layers], c->rb.Y, c->mlp_data,
+                         c->mlp_isig, nullptr, c->d_clogL, gate, c->stream, c->d_count));
+    }
     NS_TRY(launch_scatter(static_cast<int>(n), d, c->d_count, c->d_idx, c->d_aud, c->d_clogL, c->rb.rthr, c->d_xc, c->rb.rlogL,
                           c->rep_x, c->rep_y, c->surr ? c->rep_cap : 0, c->d_sc, gate, c->stream));
   } else {
@@ -628,6 +636,10 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
         std::vector<__bf16> wb(wt.size());
         for (size_t q = 0; q < wt.size(); ++q) wb[q] = static_cast<__bf16>(wt[q]);
         NS_INIT_TRY(upload(c, wb.data(), wb.size(), &net.Wb[l]));
+        if (Nn % 32 == 0) {
+          frag_layout_host(wt.data(), Nn, K, wb.data());
+          NS_INIT_TRY(upload(c, wb.data(), wb.size(), &net.Wf[l]));
+        }
       }
     }
     const int nout = lik->widths[lik->n_layers];
@@ -642,6 +654,7 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
     // layer 0 always FP32 (theta is never rounded); the rest BF16 x3-split or FP32
     c->mode_first = kF32;
     c->mode_rest = lik->prec == NS_BF16X3 ? kBF16S : (lik->prec == NS_BF16 ? kBF16 : kF32);
+    c->emu_frag = emu_frag_eligible(net, c->mode_first, c->mode_rest);
   }
   // state
   DevBufs& b = c->b;
@@ -720,8 +733,10 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
     NS_INIT_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_gate), sizeof(int), hipHostMallocDefault));
     if (c->is_mlp) {
       // hidden activations: FP32, or three bfloat16 planes (1.5x) on the split path
-      NS_INIT_HIP(dalloc(&rb.H0, static_cast<size_t>(rb.rows_cap) * c->net.max_width * 3 / 2 + 64));
-      NS_INIT_HIP(dalloc(&rb.H1, static_cast<size_t>(rb.rows_cap) * c->net.max_width * 3 / 2 + 64));
+      // three bfloat16 planes of rows (padded to 16) x max_width = 1.5 floats per element
+      const size_t hp = static_cast<size_t>(emu_frag_plane(rb.rows_cap, c->net.max_width));
+      NS_INIT_HIP(dalloc(&rb.H0, hp * 3 / 2 + 64));
+      NS_INIT_HIP(dalloc(&rb.H1, hp * 3 / 2 + 64));
       NS_INIT_HIP(dalloc(&rb.Y, static_cast<size_t>(rb.rows_cap) * c->net.widths[c->net.n_layers]));
       NS_INIT_HIP(dalloc(&rb.rthr, rb.rows_cap));
       NS_INIT_HIP(dalloc(&rb.sflag, rb.rows_cap));

@@ -45,6 +45,7 @@ struct NetDev {
   int max_width;
   int w_rowmajor;
   const __bf16* Wb[8];  // bfloat16 copies of Wt (layers >= 1) for the split-activation path
+  const __bf16* Wf[8];  // the same in the fragment-major layout (emu_forward_logL)
 };
 
 // Forward over M rows of X (M x widths[0]); H0/H1 ping-pong buffers of
@@ -55,5 +56,19 @@ struct NetDev {
 hipError_t net_forward(const NetDev& net, int mode_first, int mode_rest, int M, const float* X,
                        float* H0, float* H1, float* Y, const int* gate, hipStream_t s,
                        const int* dM = nullptr);
+
+// Emulator log-likelihood on fragment-major split activations (k_gemm.hip):
+// layer 0 in FP32, hidden layers and the output layer on bfloat16 MFMA, the
+// diagonal chi^2 fused into the output layer.  Applies when layer 0 is FP32,
+// the others split bfloat16, at least two layers, widths[0] <= 32 and every
+// other width a multiple of 32 (emu_frag_eligible).  P0/P1: three planes of
+// emu_frag_plane(M, max_width) bfloat16 each; part: M x widths[L]/32 doubles.
+bool emu_frag_eligible(const NetDev& net, int mode_first, int mode_rest);
+long emu_frag_plane(long M, int max_width);
+hipError_t emu_forward_logL(const NetDev& net, int M, const float* X, __bf16* P0, __bf16* P1, double* part,
+                            const double* data, const double* isig, double* logL, const int* gate,
+                            const int* dM, hipStream_t s);
+// Host: W^T (N x K FP32, N % 16 == 0, K % 32 == 0) -> fragment-major bfloat16.
+void frag_layout_host(const float* Wt, int N, int K, __bf16* out);
 
 }  // namespace ns

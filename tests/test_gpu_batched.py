@@ -9,7 +9,9 @@ oracle.
   gamma_K * sum |a||w| (gamma_K = K 2^-24) of the FP64 product; single-bfloat16
   operands within the bfloat16 rounding bound.
 * Network backward: against the oracle's FP64 backward within FP32 bounds.
-* Emulator likelihood: quantiles of |dlogL| against the FP64 oracle.
+* Emulator likelihood: quantiles of |dlogL| against the FP64 oracle, and every
+  row within a forward error bound derived from the FP32 / split-bfloat16
+  arithmetic of each layer (both the fragment-major path and the generic one).
 """
 import math
 import numpy as np
@@ -182,3 +184,118 @@ def test_small_emulator_run_agrees_with_oracle():
         sg = np.mean([x[1] for x in z])
         print(prec, mg, mo, sg, so)
         assert abs(mg - mo) < 2 * math.sqrt((sg ** 2 + so ** 2) / 3) * 1.5
+
+
+U32 = 2.0 ** -24
+
+
+def _gamma(n):
+    return n * U32 / (1.0 - n * U32)
+
+
+def _emulator_logL_bound(spec, X):
+    """Per-row bound on |logL_gpu - logL_exact| for the emulator likelihood
+    evaluated with an FP32 first layer (fused multiply-adds from zero, then the
+    bias) and split-bfloat16 MFMA layers (hi + mid + lo activations, bfloat16
+    weights, FP32 accumulation of 3K products, then the bias), tanh hidden
+    activations, FP64 chi^2.  Layer by layer, with h the exact activations:
+      first layer: |dz| <= gamma(K0 + 1) (sum |x||w| + |b|)
+      MFMA layer:  |dz| <= gamma(3K + 2) 1.02 (sum |h||w| + |b|) + sum |dh||w|
+      tanh (1-Lipschitz, <= 2 ulp) and the three-term split: |dh| <= |dz| + 9 u |h|
+      output y = z; chi^2: |dlogL| <= sum |r| d / sigma + (d / sigma)^2 / 2,
+    r = (y - D) / sigma, plus 1e-12 |logL| for the FP64 sum."""
+    Ws, bs = spec["weights"], spec["biases"]
+    L = len(Ws)
+    h = np.asarray(X, dtype=np.float64)
+    dh = np.zeros_like(h)
+    for l in range(L):
+        Wl, bl = np.asarray(Ws[l], dtype=np.float64), np.asarray(bs[l], dtype=np.float64)
+        K = Wl.shape[0]
+        mag = np.abs(h) @ np.abs(Wl) + np.abs(bl)
+        z = h @ Wl + bl
+        if l == 0:
+            dz = _gamma(K + 1) * mag
+        else:
+            dz = _gamma(3 * K + 2) * 1.02 * mag + dh @ np.abs(Wl)
+        if l + 1 < L:
+            h = np.tanh(z)
+            dh = dz + 9.0 * U32 * np.abs(h)
+        else:
+            h, dh = z, dz
+    sig = np.asarray(spec["sigma"], dtype=np.float64)
+    r = (h - np.asarray(spec["data"], dtype=np.float64)) / sig
+    q = dh / sig
+    logL = -0.5 * np.sum(r * r, axis=1)
+    return np.sum(np.abs(r) * q, axis=1) + 0.5 * np.sum(q * q, axis=1) + 1e-12 * np.abs(logL)
+
+
+def _bf16(x):
+    """Round FP32 values to bfloat16 (nearest, ties to even), returned as FP32."""
+    b = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)
+
+
+def _emulator_logL_fp32_model(spec, X):
+    """The intended arithmetic in numpy: FP32 first layer, then per layer the
+    activations split into hi + mid + lo bfloat16 terms, three FP32 products
+    with the bfloat16 weights, FP32 bias and tanh; chi^2 in FP64."""
+    h = np.asarray(X, dtype=np.float32)
+    L = len(spec["weights"])
+    for l in range(L):
+        Wl = np.asarray(spec["weights"][l], dtype=np.float32)
+        bl = np.asarray(spec["biases"][l], dtype=np.float32)
+        if l == 0:
+            z = h @ Wl
+        else:
+            hi = _bf16(h)
+            r1 = (h - hi).astype(np.float32)
+            mid = _bf16(r1)
+            lo = _bf16((r1 - mid).astype(np.float32))
+            z = (lo @ Wl + mid @ Wl + hi @ Wl).astype(np.float32)
+        z = (z + bl).astype(np.float32)
+        h = np.tanh(z).astype(np.float32) if l + 1 < L else z
+    r = (h.astype(np.float64) - spec["data"]) / spec["sigma"]
+    return -0.5 * np.sum(r * r, axis=1)
+
+
+@pytest.mark.parametrize("widths,n", [
+    ((27, 64, 96, 64), 333),            # fragment-major path, ragged rows, several tiles
+    ((27, 512, 512, 512, 1024), 300),   # the 27-d emulator on the fragment-major path
+    ((5, 32, 32, 32, 16), 333),         # output width 16: the generic split path
+])
+def test_emulator_rows_within_error_bound(widths, n):
+    """Every row within the worst-case forward bound, and the error
+    distribution no wider than that of the numpy model of the same arithmetic
+    (a lost bfloat16 term or a misplaced bias widens it by orders of magnitude)."""
+    spec = W.emulator(seed=5, widths=widths, noise_frac=0.05)
+    rng = np.random.default_rng(11)
+    # FP32-representable non-zero biases; data regenerated around theta0
+    spec["biases"] = [rng.normal(0, 0.1, size=w).astype(np.float32).astype(np.float64) for w in widths[1:]]
+    y0 = W._forward_f64(spec["weights"], spec["biases"], spec["theta0"])
+    spec["sigma"] = 0.05 * np.abs(y0)
+    spec["data"] = y0 + rng.normal(size=y0.shape) * spec["sigma"]
+    d = widths[0]
+    near = np.clip(spec["theta0"] + rng.normal(0, 1e-3, size=(n - n // 4, d)), 0, 1)
+    prior = rng.uniform(size=(n // 4, d))
+    u = np.concatenate([near, prior]).astype(np.float32).astype(np.float64)
+    s = native.Sampler(spec, 64, prec="bf16x3", state="f32", seed=0, tree_depth=1)
+    d_u = torch.tensor(u, device=DEV)
+    d_o = torch.zeros(len(u), dtype=torch.float64, device=DEV)
+    native.ns_loglike_batch(s.ctx, d_u, d_o)
+    native.ns_sync(s.ctx)
+    got = d_o.cpu().numpy()
+    s.close()
+    ref = oracle.loglike(spec, u)
+    bound = _emulator_logL_bound(spec, u)
+    err = np.abs(got - ref)
+    model = np.abs(_emulator_logL_fp32_model(spec, u) - ref)
+    k = len(near)
+    print(f"widths {widths}: max |dlogL|/bound = {np.max(err / bound):.3g}; near theta0 median |dlogL| "
+          f"{np.median(err[:k]):.3g} (model {np.median(model[:k]):.3g}), p90 {np.quantile(err[:k], 0.9):.3g} "
+          f"(model {np.quantile(model[:k], 0.9):.3g})")
+    assert np.all(np.isfinite(got))
+    assert np.all(err <= bound)
+    for q in (0.5, 0.9):
+        assert np.quantile(err[:k], q) <= 4.0 * np.quantile(model[:k], q) + 1e-9
+        assert np.quantile(err[k:] / np.abs(ref[k:]), q) <= 4.0 * np.quantile(model[k:] / np.abs(ref[k:]), q) + 1e-15
