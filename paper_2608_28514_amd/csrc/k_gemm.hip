@@ -311,71 +311,27 @@ hipError_t launch_dense_split(int M, int N, int K, const __bf16* A, long aplane,
 }
 
 // ---------------------------------------------------------------------------
-// Emulator likelihood on fragment-major activations.
-//
-// A bfloat16 matrix X[M][K] (K % 32 == 0) is stored in blocks of 16 rows x 32
-// columns, block (rb, kb) at element (rb (K/32) + kb) 512; inside a block the
-// eight columns 8g..8g+7 of row i are 16 contiguous bytes at element
-// (i + 16 g) 8.  A block is exactly the operand fragment of one
-// v_mfma_f32_16x16x32_bf16 (lane i + 16 g holds those 8 values), so each
+// Emulator likelihood on fragment-major activations (frag_index): each
 // operand load of a wave is one contiguous 1 KB read.  Activations travel as
 // three such planes (hi, mid, lo); the transposed weights W^T[N][K] use the
 // same layout (rows = output columns).  Row counts are padded to a multiple
 // of 16; padded rows hold unspecified values and never reach an output.
 
-__device__ __forceinline__ long frag_index(long r, int k, int K) {
-  return ((r >> 4) * (K >> 5) + (k >> 5)) * 512 + ((r & 15) + 16 * ((k & 31) >> 3)) * 8 + (k & 7);
-}
-
-// First layer in FP32 (K0 <= 32 inputs, fused multiply-adds in k order from
-// zero, then + bias and the activation, as k_gemm<kF32>), written as three
-// fragment-major bfloat16 planes of width N (N % 32 == 0).  Eight rows per
-// workgroup; thread t owns columns t, t + 256, ...
-constexpr int kL1Rows = 8;
-
-__global__ void __launch_bounds__(256)
-k_l1_frag(int M, int N, int K0, const float* __restrict__ X, const float* __restrict__ Wt,
-          const float* __restrict__ bias, int act, __bf16* __restrict__ out, long plane,
-          const int* __restrict__ gate, const int* __restrict__ dM) {
-  if (gate && *gate == 0) return;
-  if (dM) M = min(M, *dM);
-  const int r0 = blockIdx.x * kL1Rows;
-  if (r0 >= M) return;
-  __shared__ float xs[kL1Rows * kMaxD];
-  for (int q = threadIdx.x; q < kL1Rows * K0; q += blockDim.x) {
-    const int r = r0 + q / K0;
-    xs[q] = r < M ? X[static_cast<long>(r) * K0 + q % K0] : 0.f;
-  }
-  __syncthreads();
-  for (int c = threadIdx.x; c < N; c += blockDim.x) {
-    float w[kMaxD];
-#pragma unroll
-    for (int k = 0; k < kMaxD; ++k) w[k] = k < K0 ? Wt[static_cast<long>(c) * K0 + k] : 0.f;
-    const float b = bias ? bias[c] : 0.f;
-    for (int rr = 0; rr < kL1Rows && r0 + rr < M; ++rr) {
-      float acc = 0.f;
-#pragma unroll
-      for (int k = 0; k < kMaxD; ++k)
-        if (k < K0) acc = __builtin_fmaf(xs[rr * K0 + k], w[k], acc);
-      const float h = act_fwd(act, acc + b);
-      store_split(out, plane, frag_index(r0 + rr, c, N), h);
-    }
-  }
-}
-
 // One dense layer on split activations: one wave per workgroup computes a
-// 16 x 32 output block as two 16 x 16 MFMA tiles, k in steps of 32 (lo, mid,
-// hi products in that order, as k_dense_split) with the loads of the next two
-// steps in flight.  Hidden layers: act(z) as three fragment-major planes of
+// 16 x 32 output block as two 16 x 16 MFMA tiles, k in steps of 32 with the
+// loads of the next two steps in flight.  WS = 1: bfloat16 weights, products
+// lo, mid, hi in that order (as k_dense_split); WS = 3 (the first layer, whose
+// FP32 weights are split like the activations): the nine products of the
+// activation and weight terms, smallest first.  Hidden layers: act(z) as three fragment-major planes of
 // width N (transposed through LDS, 16-byte stores).  CHI2: the output layer;
 // instead of storing y = z, every row's sum over the block's 32 columns of
-// ((y - data) isig)^2 (FP64) goes to part[r (N/32) + block column].
-template <bool CHI2>
+// ((y - data) isig)^2 (FP64) goes to part[block column * pstride + r].
+template <bool CHI2, int WS>
 __global__ void __launch_bounds__(64)
 k_dense_frag(int M, int N, int K, const __bf16* __restrict__ A, long aplane, const __bf16* __restrict__ Wf,
-             const float* __restrict__ bias, int act, __bf16* __restrict__ out, long cplane,
+             long wplane, const float* __restrict__ bias, int act, __bf16* __restrict__ out, long cplane,
              const double* __restrict__ data, const double* __restrict__ isig, double* __restrict__ part,
-             const int* __restrict__ gate, const int* __restrict__ dM) {
+             long pstride, const int* __restrict__ gate, const int* __restrict__ dM) {
   if (gate && *gate == 0) return;
   if (dM) M = min(M, *dM);
   const int nbc = N >> 5;
@@ -387,22 +343,29 @@ k_dense_frag(int M, int N, int K, const __bf16* __restrict__ A, long aplane, con
   const __bf16* bp0 = Wf + static_cast<long>(2 * cb) * S * 512 + lane * 8;
   const __bf16* bp1 = bp0 + static_cast<long>(S) * 512;
   f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-  bf16x8 a0[3], a1[3], a2[3], b0[2], b1[2], b2[2];
+  bf16x8 a0[3], a1[3], a2[3], b0[2 * WS], b1[2 * WS], b2[2 * WS];
   auto load = [&](int s, bf16x8* a, bf16x8* b) {
     const long o = static_cast<long>(s) * 512;
     a[0] = *reinterpret_cast<const bf16x8*>(ap + o);
     a[1] = *reinterpret_cast<const bf16x8*>(ap + aplane + o);
     a[2] = *reinterpret_cast<const bf16x8*>(ap + 2 * aplane + o);
-    b[0] = *reinterpret_cast<const bf16x8*>(bp0 + o);
-    b[1] = *reinterpret_cast<const bf16x8*>(bp1 + o);
+#pragma unroll
+    for (int q = 0; q < WS; ++q) {
+      b[2 * q] = *reinterpret_cast<const bf16x8*>(bp0 + q * wplane + o);
+      b[2 * q + 1] = *reinterpret_cast<const bf16x8*>(bp1 + q * wplane + o);
+    }
   };
   auto step = [&](const bf16x8* a, const bf16x8* b) {
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], acc0, 0, 0, 0);
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], acc0, 0, 0, 0);
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[1], acc1, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], acc1, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], acc1, 0, 0, 0);
+    // term pairs (activation pa, weight pb) by decreasing pa + pb, then pa
+#pragma unroll
+    for (int sum = 2 + WS - 1; sum >= 0; --sum)
+#pragma unroll
+      for (int pa = 2; pa >= 0; --pa) {
+        const int pb = sum - pa;
+        if (pb < 0 || pb >= WS) continue;
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[pa], b[2 * pb], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[pa], b[2 * pb + 1], acc1, 0, 0, 0);
+      }
   };
   load(0, a0, b0);
   if (S > 1) load(1, a1, b1);
@@ -427,7 +390,7 @@ k_dense_frag(int M, int N, int K, const __bf16* __restrict__ A, long aplane, con
       double t = e0 * e0 + e1 * e1;
       for (int o = 8; o > 0; o >>= 1) t += __shfl_xor(t, o);
       const int r = rb * 16 + 4 * (lane >> 4) + i;
-      if ((lane & 15) == 0 && r < M) part[static_cast<long>(r) * nbc + cb] = t;
+      if ((lane & 15) == 0 && r < M) part[static_cast<long>(cb) * pstride + r] = t;
     }
   } else {
     __shared__ __attribute__((aligned(16))) __bf16 tile[3][16][32 + 8];
@@ -452,67 +415,129 @@ k_dense_frag(int M, int N, int K, const __bf16* __restrict__ A, long aplane, con
   }
 }
 
-// logL[r] = -1/2 sum_q part[r nb + q] (q ascending); NaN -> -inf.
-__global__ void k_chi2_sum(int M, int nb, const double* __restrict__ part, double* __restrict__ logL,
+// logL[r] = -1/2 sum_q part[q pstride + r] (q ascending); NaN -> -inf.
+__global__ void k_chi2_sum(int M, int nb, const double* __restrict__ part, long pstride, double* __restrict__ logL,
                            const int* __restrict__ gate, const int* __restrict__ dM) {
   if (gate && *gate == 0) return;
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= M || (dM && r >= *dM)) return;
+  // loads in groups of eight ahead of the (in-order) additions
   double t = 0.0;
-  for (int q = 0; q < nb; ++q) t += part[static_cast<long>(r) * nb + q];
+  for (int q0 = 0; q0 < nb; q0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = part[min(q0 + j, nb - 1) * pstride + r];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (q0 + j < nb) t += v[j];
+  }
   const double v = -0.5 * t;
   logL[r] = isnan(v) ? -INFINITY : v;
 }
 
+// Direct rounds: compacted row i (i < *crows) belongs to row cmap[i/P] P + i%P
+// of the round; its logL is -1/2 sum_q part[q pstride + i] (q ascending; NaN
+// -> -inf), or -inf when that row's flag is 0.  Adds the compacted row count
+// to *net_rows.
+__global__ void k_chi2_rows(int P, const double* __restrict__ part, int nb, long pstride,
+                            const int* __restrict__ crows, const int* __restrict__ cmap,
+                            const int* __restrict__ flag, double* __restrict__ rlogL,
+                            unsigned long long* __restrict__ net_rows, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int n = *crows;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && net_rows) *net_rows += static_cast<unsigned long long>(n);
+  if (i >= n) return;
+  const long r = static_cast<long>(cmap[i / P]) * P + i % P;
+  double t = 0.0;
+  for (int q0 = 0; q0 < nb; q0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = part[min(q0 + j, nb - 1) * pstride + i];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (q0 + j < nb) t += v[j];
+  }
+  const double v = -0.5 * t;
+  rlogL[r] = (flag[r] == 0 || isnan(v)) ? -INFINITY : v;
+}
+
+hipError_t launch_chi2_rows(int M, int P, int nb, const double* part, const int* crows, const int* cmap,
+                            const int* flag, double* rlogL, unsigned long long* net_rows, const int* gate,
+                            hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_chi2_rows, dim3((M + 255) / 256), dim3(256), 0, s, P, part, nb, static_cast<long>(M), crows,
+                     cmap, flag, rlogL, net_rows, gate);
+  return hipGetLastError();
+}
+
 bool emu_frag_eligible(const NetDev& net, int mode_first, int mode_rest) {
-  if (mode_first != kF32 || mode_rest != kBF16S || net.n_layers < 2 || net.widths[0] > kMaxD) return false;
+  if (mode_first != kF32 || mode_rest != kBF16S || net.n_layers < 2 || net.widths[0] > 32) return false;
   for (int l = 1; l <= net.n_layers; ++l)
     if (net.widths[l] % 32 != 0) return false;
-  for (int l = 1; l < net.n_layers; ++l)
+  for (int l = 0; l < net.n_layers; ++l)
     if (!net.Wf[l]) return false;
   return true;
 }
 
 long emu_frag_plane(long M, int max_width) { return (M + 15) / 16 * 16 * max_width; }
 
-hipError_t emu_forward_logL(const NetDev& net, int M, const float* X, __bf16* P0, __bf16* P1, double* part,
-                            const double* data, const double* isig, double* logL, const int* gate,
+hipError_t emu_forward_logL(const NetDev& net, int M, const __bf16* Xf, long xplane, __bf16* P0, __bf16* P1,
+                            double* part, const double* data, const double* isig, double* logL, const int* gate,
                             const int* dM, hipStream_t s) {
   if (M <= 0) return hipSuccess;
   const long plane = emu_frag_plane(M, net.max_width);
   const int L = net.n_layers;
-  hipLaunchKernelGGL(k_l1_frag, dim3((M + kL1Rows - 1) / kL1Rows), dim3(256), 0, s, M, net.widths[1],
-                     net.widths[0], X, net.Wt[0], net.b[0], net.act, P0, plane, gate, dM);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  __bf16* in = P0;
-  __bf16* out = P1;
   const int rbs = (M + 15) / 16;
-  for (int l = 1; l < L; ++l) {
-    const int K = net.widths[l], N = net.widths[l + 1];
+  const __bf16* in = Xf;
+  long inplane = xplane;
+  __bf16* out = P0;
+  for (int l = 0; l < L; ++l) {
+    const int K = l == 0 ? 32 : net.widths[l], N = net.widths[l + 1];
     const dim3 grid(static_cast<unsigned>(rbs * (N / 32)));
-    if (l < L - 1) {
-      hipLaunchKernelGGL(k_dense_frag<false>, grid, dim3(64), 0, s, M, N, K, in, plane, net.Wf[l], net.b[l],
-                         net.act, out, plane, nullptr, nullptr, nullptr, gate, dM);
-      std::swap(in, out);
+    if (l == 0) {
+      hipLaunchKernelGGL((k_dense_frag<false, 3>), grid, dim3(64), 0, s, M, N, K, in, inplane, net.Wf[0],
+                         static_cast<long>(N) * 32, net.b[0], net.act, out, plane, nullptr, nullptr, nullptr, 0L,
+                         gate, dM);
+    } else if (l < L - 1) {
+      hipLaunchKernelGGL((k_dense_frag<false, 1>), grid, dim3(64), 0, s, M, N, K, in, inplane, net.Wf[l], 0L,
+                         net.b[l], net.act, out, plane, nullptr, nullptr, nullptr, 0L, gate, dM);
     } else {
-      hipLaunchKernelGGL(k_dense_frag<true>, grid, dim3(64), 0, s, M, N, K, in, plane, net.Wf[l], net.b[l],
-                         kActNone, nullptr, 0L, data, isig, part, gate, dM);
+      hipLaunchKernelGGL((k_dense_frag<true, 1>), grid, dim3(64), 0, s, M, N, K, in, inplane, net.Wf[l], 0L,
+                         net.b[l], kActNone, nullptr, 0L, data, isig, part, static_cast<long>(M), gate, dM);
     }
-    e = hipGetLastError();
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (l < L - 1) {
+      in = out;
+      inplane = plane;
+      out = (out == P0) ? P1 : P0;
+    }
   }
-  hipLaunchKernelGGL(k_chi2_sum, dim3((M + 255) / 256), dim3(256), 0, s, M, net.widths[L] / 32, part, logL,
-                     gate, dM);
+  if (!logL) return hipSuccess;   // the caller sums the partials (launch_scatter)
+  hipLaunchKernelGGL(k_chi2_sum, dim3((M + 255) / 256), dim3(256), 0, s, M, net.widths[L] / 32, part,
+                     static_cast<long>(M), logL, gate, dM);
   return hipGetLastError();
 }
 
 void frag_layout_host(const float* Wt, int N, int K, __bf16* out) {
   for (int n = 0; n < N; ++n)
-    for (int k = 0; k < K; ++k) {
-      const long idx = ((static_cast<long>(n) >> 4) * (K >> 5) + (k >> 5)) * 512 + ((n & 15) + 16 * ((k & 31) >> 3)) * 8 +
-                       (k & 7);
-      out[idx] = static_cast<__bf16>(Wt[static_cast<long>(n) * K + k]);
+    for (int k = 0; k < K; ++k) out[frag_index(n, k, K)] = static_cast<__bf16>(Wt[static_cast<long>(n) * K + k]);
+}
+
+void frag_split_host(const float* Wt, int N, int K0, __bf16* out) {
+  const long plane = static_cast<long>(N) * 32;
+  for (long q = 0; q < 3 * plane; ++q) out[q] = static_cast<__bf16>(0.f);
+  for (int n = 0; n < N; ++n)
+    for (int k = 0; k < K0; ++k) {
+      const float x = Wt[static_cast<long>(n) * K0 + k];
+      const __bf16 h = static_cast<__bf16>(x);
+      const float r1 = x - static_cast<float>(h);
+      const __bf16 m = static_cast<__bf16>(r1);
+      const long idx = frag_index(n, k, 32);
+      out[idx] = h;
+      out[plane + idx] = m;
+      out[2 * plane + idx] = static_cast<__bf16>(r1 - static_cast<float>(m));
     }
 }
 

@@ -27,20 +27,38 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
                  double* __restrict__ rthr, const int* __restrict__ sflag,
                  int* __restrict__ gate, T* __restrict__ new_u, double* __restrict__ new_logL,
                  int* __restrict__ chain_stat, double* __restrict__ hist_logL,
-                 T* __restrict__ hist_u, int* __restrict__ hist_n, const RunState* __restrict__ st) {
-  if (st->done) return;
-  if (round > 0 && gate[round - 1] == 0) return;   // every chain finished earlier
+                 T* __restrict__ hist_u, int* __restrict__ hist_n, const RunState* __restrict__ st,
+                 __bf16* __restrict__ xf, long xfplane, int* __restrict__ crows, int* __restrict__ cmap) {
+  // Everything the round reads from memory is loaded at once: run and round
+  // flags, thresholds, the chain state words and this chain's P result rows
+  // (a load behind a branch on an earlier one would wait for it).
+  constexpr int kWords = static_cast<int>(sizeof(ChainState<T>) / 4);
+  constexpr int kSW = (kWords + 63) / 64;
   const int j = blockIdx.x, lane = threadIdx.x;
   const int d = p.d, m = p.m, TH = p.T, P = p.P;
+  const long row0 = static_cast<long>(j) * P;
+  const int run_done = st->done, prev_gate = gate[round > 0 ? round - 1 : 0];
   const uint32_t step = static_cast<uint32_t>(st->step);
+  const double tau_j = tau[j], tau_e = LW[0];
+  int sw[kSW];
+  int fl = 0, sf = 0;
+  double rl = -INFINITY;
+  if (round > 0) {
+    const int* src = reinterpret_cast<const int*>(&cs[j]);
+#pragma unroll
+    for (int i = 0; i < kSW; ++i) sw[i] = src[min(lane + 64 * i, kWords - 1)];
+    const long rr = row0 + min(lane, P - 1);   // rows past the chain's block are never used
+    fl = flag[rr];
+    sf = sflag ? sflag[rr] : 0;
+    rl = rlogL[rr];
+  }
+  if (run_done) return;
+  if (round > 0 && prev_gate == 0) return;   // every chain finished earlier
   __shared__ ChainState<T> S;
   __shared__ T zs[kMaxD];
   __shared__ T Ls[kMaxD * kMaxD];
   __shared__ T Us[64];
   const T w = static_cast<T>(p.w);
-  const double tau_j = tau[j], tau_e = LW[0];
-  const long row0 = static_cast<long>(j) * P;
-  constexpr int kWords = static_cast<int>(sizeof(ChainState<T>) / 4);
 
   if (round == 0) {
     if (lane == 0) {
@@ -53,13 +71,24 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
     __syncthreads();
     if (lane < d) S.x[lane] = u[static_cast<long>(S.seed_slot) * d + lane];
   } else {
-    const int* src = reinterpret_cast<const int*>(&cs[j]);
     int* dst = reinterpret_cast<int*>(&S);
-    for (int q = lane; q < kWords; q += 64) dst[q] = src[q];
+#pragma unroll
+    for (int i = 0; i < kSW; ++i)
+      if (lane + 64 * i < kWords) dst[lane + 64 * i] = sw[i];
   }
   __syncthreads();
-  const T* Lc = chol + static_cast<long>(S.label) * kMaxD * kMaxD;
-  for (int q = lane; q < d * kMaxD; q += 64) Ls[q] = Lc[q];
+  // A new direction (after an accepted shrink, or at the start) needs the
+  // cluster's Cholesky rows: their loads are issued now and overlap the
+  // consume step.
+  constexpr int kLq = (kMaxD * kMaxD) / 64;
+  T lreg[kLq];
+  const bool lpre = S.phase != kPhaseStepout;
+  if (lpre) {
+    const T* Lc = chol + static_cast<long>(S.label) * kMaxD * kMaxD;
+    const int tot = d * kMaxD;
+#pragma unroll
+    for (int q = 0; q < kLq; ++q) lreg[q] = Lc[min(lane + 64 * q, tot - 1)];
+  }
 
   // ---------------------------------------------------------------- consume
   if (round > 0 && S.phase == kPhaseStepout) {
@@ -67,9 +96,9 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
     const bool left = lane < E;
     const int k = S.base + (left ? lane : lane - E);
     const bool active = lane < 2 * E && (left ? S.ka < 0 : S.kb < 0) && k < p.max_stepout;
-    const bool inb = active && flag[row0 + lane] != 0;
-    const bool scr = inb && sflag && sflag[row0 + lane] != 0;   // screened: predicted to fail
-    const bool pass = inb && !scr && rlogL[row0 + lane] > tau_e;
+    const bool inb = active && fl != 0;
+    const bool scr = inb && sf != 0;   // screened: predicted to fail
+    const bool pass = inb && !scr && rl > tau_e;
     const uint64_t mp = __ballot(pass);
     const uint64_t mo = __ballot(active && !inb);
     const uint64_t ms = __ballot(scr);
@@ -113,9 +142,9 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
   } else if (round > 0 && S.phase == kPhaseShrink) {
     const int Sn = min(p.sh_spec, p.max_shrink - S.s0);
     const bool mine = lane < Sn;
-    const bool inb = mine && flag[row0 + lane] != 0;
-    const bool scr = inb && sflag && sflag[row0 + lane] != 0;
-    const double l = (inb && !scr) ? rlogL[row0 + lane] : -INFINITY;
+    const bool inb = mine && fl != 0;
+    const bool scr = inb && sf != 0;
+    const double l = (inb && !scr) ? rl : -INFINITY;
     const bool pass = mine && l > tau_j;
     const uint64_t mp = __ballot(pass);
     const uint64_t mi = __ballot(inb && !scr);
@@ -123,15 +152,38 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
     const int upto = mp ? __builtin_ctzll(mp) : Sn - 1;
     const uint64_t taken = (upto >= 63) ? ~0ull : ((2ull << upto) - 1ull);
     const bool last = (S.it == p.n_iter - 1);
-    if (last && lane <= upto && S.s0 + lane < TH - 1) {
-      const int slot = S.s0 + lane;
-      hist_logL[static_cast<long>(slot) * m + j] = l;
-      T* hu = hist_u + (static_cast<long>(j) * TH + slot) * d;
-      for (int i = 0; i < d; ++i) hu[i] = pts[(row0 + lane) * d + i];
+    if (last) {
+      // the rows up to the accepted one (at most TH - 1 slots), copied by all lanes
+      const int nh = min(upto + 1, TH - 1 - S.s0);
+      if (lane < nh) hist_logL[static_cast<long>(S.s0 + lane) * m + j] = l;
+      const int tot = nh * d;
+      T* hu = hist_u + (static_cast<long>(j) * TH + S.s0) * d;
+      const T* src = pts + row0 * d;
+      for (int e0 = lane; e0 < tot; e0 += 8 * 64) {
+        T v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = src[min(e0 + 64 * q, tot - 1)];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (e0 + 64 * q < tot) hu[e0 + 64 * q] = v[q];
+      }
     }
-    if (mp && lane == upto) {
-      for (int i = 0; i < d; ++i) S.x[i] = pts[(row0 + lane) * d + i];
-      S.lx = l;
+    if (mp) {
+      // the accepted point, recomputed from the chain's line exactly as it was
+      // proposed (same draws, same bracket recurrence, same expression)
+      const uint32_t c3 = (kStreamSlice << 24) | static_cast<uint32_t>(S.it);
+      if (lane <= upto) {
+        const Draw2 du = uniform2(p.seed, kSlotShrink0 + S.s0 + lane, static_cast<uint32_t>(j), step, c3);
+        Us[lane] = static_cast<T>(du.a);
+      }
+      __syncthreads();
+      T aa = S.a, bb = S.b, t = T(0);
+      for (int q = 0; q <= upto; ++q) {
+        t = aa + Us[q] * (bb - aa);
+        if (t < T(0)) aa = t; else bb = t;
+      }
+      if (lane < d) S.x[lane] = S.x[lane] + t * S.v[lane];
+      if (lane == upto) S.lx = l;
     }
     __syncthreads();
     if (lane == 0) {
@@ -175,6 +227,19 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
 
   // ---------------------------------------------------------------- propose
   if (S.phase == kPhaseDir) {
+    // the Cholesky rows loaded above (the phase was Dir or Shrink at entry,
+    // the only ones that lead here)
+    {
+      const int tot = d * kMaxD;
+      if (!lpre) {
+        const T* Lc = chol + static_cast<long>(S.label) * kMaxD * kMaxD;
+#pragma unroll
+        for (int q = 0; q < kLq; ++q) lreg[q] = Lc[min(lane + 64 * q, tot - 1)];
+      }
+#pragma unroll
+      for (int q = 0; q < kLq; ++q)
+        if (lane + 64 * q < tot) Ls[lane + 64 * q] = lreg[q];
+    }
     const uint32_t c3 = (kStreamSlice << 24) | static_cast<uint32_t>(S.it);
     if (2 * lane < d) {
       const Draw2 dr = uniform2(p.seed, kSlotDir0 + lane, static_cast<uint32_t>(j), step, c3);
@@ -234,16 +299,50 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
       if (lane == Sn - 1) { S.br_a = aa; S.br_b = bb; }
     }
   }
+  __shared__ T s_toff[64];
+  __shared__ int s_has[64];
+  __shared__ int s_crow;
   if (lane < P) {
     const long r = row0 + lane;
     flag[r] = inb ? 1 : 0;
     if (rthr) rthr[r] = (S.phase == kPhaseStepout) ? tau_e : tau_j;
-    if (has)
-      for (int i = 0; i < d; ++i) {
-        const T yi = S.x[i] + toff * S.v[i];
-        pts[r * d + i] = yi;
-        xin[r * d + i] = p.lo_f[i] + p.span_f[i] * static_cast<float>(yi);
+    s_toff[lane] = toff;
+    s_has[lane] = has ? 1 : 0;
+  }
+  // xf set: this chain's P rows also go, as the network input in three
+  // bfloat16 terms, to P compacted rows of the fragment-major planes, at a
+  // position taken with one atomic per chain that has a row to evaluate
+  // (cmap: position / P -> chain).  Each row's likelihood depends only on its
+  // own input, so the placement changes no result.
+  if (xf) {
+    const uint64_t any = __ballot(lane < P && inb);
+    if (lane == 0) {
+      s_crow = -1;
+      if (any) {
+        s_crow = atomicAdd(&crows[round], P);
+        cmap[s_crow / P] = j;
       }
+    }
+  }
+  __syncthreads();
+  // the rows' points: lanes over (row, coordinate) pairs
+  for (int e = lane; e < P * d; e += 64) {
+    const int q = e / d, i = e - q * d;
+    if (!s_has[q]) continue;
+    const T yi = S.x[i] + s_toff[q] * S.v[i];
+    const long r = row0 + q;
+    pts[r * d + i] = yi;
+    const float xv = p.lo_f[i] + p.span_f[i] * static_cast<float>(yi);
+    xin[r * d + i] = xv;
+    if (xf && s_crow >= 0) {
+      const long fi = frag_index(s_crow + q, i, 32);
+      const __bf16 h = static_cast<__bf16>(xv);
+      const float r1 = xv - static_cast<float>(h);
+      const __bf16 mm = static_cast<__bf16>(r1);
+      xf[fi] = h;
+      xf[xfplane + fi] = mm;
+      xf[2 * xfplane + fi] = static_cast<__bf16>(r1 - static_cast<float>(mm));
+    }
   }
   __syncthreads();
   if (lane == 0 && S.phase != kPhaseDone) atomicOr(&gate[round], 1);
@@ -272,14 +371,16 @@ hipError_t launch_rounds_advance(int round, const RoundsParams& p, const Shape& 
                        static_cast<const float*>(b.u), b.logL, b.label, b.chol_f, b.seeds, b.tau, b.LW,
                        static_cast<ChainState<float>*>(r.cs), static_cast<float*>(r.pts), r.xin, r.flag,
                        r.rlogL, r.rthr, r.sflag, r.gate, static_cast<float*>(b.new_u), b.new_logL, b.chain_stat,
-                       b.hist_logL, static_cast<float*>(b.hist_u), b.hist_n, b.st);
+                       b.hist_logL, static_cast<float*>(b.hist_u), b.hist_n, b.st, r.xf_direct, r.xf_plane,
+                       r.crows, r.cmap);
   else
     hipLaunchKernelGGL(k_rounds_advance<double>, dim3(p.m), dim3(64), 0, s, round, p,
                        static_cast<const double*>(b.u), b.logL, b.label, b.chol, b.seeds, b.tau, b.LW,
                        static_cast<ChainState<double>*>(r.cs), static_cast<double*>(r.pts), r.xin,
                        r.flag, r.rlogL, r.rthr, r.sflag, r.gate, static_cast<double*>(b.new_u), b.new_logL,
                        b.chain_stat,
-                       b.hist_logL, static_cast<double*>(b.hist_u), b.hist_n, b.st);
+                       b.hist_logL, static_cast<double*>(b.hist_u), b.hist_n, b.st, r.xf_direct,
+                       r.xf_plane, r.crows, r.cmap);
   return hipGetLastError();
 }
 

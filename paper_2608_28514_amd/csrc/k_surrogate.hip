@@ -92,7 +92,8 @@ __global__ void __launch_bounds__(kSC)
 k_screen_write(int M, int d, int screening, double margin, int audit_period, const int* __restrict__ flag,
                const double* __restrict__ rthr, const float* __restrict__ yhat, const float* __restrict__ norm,
                const float* __restrict__ xin, const int* __restrict__ chunk_cnt, int* __restrict__ sflag,
-               int* __restrict__ idx, int* __restrict__ aud, float* __restrict__ xc, int* __restrict__ count,
+               int* __restrict__ idx, int* __restrict__ aud, float* __restrict__ xc, __bf16* __restrict__ xf,
+               long xfplane, int* __restrict__ count,
                double* __restrict__ rlogL, SurrCounters* __restrict__ sc, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
   __shared__ int wave_tot[kSC / 64];
@@ -102,22 +103,38 @@ k_screen_write(int M, int d, int screening, double margin, int audit_period, con
   const int nchunk = (M + kSC - 1) / kSC;
   const unsigned long long sbase = sc->screened_seen;
   const long long period = audit_period;
-  if (threadIdx.x == 0) {
-    long long ps = 0, pe = 0, ts = 0, te = 0;
-    for (int c = 0; c < nchunk; ++c) {
-      const int ni = chunk_cnt[2 * c], ns = chunk_cnt[2 * c + 1];
-      const long long ev = (ni - ns) + audits_in(sbase, ts, ns, period);
-      if (c == static_cast<int>(blockIdx.x)) { ps = ts; pe = te; }
-      ts += ns;
-      te += ev;
+  if (threadIdx.x < 64) {
+    // prefix over the chunks, 64 at a time (one lane each): screened rows
+    // before each chunk, then the rows it evaluates (audits in closed form)
+    const int lane = threadIdx.x;
+    int carry_s = 0, carry_e = 0;
+    for (int c0 = 0; c0 < nchunk; c0 += 64) {
+      const int c = c0 + lane;
+      const int ni = c < nchunk ? chunk_cnt[2 * c] : 0, ns = c < nchunk ? chunk_cnt[2 * c + 1] : 0;
+      int is = ns;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(is, o);
+        if (lane >= o) is += t;
+      }
+      const int ts = carry_s + is - ns;
+      const int ev = c < nchunk ? (ni - ns) + static_cast<int>(audits_in(sbase, ts, ns, period)) : 0;
+      int ie = ev;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(ie, o);
+        if (lane >= o) ie += t;
+      }
+      if (c == static_cast<int>(blockIdx.x)) {
+        s_off[0] = ts;
+        s_off[1] = carry_e + ie - ev;
+      }
+      carry_s += __shfl(is, 63);
+      carry_e += __shfl(ie, 63);
     }
-    s_off[0] = ps;
-    s_off[1] = pe;
     // count[0]: rows to evaluate; count[1]: rows screened by this call (added
     // to the running total by k_scatter, after every chunk has read it)
-    if (blockIdx.x == 0) {
-      count[0] = static_cast<int>(te);
-      count[1] = static_cast<int>(ts);
+    if (blockIdx.x == 0 && lane == 0) {
+      count[0] = carry_e;
+      count[1] = carry_s;
     }
   }
   __syncthreads();
@@ -143,16 +160,63 @@ k_screen_write(int M, int d, int screening, double margin, int audit_period, con
   __syncthreads();
   // the chunk's evaluated rows, coordinates in order (consecutive threads read
   // consecutive coordinates of a row)
-  for (int e = threadIdx.x; e < n_eval * d; e += kSC) {
-    const int k = e / d, q = e - k * d;
-    xc[(base + k) * d + q] = xin[static_cast<long>(s_rows[k]) * d + q];
+  // (eight loads in flight per thread before their stores)
+  const int tot = n_eval * d;
+  for (int e0 = threadIdx.x; e0 < tot; e0 += 8 * kSC) {
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = min(e0 + j * kSC, tot - 1), k = e / d;
+      v[j] = xin[static_cast<long>(s_rows[k]) * d + (e - k * d)];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = e0 + j * kSC;
+      if (e < tot) xc[base * d + e] = v[j];
+    }
+  }
+  if (!xf) return;
+  // the network input as three bfloat16 terms, fragment-major with 32 columns:
+  // one item = 8 consecutive coordinates of a row (zero past d), 16-byte stores
+  typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
+  const int oct = (d + 7) >> 3, nit = n_eval * oct;
+  for (int i0 = threadIdx.x; i0 < nit; i0 += 4 * kSC) {
+    float v[4][8];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int it = min(i0 + a * kSC, nit - 1), k = it / oct, g = it - k * oct;
+      const float* row = xin + static_cast<long>(s_rows[k]) * d;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[a][e] = row[min(8 * g + e, d - 1)];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int it = i0 + a * kSC;
+      if (it >= nit) continue;
+      const int k = it / oct, g = it - k * oct;
+      bf16x8_t h, mm, lo;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float x = 8 * g + e < d ? v[a][e] : 0.f;
+        const __bf16 hh = static_cast<__bf16>(x);
+        const float r1 = x - static_cast<float>(hh);
+        const __bf16 m = static_cast<__bf16>(r1);
+        h[e] = hh;
+        mm[e] = m;
+        lo[e] = static_cast<__bf16>(r1 - static_cast<float>(m));
+      }
+      const long fi = frag_index(base + k, 8 * g, 32);
+      *reinterpret_cast<bf16x8_t*>(xf + fi) = h;
+      *reinterpret_cast<bf16x8_t*>(xf + xfplane + fi) = mm;
+      *reinterpret_cast<bf16x8_t*>(xf + 2 * xfplane + fi) = lo;
+    }
   }
 }
 
 hipError_t launch_screen(int M, int d, int screening, double margin, int audit_period, const int* flag,
                          const double* rthr, const float* yhat, const float* norm, const float* xin,
-                         int* sflag, int* idx, int* aud, float* xc, int* count, double* rlogL,
-                         SurrCounters* sc, int* chunk_cnt, const int* gate, hipStream_t s) {
+                         int* sflag, int* idx, int* aud, float* xc, __bf16* xf, long xfplane, int* count,
+                         double* rlogL, SurrCounters* sc, int* chunk_cnt, const int* gate, hipStream_t s) {
   if (M <= 0) return hipSuccess;
   const int nchunk = (M + kSC - 1) / kSC;
   hipLaunchKernelGGL(k_screen_count, dim3(nchunk), dim3(kSC), 0, s, M, screening, margin, flag, rthr, yhat,
@@ -160,7 +224,8 @@ hipError_t launch_screen(int M, int d, int screening, double margin, int audit_p
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_screen_write, dim3(nchunk), dim3(kSC), 0, s, M, d, screening, margin, audit_period,
-                     flag, rthr, yhat, norm, xin, chunk_cnt, sflag, idx, aud, xc, count, rlogL, sc, gate);
+                     flag, rthr, yhat, norm, xin, chunk_cnt, sflag, idx, aud, xc, xf, xfplane, count, rlogL, sc,
+                     gate);
   return hipGetLastError();
 }
 
@@ -169,7 +234,8 @@ hipError_t launch_screen(int M, int d, int screening, double margin, int audit_p
 // position sc->pairs, which k_scatter_final advances afterwards.
 __global__ void __launch_bounds__(kSC)
 k_scatter(int d, const int* __restrict__ count, const int* __restrict__ idx, const int* __restrict__ aud,
-          const double* __restrict__ clogL, const double* __restrict__ rthr, const float* __restrict__ xc,
+          const double* __restrict__ clogL, const double* __restrict__ part, int nb, long pstride,
+          const double* __restrict__ rthr, const float* __restrict__ xc,
           double* __restrict__ rlogL, float* __restrict__ rep_x, double* __restrict__ rep_y, long cap,
           SurrCounters* __restrict__ sc, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
@@ -184,7 +250,23 @@ k_scatter(int d, const int* __restrict__ count, const int* __restrict__ idx, con
   const int i = i0 + threadIdx.x;
   if (i < i1) {
     const int r = idx[i];
-    const double l = clogL[i];
+    double l;
+    if (part) {
+      // chi^2 column-block partials of compacted row i, summed in block order
+      double t = 0.0;
+      for (int q0 = 0; q0 < nb; q0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = part[min(q0 + j, nb - 1) * pstride + i];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (q0 + j < nb) t += v[j];
+      }
+      const double v = -0.5 * t;
+      l = isnan(v) ? -INFINITY : v;
+    } else {
+      l = clogL[i];
+    }
     rlogL[r] = l;
     if (aud[i]) {
       atomicAdd(&s_aud, 1);
@@ -192,12 +274,22 @@ k_scatter(int d, const int* __restrict__ count, const int* __restrict__ idx, con
     }
     if (cap > 0) rep_y[static_cast<long>((base + i) % static_cast<unsigned long long>(cap))] = l;
   }
-  if (cap > 0)
-    for (int e = threadIdx.x; e < (i1 - i0) * d; e += kSC) {
-      const int k = e / d, q = e - k * d;
-      const long pos = static_cast<long>((base + i0 + k) % static_cast<unsigned long long>(cap));
-      rep_x[pos * d + q] = xc[static_cast<long>(i0 + k) * d + q];
+  if (cap > 0) {
+    const int tot = (i1 - i0) * d;
+    for (int e0 = threadIdx.x; e0 < tot; e0 += 8 * kSC) {
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = xc[static_cast<long>(i0) * d + min(e0 + j * kSC, tot - 1)];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = e0 + j * kSC;
+        if (e >= tot) continue;
+        const int k = e / d, q = e - k * d;
+        const long pos = static_cast<long>((base + i0 + k) % static_cast<unsigned long long>(cap));
+        rep_x[pos * d + q] = v[j];
+      }
     }
+  }
   __syncthreads();
   // integer counts: the same totals whatever the order of the chunks
   if (threadIdx.x == 0 && s_aud) atomicAdd(&sc->audited, static_cast<unsigned long long>(s_aud));
@@ -217,11 +309,12 @@ __global__ void k_scatter_final(const int* __restrict__ count, long cap, SurrCou
 }
 
 hipError_t launch_scatter(int M, int d, const int* count, const int* idx, const int* aud, const double* clogL,
-                          const double* rthr, const float* xc, double* rlogL, float* rep_x, double* rep_y,
-                          long cap, SurrCounters* sc, const int* gate, hipStream_t s) {
+                          const double* part, int nb, const double* rthr, const float* xc, double* rlogL,
+                          float* rep_x, double* rep_y, long cap, SurrCounters* sc, const int* gate,
+                          hipStream_t s) {
   if (M <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scatter, dim3((M + kSC - 1) / kSC), dim3(kSC), 0, s, d, count, idx, aud, clogL, rthr,
-                     xc, rlogL, rep_x, rep_y, cap, sc, gate);
+  hipLaunchKernelGGL(k_scatter, dim3((M + kSC - 1) / kSC), dim3(kSC), 0, s, d, count, idx, aud, clogL, part, nb,
+                     static_cast<long>(M), rthr, xc, rlogL, rep_x, rep_y, cap, sc, gate);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_scatter_final, dim3(1), dim3(64), 0, s, count, cap, sc, gate);

@@ -62,6 +62,8 @@ struct ns_ctx {
   int* d_idx = nullptr;
   int* d_aud = nullptr;
   float* d_xc = nullptr;
+  __bf16* d_xf = nullptr;     // compacted inputs, fragment-major split planes (emu_forward_logL)
+  long xf_plane = 0;
   double* d_clogL = nullptr;
   float* d_yhat = nullptr;
   bool surr = false, screening = false, surr_disabled = false;
@@ -229,8 +231,8 @@ static void free_all(ns_ctx* c) {
                   b.chain_stat, b.hist_logL, b.hist_u, b.hist_n, b.draws, b.nodeof, b.count,
                   b.accepted, b.split_ok, b.logV, b.logV_eff, b.centre, b.cov, b.chol, b.chol_f,
                   b.dead_u, b.dead_logL, b.st, c->d_out3, c->rb.cs, c->rb.pts, c->rb.xin,
-                  c->rb.flag, c->rb.rlogL, c->rb.gate, c->rb.H0, c->rb.H1, c->rb.Y, c->rb.rthr,
-                  c->rb.sflag, c->d_sc, c->d_count, c->d_chunk, c->d_idx, c->d_aud, c->d_xc, c->d_clogL,
+                  c->rb.flag, c->rb.rlogL, c->rb.gate, c->rb.crows, c->rb.cmap, c->rb.H0, c->rb.H1, c->rb.Y, c->rb.rthr,
+                  c->rb.sflag, c->d_sc, c->d_count, c->d_chunk, c->d_idx, c->d_aud, c->d_xc, c->d_xf, c->d_clogL,
                   c->d_yhat, c->sP, c->sG, c->sM, c->sV, c->s_norm, c->s_loss, c->s_Xb, c->s_yb,
                   c->s_Yb, c->s_Z, c->s_H, c->s_dY, c->s_work, c->s_red, c->s_H0, c->s_H1, c->rep_x, c->rep_y,
                   c->s_xs, c->d_lo_box, c->d_span_box};
@@ -354,8 +356,20 @@ static NetDev surr_netdev(const ns_ctx* c) {
 // Likelihood of the first n rows of the row buffers (gate: skip when zero).
 // Network likelihoods: in-box rows (minus the ones the surrogate screens out,
 // when allowed) are compacted, evaluated, and scattered back.
-static ns_status eval_rows(ns_ctx* c, long n, const int* gate, bool allow_screen = false) {
+static ns_status eval_rows(ns_ctx* c, long n, const int* gate, bool allow_screen = false, int round = -1) {
   TimeScope ts(c, NS_TIME_LIK);
+  if (c->is_mlp && round >= 0 && c->rb.xf_direct) {
+    // rows written by the advance kernel straight into compacted split planes
+    const int* crows = c->rb.crows + round;
+    NS_TRY(emu_forward_logL(c->net, static_cast<int>(n), c->rb.xf_direct, c->rb.xf_plane,
+                            reinterpret_cast<__bf16*>(c->rb.H0), reinterpret_cast<__bf16*>(c->rb.H1),
+                            reinterpret_cast<double*>(c->rb.Y), c->mlp_data, c->mlp_isig, nullptr, gate, crows,
+                            c->stream));
+    NS_TRY(launch_chi2_rows(static_cast<int>(n), c->rp.P, c->net.widths[c->net.n_layers] / 32,
+                            reinterpret_cast<const double*>(c->rb.Y), crows, c->rb.cmap, c->rb.flag,
+                            c->rb.rlogL, &c->d_sc->emu_rows, gate, c->stream));
+    return NS_OK;
+  }
   if (c->is_mlp) {
     const int screening = (allow_screen && c->screening) ? 1 : 0;
     const int d = c->sh.d;
@@ -368,19 +382,24 @@ static ns_status eval_rows(ns_ctx* c, long n, const int* gate, bool allow_screen
     }
     NS_TRY(launch_screen(static_cast<int>(n), d, screening, c->scfg.margin, std::max(1, c->scfg.audit_period),
                          c->rb.flag, c->rb.rthr, c->d_yhat, c->s_norm, c->rb.xin, c->rb.sflag, c->d_idx,
-                         c->d_aud, c->d_xc, c->d_count, c->rb.rlogL, c->d_sc, c->d_chunk, gate, c->stream));
+                         c->d_aud, c->d_xc, c->emu_frag ? c->d_xf : nullptr, c->xf_plane, c->d_count,
+                         c->rb.rlogL, c->d_sc, c->d_chunk, gate, c->stream));
+    const double* part = nullptr;
     if (c->emu_frag) {
-      // the chi^2 partials (n x widths[L]/32 doubles) reuse the output buffer
-      NS_TRY(emu_forward_logL(c->net, static_cast<int>(n), c->d_xc, reinterpret_cast<__bf16*>(c->rb.H0),
+      // the chi^2 partials (widths[L]/32 x n doubles) reuse the output buffer;
+      // the scatter below sums them
+      part = reinterpret_cast<const double*>(c->rb.Y);
+      NS_TRY(emu_forward_logL(c->net, static_cast<int>(n), c->d_xf, c->xf_plane, reinterpret_cast<__bf16*>(c->rb.H0),
                               reinterpret_cast<__bf16*>(c->rb.H1), reinterpret_cast<double*>(c->rb.Y),
-                              c->mlp_data, c->mlp_isig, c->d_clogL, gate, c->d_count, c->stream));
+                              c->mlp_data, c->mlp_isig, nullptr, gate, c->d_count, c->stream));
     } else {
       NS_TRY(net_forward(c->net, c->mode_first, c->mode_rest, static_cast<int>(n), c->d_xc, c->rb.H0,
                          c->rb.H1, c->rb.Y, gate, c->stream, c->d_count));
       NS_TRY(launch_chi2(static_cast<int>(n), c->net.widths[c->net.n_layers], c->rb.Y, c->mlp_data,
                          c->mlp_isig, nullptr, c->d_clogL, gate, c->stream, c->d_count));
     }
-    NS_TRY(launch_scatter(static_cast<int>(n), d, c->d_count, c->d_idx, c->d_aud, c->d_clogL, c->rb.rthr, c->d_xc, c->rb.rlogL,
+    NS_TRY(launch_scatter(static_cast<int>(n), d, c->d_count, c->d_idx, c->d_aud, c->d_clogL, part,
+                          part ? c->net.widths[c->net.n_layers] / 32 : 0, c->rb.rthr, c->d_xc, c->rb.rlogL,
                           c->rep_x, c->rep_y, c->surr ? c->rep_cap : 0, c->d_sc, gate, c->stream));
   } else {
     NS_TRY(launch_rows_loglike(c->sh, c->lik, n, c->rb.pts, c->rb.flag, c->rb.rlogL, gate, c->stream));
@@ -396,6 +415,11 @@ static ns_status run_rounds(ns_ctx* c, int m) {
   p.m = m;
   const long rows = static_cast<long>(m) * p.P;
   NS_TRY(launch_fill_int(c->rb.gate, c->rb.gate_cap, 0, c->stream));
+  // plain emulator rounds: no compaction pass (the replay ring of the learned
+  // screen needs it, so not while a surrogate is attached)
+  c->rb.xf_direct = (c->is_mlp && c->emu_frag && !c->surr) ? c->d_xf : nullptr;
+  c->rb.xf_plane = c->xf_plane;
+  if (c->rb.xf_direct) NS_TRY(launch_fill_int(c->rb.crows, c->rb.gate_cap, 0, c->stream));
   const int chunk = 48;
   int r = 0;
   for (;;) {
@@ -404,7 +428,7 @@ static ns_status run_rounds(ns_ctx* c, int m) {
         TimeScope ts(c, NS_TIME_SLICE);
         NS_TRY(launch_rounds_advance(r, p, c->sh, c->b, c->rb, c->stream));
       }
-      ns_status e = eval_rows(c, rows, c->rb.gate + r, true);
+      ns_status e = eval_rows(c, rows, c->rb.gate + r, true, r);
       if (e != NS_OK) return e;
     }
     NS_TRY(hipMemcpyAsync(c->h_gate, c->rb.gate + (r - 1), sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -631,6 +655,11 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
       off_w += static_cast<size_t>(K) * Nn;
       off_b += Nn;
       NS_INIT_TRY(upload(c, wt.data(), wt.size(), &net.Wt[l]));
+      if (lik->prec == NS_BF16X3 && l == 0 && K <= 32 && Nn % 32 == 0) {
+        std::vector<__bf16> wf(static_cast<size_t>(3) * Nn * 32);
+        frag_split_host(wt.data(), Nn, K, wf.data());
+        NS_INIT_TRY(upload(c, wf.data(), wf.size(), &net.Wf[0]));
+      }
       NS_INIT_TRY(upload(c, bb.data(), bb.size(), &net.b[l]));
       if (lik->prec == NS_BF16X3 && l >= 1 && K % 32 == 0) {
         std::vector<__bf16> wb(wt.size());
@@ -730,6 +759,8 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
     NS_INIT_HIP(dalloc(&rb.flag, rb.rows_cap));
     NS_INIT_HIP(dalloc(&rb.rlogL, rb.rows_cap));
     NS_INIT_HIP(dalloc(&rb.gate, rb.gate_cap));
+    NS_INIT_HIP(dalloc(&rb.crows, rb.gate_cap));
+    NS_INIT_HIP(dalloc(&rb.cmap, static_cast<size_t>(rb.rows_cap / rp.P + 1)));
     NS_INIT_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_gate), sizeof(int), hipHostMallocDefault));
     if (c->is_mlp) {
       // hidden activations: FP32, or three bfloat16 planes (1.5x) on the split path
@@ -747,6 +778,12 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
       NS_INIT_HIP(dalloc(&c->d_idx, rb.rows_cap));
       NS_INIT_HIP(dalloc(&c->d_aud, rb.rows_cap));
       NS_INIT_HIP(dalloc(&c->d_xc, static_cast<size_t>(rb.rows_cap) * d));
+      if (c->emu_frag) {
+        // columns d..31 stay zero: written once here, never by the compaction
+        c->xf_plane = (rb.rows_cap + 15) / 16 * 16 * 32;
+        NS_INIT_HIP(dalloc(&c->d_xf, static_cast<size_t>(3 * c->xf_plane)));
+        NS_INIT_HIP(hipMemsetAsync(c->d_xf, 0, sizeof(__bf16) * 3 * c->xf_plane, c->stream));
+      }
       NS_INIT_HIP(dalloc(&c->d_clogL, rb.rows_cap));
       NS_INIT_HIP(dalloc(&c->s_norm, kNormLen));
       NS_INIT_HIP(hipMemsetAsync(c->d_sc, 0, sizeof(SurrCounters), c->stream));

@@ -7,6 +7,15 @@
 namespace ns {
 
 enum GemmMode : int { kF32 = 0, kBF16S = 1, kBF16 = 2 };
+
+// Fragment-major bfloat16 layout of a matrix with K columns (K % 32 == 0):
+// blocks of 16 rows x 32 columns, block (r/16, k/32) at element
+// ((r/16) (K/32) + k/32) 512; inside a block the eight columns 8g..8g+7 of row
+// i are contiguous at element (i + 16 g) 8, so a block is exactly one
+// 16x16x32 MFMA operand fragment (lane i + 16 g holds 16 bytes).
+__host__ __device__ inline long frag_index(long r, int k, int K) {
+  return ((r >> 4) * (K >> 5) + (k >> 5)) * 512 + ((r & 15) + 16 * ((k & 31) >> 3)) * 8 + (k & 7);
+}
 enum Act : int { kActNone = 0, kActTanh = 1, kActSilu = 2 };
 
 // dM (may be null): device-side row count; rows at or beyond it are skipped.
@@ -45,7 +54,8 @@ struct NetDev {
   int max_width;
   int w_rowmajor;
   const __bf16* Wb[8];  // bfloat16 copies of Wt (layers >= 1) for the split-activation path
-  const __bf16* Wf[8];  // the same in the fragment-major layout (emu_forward_logL)
+  const __bf16* Wf[8];  // the same in the fragment-major layout (emu_forward_logL); layer 0:
+                        // hi, mid, lo planes of widths[1] x 32 (inputs padded with zeros)
 };
 
 // Forward over M rows of X (M x widths[0]); H0/H1 ping-pong buffers of
@@ -58,17 +68,33 @@ hipError_t net_forward(const NetDev& net, int mode_first, int mode_rest, int M, 
                        const int* dM = nullptr);
 
 // Emulator log-likelihood on fragment-major split activations (k_gemm.hip):
-// layer 0 in FP32, hidden layers and the output layer on bfloat16 MFMA, the
-// diagonal chi^2 fused into the output layer.  Applies when layer 0 is FP32,
-// the others split bfloat16, at least two layers, widths[0] <= 32 and every
-// other width a multiple of 32 (emu_frag_eligible).  P0/P1: three planes of
-// emu_frag_plane(M, max_width) bfloat16 each; part: M x widths[L]/32 doubles.
+// every layer on bfloat16 MFMA with FP32 accumulation (the input and the
+// first layer's weights split into three bfloat16 terms each, later layers'
+// activations into three terms against bfloat16 weights), the diagonal chi^2
+// (FP64) fused into the output layer.  Applies with layer 0 FP32, the others
+// split bfloat16, at least two layers, widths[0] <= 32 and every other width
+// a multiple of 32 (emu_frag_eligible).  Xf: the inputs as three
+// fragment-major planes of (M rounded up to 16) x 32 (columns >= widths[0]
+// zero), plane stride xplane.  P0/P1: three planes of emu_frag_plane(M,
+// max_width) bfloat16 each; part: widths[L]/32 x M doubles (column block q of
+// row r at q M + r).  With logL null the partials are left for the caller to
+// sum (in ascending q, then -1/2, NaN -> -inf).
 bool emu_frag_eligible(const NetDev& net, int mode_first, int mode_rest);
 long emu_frag_plane(long M, int max_width);
-hipError_t emu_forward_logL(const NetDev& net, int M, const float* X, __bf16* P0, __bf16* P1, double* part,
-                            const double* data, const double* isig, double* logL, const int* gate,
+hipError_t emu_forward_logL(const NetDev& net, int M, const __bf16* Xf, long xplane, __bf16* P0, __bf16* P1,
+                            double* part, const double* data, const double* isig, double* logL, const int* gate,
                             const int* dM, hipStream_t s);
+// Direct rounds (no compaction pass): the partials of emu_forward_logL over
+// M = *crows compacted rows (pstride M, the host bound), summed into the
+// round's rows: compacted row i is row cmap[i/P] P + i%P; flag 0 -> -inf.
+// net_rows (may be null) accumulates the compacted row count.
+hipError_t launch_chi2_rows(int M, int P, int nb, const double* part, const int* crows, const int* cmap,
+                            const int* flag, double* rlogL, unsigned long long* net_rows, const int* gate,
+                            hipStream_t s);
 // Host: W^T (N x K FP32, N % 16 == 0, K % 32 == 0) -> fragment-major bfloat16.
 void frag_layout_host(const float* Wt, int N, int K, __bf16* out);
+// Host: W^T (N x K0 FP32, K0 <= 32) -> three fragment-major planes (hi, mid,
+// lo) of N x 32, inputs K0..31 zero.
+void frag_split_host(const float* Wt, int N, int K0, __bf16* out);
 
 }  // namespace ns

@@ -39,6 +39,15 @@ struct RoundBufs {
   float* H0;       // rows x max_width
   float* H1;
   float* Y;        // rows x out_width
+  // Direct network evaluation (no row compaction pass): when xf_direct is set
+  // the advance kernel also writes each chain's rows, split into three
+  // bfloat16 terms, to compacted fragment-major planes (stride xf_plane);
+  // crows[round] counts the compacted rows, cmap[c] is the chain of compacted
+  // rows c P .. c P + P - 1.
+  __bf16* xf_direct;
+  long xf_plane;
+  int* crows;      // gate_cap entries
+  int* cmap;       // m entries
 };
 
 hipError_t launch_fill_int(int* p, long n, int v, hipStream_t s);

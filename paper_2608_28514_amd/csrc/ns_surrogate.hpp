@@ -18,15 +18,21 @@ struct SurrCounters {
   unsigned long long false_screens;  // audited rows that cleared their threshold
 };
 
-// chunk_cnt: 2 ints per chunk of 256 rows (scratch shared by the two passes)
+// chunk_cnt: 2 ints per chunk of 256 rows (scratch shared by the two passes).
+// xf (may be null): the compacted inputs also as three fragment-major
+// bfloat16 planes (hi, mid, lo) of 32 columns, plane stride xfplane; columns
+// d..31 are not written.
 hipError_t launch_screen(int M, int d, int screening, double margin, int audit_period, const int* flag,
                          const double* rthr, const float* yhat, const float* norm, const float* xin,
-                         int* sflag, int* idx, int* aud, float* xc, int* count, double* rlogL,
-                         SurrCounters* sc, int* chunk_cnt, const int* gate, hipStream_t s);
-// M: rows of the round (upper bound of count[0])
+                         int* sflag, int* idx, int* aud, float* xc, __bf16* xf, long xfplane, int* count,
+                         double* rlogL, SurrCounters* sc, int* chunk_cnt, const int* gate, hipStream_t s);
+// M: rows of the round (upper bound of count[0]).  The logL of compacted row
+// i is clogL[i], or, with part non-null, -1/2 sum_q part[q M + i] over the nb
+// chi^2 column blocks of emu_forward_logL.
 hipError_t launch_scatter(int M, int d, const int* count, const int* idx, const int* aud, const double* clogL,
-                          const double* rthr, const float* xc, double* rlogL, float* rep_x, double* rep_y,
-                          long cap, SurrCounters* sc, const int* gate, hipStream_t s);
+                          const double* part, int nb, const double* rthr, const float* xc, double* rlogL,
+                          float* rep_x, double* rep_y, long cap, SurrCounters* sc, const int* gate,
+                          hipStream_t s);
 hipError_t launch_sample_batch(int B, int d, uint64_t seed, uint32_t call, uint32_t iter, const float* rep_x,
                                const double* rep_y, long cap, const SurrCounters* sc, const double* LW,
                                const RunState* st, const double* root_centre, const double* root_cov,

@@ -195,12 +195,13 @@ def _gamma(n):
 
 def _emulator_logL_bound(spec, X):
     """Per-row bound on |logL_gpu - logL_exact| for the emulator likelihood
-    evaluated with an FP32 first layer (fused multiply-adds from zero, then the
-    bias) and split-bfloat16 MFMA layers (hi + mid + lo activations, bfloat16
-    weights, FP32 accumulation of 3K products, then the bias), tanh hidden
-    activations, FP64 chi^2.  Layer by layer, with h the exact activations:
-      first layer: |dz| <= gamma(K0 + 1) (sum |x||w| + |b|)
-      MFMA layer:  |dz| <= gamma(3K + 2) 1.02 (sum |h||w| + |b|) + sum |dh||w|
+    evaluated on split-bfloat16 MFMA layers with FP32 accumulation, tanh hidden
+    activations and an FP64 chi^2.  Products per (row, k): the first layer
+    multiplies the three bfloat16 terms of the input by the three of the FP32
+    weight (P = 9; the generic path instead runs an FP32 fused multiply-add
+    chain, covered by the same bound), later layers the three terms of the
+    activation by the bfloat16 weight (P = 3).  Layer by layer, with h exact:
+      |dz| <= gamma(P K + 2) 1.02 (sum |h||w| + |b|) + sum |dh||w|
       tanh (1-Lipschitz, <= 2 ulp) and the three-term split: |dh| <= |dz| + 9 u |h|
       output y = z; chi^2: |dlogL| <= sum |r| d / sigma + (d / sigma)^2 / 2,
     r = (y - D) / sigma, plus 1e-12 |logL| for the FP64 sum."""
@@ -213,10 +214,8 @@ def _emulator_logL_bound(spec, X):
         K = Wl.shape[0]
         mag = np.abs(h) @ np.abs(Wl) + np.abs(bl)
         z = h @ Wl + bl
-        if l == 0:
-            dz = _gamma(K + 1) * mag
-        else:
-            dz = _gamma(3 * K + 2) * 1.02 * mag + dh @ np.abs(Wl)
+        P = 9 if l == 0 else 3
+        dz = _gamma(P * K + 2) * 1.02 * mag + dh @ np.abs(Wl)
         if l + 1 < L:
             h = np.tanh(z)
             dh = dz + 9.0 * U32 * np.abs(h)
@@ -236,23 +235,30 @@ def _bf16(x):
     return r.astype(np.uint32).view(np.float32)
 
 
+def _split3(x):
+    x = np.asarray(x, dtype=np.float32)
+    hi = _bf16(x)
+    r1 = (x - hi).astype(np.float32)
+    mid = _bf16(r1)
+    return hi, mid, _bf16((r1 - mid).astype(np.float32))
+
+
 def _emulator_logL_fp32_model(spec, X):
-    """The intended arithmetic in numpy: FP32 first layer, then per layer the
-    activations split into hi + mid + lo bfloat16 terms, three FP32 products
-    with the bfloat16 weights, FP32 bias and tanh; chi^2 in FP64."""
+    """The intended arithmetic in numpy: per layer the activations (the input
+    too) split into hi + mid + lo bfloat16 terms, the first layer's FP32
+    weights likewise, later weights bfloat16; FP32 products summed in FP32,
+    FP32 bias and tanh; chi^2 in FP64."""
     h = np.asarray(X, dtype=np.float32)
     L = len(spec["weights"])
     for l in range(L):
         Wl = np.asarray(spec["weights"][l], dtype=np.float32)
         bl = np.asarray(spec["biases"][l], dtype=np.float32)
-        if l == 0:
-            z = h @ Wl
-        else:
-            hi = _bf16(h)
-            r1 = (h - hi).astype(np.float32)
-            mid = _bf16(r1)
-            lo = _bf16((r1 - mid).astype(np.float32))
-            z = (lo @ Wl + mid @ Wl + hi @ Wl).astype(np.float32)
+        a = _split3(h)
+        w = _split3(Wl) if l == 0 else (Wl,)
+        z = np.zeros((h.shape[0], Wl.shape[1]), dtype=np.float32)
+        for pa in (2, 1, 0):
+            for pb in range(len(w)):
+                z = (z + a[pa] @ w[pb]).astype(np.float32)
         z = (z + bl).astype(np.float32)
         h = np.tanh(z).astype(np.float32) if l + 1 < L else z
     r = (h.astype(np.float64) - spec["data"]) / spec["sigma"]
@@ -299,3 +305,25 @@ def test_emulator_rows_within_error_bound(widths, n):
     for q in (0.5, 0.9):
         assert np.quantile(err[:k], q) <= 4.0 * np.quantile(model[:k], q) + 1e-9
         assert np.quantile(err[k:] / np.abs(ref[k:]), q) <= 4.0 * np.quantile(model[k:] / np.abs(ref[k:]), q) + 1e-15
+
+
+def test_direct_rounds_equal_compacted_rounds():
+    """Plain emulator rounds evaluate the advance kernel's compacted planes
+    directly; with a surrogate attached (never trained here) every round goes
+    through the row-compaction pass instead.  Placement aside the arithmetic
+    per row is the same, so the two runs must agree bit for bit."""
+    spec = W.emulator(seed=3, widths=(27, 64, 96, 64), noise_frac=0.05)
+    out = []
+    for attach in (False, True):
+        s = native.Sampler(spec, 200, prec="bf16x3", state="f32", seed=4, tree_depth=1)
+        if attach:
+            s.enable_surrogate(min_pairs=2 ** 30, margin=1e30)   # never screens
+        s.run(20, max_steps=40)
+        out.append((s.dead(), s.stats()))
+        s.close()
+    (da, sa), (db, sb) = out
+    assert len(da["logL"]) == len(db["logL"]) > 0
+    assert np.array_equal(da["logL"], db["logL"])
+    assert np.array_equal(da["u"], db["u"])
+    for k in ("evals", "oob", "stepout_caps", "shrink_caps", "steps", "dead"):
+        assert sa[k] == sb[k], k
