@@ -40,8 +40,8 @@ BF16_PEAK = 2.5e15                                          # MI355X dense BF16 
 SLICE_TRAFFIC = {
     "sources": ["paper_2608_28514_amd/csrc/k_slice.hip", "paper_2608_28514_amd/csrc/ns_device.hpp",
                 "paper_2608_28514_amd/csrc/ns_internal.hpp"],
-    "sha256": "ce169e143eb6491e301d50d8e4e993a4ec35fec080297cd2abaea0308a6dbadb",
-    "fetch_kib": 317.3, "fetch_scale": 2.0, "write_kib": 18.19, "write_scale": 1.0,
+    "sha256": "0202a0b6d7ae70a4e263a92e70e63ed28a4cf7d8d94144a41e087b4a47ed1bb2",
+    "fetch_kib": 289.01, "fetch_scale": 2.0, "write_kib": 18.30, "write_scale": 1.0,
 }
 
 
@@ -305,11 +305,12 @@ def bench_emulator(args, np, torch, native, workloads):
         "evals_per_s": evals / t_total, "net_rows_per_s": rows / t_total,
         "kernel_ms": {c: round(v[0], 3) for c, v in kern.items()},
         "kernel_launches": {c: v[1] for c, v in kern.items()},
-        "roofline": {"kernel": "k_gemm (emulator layers) + k_chi2, batched rounds", "bound": "mfma"
-                     if prec.startswith("bf16") else "alu", "achieved": achieved / 1e12,
+        "roofline": {"kernel": ("k_dense_frag (emulator layers, chi^2 fused) + k_chi2_rows"
+                                if prec.startswith("bf16") else "k_gemm<F32> + k_chi2"),
+                     "bound": "mfma" if prec.startswith("bf16") else "alu", "achieved": achieved / 1e12,
                      "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                     "note": "useful emulator FLOPs (2,124,800 per row) over the batched-likelihood "
-                             "kernel time; the split activations issue 3x the MFMA work on layers 2-4"},
+                     "note": "network rows x 2,124,800 FLOP over the batched-likelihood time (HIP events); "
+                             "the split activations issue 3x this MFMA work (9x in the first layer)"},
         "runs": runs,
     }
     print(json.dumps(out, default=float))

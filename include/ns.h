@@ -232,20 +232,22 @@ ns_status ns_philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32
 /* Per-kernel-class device time, measured with HIP events recorded on the
  * context's stream around each launch sequence: classes NS_TIME_SELECT
  * (sort + seeds), NS_TIME_SLICE (the chains), NS_TIME_CORRECT (Algorithms
- * 1/2, update, evidence), NS_TIME_CLUSTER (tree build).  ns_set_timing(c, mask)
+ * 1/2, update, evidence), NS_TIME_CLUSTER (tree build), NS_TIME_DRAWS (the
+ * draw pre-pass of the fused slice kernel).  ns_set_timing(c, mask)
  * clears the counters and times the classes whose bit (1 << class) is set in
  * mask (NS_TIMING_ALL for every class, 0 for none); each timed launch
  * sequence adds two event records to the stream.  ns_get_timing synchronises
  * and returns total milliseconds and launch counts per class (arrays of
  * NS_TIMING_CLASSES, may be NULL; untimed classes read zero).  NS_TIME_LIK:
  * the batched likelihood kernels of the rounds (network layers and chi^2). */
-#define NS_TIMING_CLASSES 5
+#define NS_TIMING_CLASSES 6
 #define NS_TIME_SELECT 0
 #define NS_TIME_SLICE 1   /* fused slice kernel, or the chain kernels of batched rounds */
 #define NS_TIME_CORRECT 2
 #define NS_TIME_CLUSTER 3
 #define NS_TIME_LIK 4     /* batched likelihood of the rounds (network layers, chi^2)  */
-#define NS_TIMING_ALL 0x1F
+#define NS_TIME_DRAWS 5   /* directions and uniforms of the fused slice kernel        */
+#define NS_TIMING_ALL 0x3F
 ns_status ns_set_timing(ns_ctx* c, int mask);
 ns_status ns_get_timing(ns_ctx* c, double* ms, int64_t* launches);
 

@@ -144,13 +144,23 @@ k_cluster_level(int level, int depth, int N, int d_arg, int iters, const T* __re
     }
     cnt = N;
   } else {
-    for (int base = 0; base < N; base += kCT) {
-      const int k = base + threadIdx.x;
-      const int flag = (k < N) && nodeof[k] == node;
-      const int off = block_scan_flag(flag, wave_tot, &s_total);
-      if (flag) s_mem[cnt + off] = k;
-      cnt += s_total;
-      __syncthreads();
+    // every thread's node labels loaded at once, then scanned in order
+    constexpr int kQ = kMaxN / kCT;
+    const int nq = (N + kCT - 1) / kCT;
+    int lab[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q)
+      if (q < nq) lab[q] = nodeof[min(q * kCT + static_cast<int>(threadIdx.x), N - 1)];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      if (q < nq) {   // uniform
+        const int k = q * kCT + threadIdx.x;
+        const int flag = (k < N) && lab[q] == node;
+        const int off = block_scan_flag(flag, wave_tot, &s_total);
+        if (flag) s_mem[cnt + off] = k;
+        cnt += s_total;
+        __syncthreads();
+      }
     }
   }
   if (threadIdx.x == 0) count[node] = cnt;
@@ -280,7 +290,8 @@ k_cluster_level(int level, int depth, int N, int d_arg, int iters, const T* __re
     }
     const int pick = block_argmax(bv, bix, s_bv, s_bi);
     if (threadIdx.x < d)
-      cab[2 * threadIdx.x + pass] = static_cast<double>(u[static_cast<long>(s_mem[pick]) * d + threadIdx.x]);
+      cab[2 * threadIdx.x + pass] = resident ? static_cast<double>(pts[threadIdx.x * cs + pick])
+                                             : static_cast<double>(u[static_cast<long>(s_mem[pick]) * d + threadIdx.x]);
     __syncthreads();
   }
   // Lloyd: pass t assigns with the current centres (a tie goes to the first

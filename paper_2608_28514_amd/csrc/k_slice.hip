@@ -290,20 +290,20 @@ k_slice(SliceParams p, int d_arg, int TH, LikDev lik, const T* __restrict__ u,
   }
 }
 
+hipError_t launch_slice_draws(const Shape& sh, const DevBufs& b, const SliceParams& p, hipStream_t s) {
+  const dim3 dgrid(p.m, p.n_iter), block(64);
+  if (sh.state_f32)
+    hipLaunchKernelGGL(k_slice_draws<float>, dgrid, block, 0, s, p, sh.d, b.chol_f, b.label, b.seeds,
+                       static_cast<float*>(b.draws), b.st);
+  else
+    hipLaunchKernelGGL(k_slice_draws<double>, dgrid, block, 0, s, p, sh.d, b.chol, b.label, b.seeds,
+                       static_cast<double*>(b.draws), b.st);
+  return hipGetLastError();
+}
+
 hipError_t launch_slice(const Shape& sh, const DevBufs& b, const LikDev& lik, const SliceParams& p,
                         hipStream_t s) {
   const dim3 grid(p.m), block(64);
-  {
-    const dim3 dgrid(p.m, p.n_iter);
-    if (sh.state_f32)
-      hipLaunchKernelGGL(k_slice_draws<float>, dgrid, block, 0, s, p, sh.d, b.chol_f, b.label, b.seeds,
-                         static_cast<float*>(b.draws), b.st);
-    else
-      hipLaunchKernelGGL(k_slice_draws<double>, dgrid, block, 0, s, p, sh.d, b.chol, b.label, b.seeds,
-                         static_cast<double*>(b.draws), b.st);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
   if (sh.state_f32) {
 #define NS_SLICE_ARGS(ST)                                                                        \
   p, sh.d, sh.T, lik, static_cast<const ST*>(b.u), b.logL, static_cast<const ST*>(b.draws),      \

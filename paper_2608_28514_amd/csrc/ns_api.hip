@@ -875,6 +875,10 @@ ns_status ns_step_batch(ns_ctx* c, int m) {
     ns_status r = run_rounds(c, m);
     if (r != NS_OK) return r;
   } else {
+    {
+      TimeScope ts(c, NS_TIME_DRAWS);
+      NS_TRY(launch_slice_draws(c->sh, c->b, p, c->stream));
+    }
     TimeScope ts(c, NS_TIME_SLICE);
     NS_TRY(launch_slice(c->sh, c->b, c->lik, p, c->stream));
   }

@@ -70,6 +70,9 @@ hipError_t launch_loglike_points(const Shape& sh, const LikDev& lik, const doubl
 hipError_t launch_select(const Shape& sh, const DevBufs& b, int m, int corr, uint64_t seed,
                          hipStream_t s);
 hipError_t launch_select_order(const double* logL, int N, int* order, hipStream_t s);
+// The fused slice kernel reads the draw blocks that launch_slice_draws writes
+// (call it first, on the same stream).
+hipError_t launch_slice_draws(const Shape& sh, const DevBufs& b, const SliceParams& p, hipStream_t s);
 hipError_t launch_slice(const Shape& sh, const DevBufs& b, const LikDev& lik, const SliceParams& p,
                         hipStream_t s);
 // sel_m > 0: also select the next step's m worst points and seeds into

@@ -312,10 +312,10 @@ def ns_philox(seed, c0, c1, c2, c3, n, d_out, stream=None):
            "ns_philox")
 
 
-TIMING_CLASSES = ("select", "slice", "correct", "cluster", "lik")
+TIMING_CLASSES = ("select", "slice", "correct", "cluster", "lik", "draws")
 
 
-TIMING_ALL = 0x1F
+TIMING_ALL = 0x3F
 
 
 def ns_set_timing(ctx, on=True):
