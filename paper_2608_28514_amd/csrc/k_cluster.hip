@@ -144,23 +144,25 @@ k_cluster_level(int level, int depth, int N, int d_arg, int iters, const T* __re
     }
     cnt = N;
   } else {
-    // every thread's node labels loaded at once, then scanned in order
-    constexpr int kQ = kMaxN / kCT;
-    const int nq = (N + kCT - 1) / kCT;
-    int lab[kQ];
+    // the node labels of all points to LDS first (eight loads in flight per
+    // thread), then compacted in place: a pass writes member indices only
+    // below the labels later passes still read
+    for (int k0 = threadIdx.x; k0 < N; k0 += 8 * kCT) {
+      int lab[8];
 #pragma unroll
-    for (int q = 0; q < kQ; ++q)
-      if (q < nq) lab[q] = nodeof[min(q * kCT + static_cast<int>(threadIdx.x), N - 1)];
+      for (int q = 0; q < 8; ++q) lab[q] = nodeof[min(k0 + q * kCT, N - 1)];
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      if (q < nq) {   // uniform
-        const int k = q * kCT + threadIdx.x;
-        const int flag = (k < N) && lab[q] == node;
-        const int off = block_scan_flag(flag, wave_tot, &s_total);
-        if (flag) s_mem[cnt + off] = k;
-        cnt += s_total;
-        __syncthreads();
-      }
+      for (int q = 0; q < 8; ++q)
+        if (k0 + q * kCT < N) s_mem[k0 + q * kCT] = lab[q];
+    }
+    __syncthreads();
+    for (int base = 0; base < N; base += kCT) {
+      const int k = base + threadIdx.x;
+      const int flag = (k < N) && s_mem[k] == node;
+      const int off = block_scan_flag(flag, wave_tot, &s_total);
+      if (flag) s_mem[cnt + off] = k;
+      cnt += s_total;
+      __syncthreads();
     }
   }
   if (threadIdx.x == 0) count[node] = cnt;
@@ -254,8 +256,15 @@ k_cluster_level(int level, int depth, int N, int d_arg, int iters, const T* __re
     while (span < GC) span <<= 1;
     for (int off = span >> 1; off > 0; off >>= 1) {
       if (blk < NB && gc < off && gc + off < GC) {
+        // all 32 reads issued before the 16 sums are written back
+        double va[16], vb[16];
 #pragma unroll
-        for (int ab = 0; ab < 16; ++ab) cpart[ab * kCT + threadIdx.x] += cpart[ab * kCT + threadIdx.x + off];
+        for (int ab = 0; ab < 16; ++ab) {
+          va[ab] = cpart[ab * kCT + threadIdx.x];
+          vb[ab] = cpart[ab * kCT + threadIdx.x + off];
+        }
+#pragma unroll
+        for (int ab = 0; ab < 16; ++ab) cpart[ab * kCT + threadIdx.x] = va[ab] + vb[ab];
       }
       __syncthreads();
     }
