@@ -30,6 +30,9 @@ FP64_PEAK = 78.6e12                 # MI355X FP64 vector FLOP/s
 
 
 EMU_FLOPS = 2 * (27 * 512 + 512 * 512 * 2 + 512 * 1024)   # one emulator evaluation
+# MFMA work actually issued per row by the split-bfloat16 path: nine products of
+# 32 (padded) inputs in the first layer, three activation terms afterwards
+EMU_MFMA_ISSUED = 2 * (9 * 32 * 512 + 3 * (512 * 512 * 2 + 512 * 1024))
 BF16_PEAK = 2.5e15                                          # MI355X dense BF16 MFMA FLOP/s
 
 # HBM bytes per launch of the fused slice kernel on this workload, from two
@@ -85,6 +88,10 @@ def main():
     ap.add_argument("--no-screen", action="store_true",
                     help="workload 5 without the learned pre-screen (the plain sampler)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--select-sweep", action="store_true",
+                    help="worst-1000 selection alone at N = 2^16 ... 2^24 (HBM streaming passes)")
+    ap.add_argument("--lik-sweep", action="store_true",
+                    help="batched emulator likelihood alone at M = 200 ... 25600 rows per call")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -108,6 +115,10 @@ def main():
     from paper_2608_28514_amd import native, workloads
 
     torch.cuda.set_device(0)
+    if args.lik_sweep:
+        return bench_lik_sweep(args, np, torch, native, workloads)
+    if args.select_sweep:
+        return bench_select_sweep(args, np, torch, native)
     if args.workload in (4, 5):
         return bench_emulator(args, np, torch, native, workloads)
     spec = workloads.likelihood(2)
@@ -219,6 +230,89 @@ def main():
     out["pass_2sigma_vs_quadrature"] = \
         f"{sum(abs(r['logZ'] - ROSEN_QUADRATURE_LOGZ) < 2 * r['sigma'] for r in runs)}/{len(runs)}"
     print(json.dumps(out))
+
+
+HBM_PEAK = 8.0e12                   # MI355X HBM3E bytes/s
+
+
+def bench_select_sweep(args, np, torch, native):
+    """ns_select_worst (the m = 1000 worst of N FP64 likelihoods, drawn from
+    N(-100, 30^2)) at N = 2^16 ... 2^24, timed with torch events on the stream
+    it runs on.  Each pass streams N doubles from HBM; the achieved rate counts
+    8 N bytes per pass over the whole call (initialisation, the early-exiting
+    launches and the final sort of at most 8192 candidates included)."""
+    m = 1000
+    work = torch.empty(native.ns_select_worst_work_bytes(), dtype=torch.uint8, device="cuda:0")
+    gen = torch.Generator().manual_seed(0)
+    res = []
+    for lg in (16, 18, 20, 22, 24):
+        N = 1 << lg
+        x = (torch.randn(N, generator=gen, dtype=torch.float64) * 30.0 - 100.0).to("cuda:0")
+        slots = torch.empty(m, dtype=torch.int32, device="cuda:0")
+        passes = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+        native.ns_select_worst(x, m, slots, work, passes)
+        torch.cuda.synchronize()
+        reps = max(10, min(200, (1 << 28) // N))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            native.ns_select_worst(x, m, slots, work, passes)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3 / reps
+        npass = int(passes.item())
+        ok = bool(torch.equal(slots.cpu().long(), torch.argsort(x, stable=True)[:m].cpu()))
+        bw = npass * 8.0 * N / t
+        res.append({"N": N, "m": m, "us_per_call": 1e6 * t, "passes": npass, "hbm_gbs": bw / 1e9,
+                    "hbm_frac": bw / HBM_PEAK, "matches_stable_sort": ok})
+        print(f"[bench] select N=2^{lg}: {1e6 * t:.1f} us, {npass} passes, {bw / 1e9:.0f} GB/s",
+              file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "worst-m selection, N sweep", "dtype": "f64", "data": "synthetic",
+                      "peak_gbs": HBM_PEAK / 1e9, "config": {"workload": "select worst 1000 of N(-100,30^2)"},
+                      "sweep": res}))
+
+
+def bench_lik_sweep(args, np, torch, native, workloads):
+    """The 27-d emulator likelihood of M prior-uniform rows per call (the
+    batched-likelihood path of the rounds: row compaction, four dense layers,
+    chi^2 and the scatter back), timed with HIP events on the sampler's stream,
+    for M in {200, 400, 1600, 6400, 25600} (calls of more than 8192 rows run in
+    chunks of 8192)."""
+    prec = args.prec or "bf16x3"
+    spec = workloads.likelihood(4, seed=0)
+    s = native.Sampler(spec, 2000, seed=0, prec=prec, state="f32", tree_depth=1)
+    gen = torch.Generator().manual_seed(0)
+    peak = BF16_PEAK if prec.startswith("bf16") else FP32_PEAK
+    res = []
+    for M in (200, 400, 1600, 6400, 25600):
+        u = torch.rand((M, 27), generator=gen, dtype=torch.float64).to("cuda:0")
+        out = torch.empty(M, dtype=torch.float64, device="cuda:0")
+        native.ns_loglike_batch(s.ctx, u, out)
+        native.ns_sync(s.ctx)
+        reps = max(20, (400 * 1600) // M)
+        native.ns_set_timing(s.ctx, 1 << native.TIMING_CLASSES.index("lik"))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            native.ns_loglike_batch(s.ctx, u, out)
+        native.ns_sync(s.ctx)
+        t1 = time.perf_counter()
+        ms, n = native.ns_get_timing(s.ctx)["lik"]
+        per_call = 1e-3 * ms / reps
+        useful = M * EMU_FLOPS / per_call
+        r = {"rows": M, "calls": reps, "us_per_call": 1e6 * per_call, "wall_us_per_call": 1e6 * (t1 - t0) / reps,
+             "rows_per_s": M / per_call, "useful_tflops": useful / 1e12, "useful_frac": useful / peak}
+        if prec == "bf16x3":
+            issued = M * EMU_MFMA_ISSUED / per_call
+            r["mfma_issued_tflops"] = issued / 1e12
+            r["mfma_issued_frac"] = issued / peak
+        res.append(r)
+        print(f"[bench] lik sweep M={M}: {1e6 * per_call:.1f} us per call", file=sys.stderr, flush=True)
+    s.close()
+    print(json.dumps({"metric": "batched emulator likelihood, rows per call sweep", "dtype": prec,
+                      "data": "synthetic", "peak_tflops": peak / 1e12,
+                      "config": {"workload": "emulator27d MLP 27-512-512-512-1024, prior-uniform rows"},
+                      "sweep": res}))
 
 
 def bench_emulator(args, np, torch, native, workloads):

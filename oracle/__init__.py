@@ -71,6 +71,8 @@ def lib():
         L.orc_cluster.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
                                   C.c_double, C.POINTER(OrcTree), _ip]
         L.orc_nearest_centre.argtypes = [C.POINTER(OrcTree), _dp]
+        L.orc_two_means.argtypes = [_dp, C.c_int, C.c_int, C.c_int, _dp, _dp, _ip]
+        L.orc_two_means.restype = None
         L.orc_correct.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _ip,
                                   _ip, _ip, _dp, _ip, _ip, _dp]
         L.orc_config_default.argtypes = [C.POINTER(OrcConfig)]
@@ -223,6 +225,16 @@ def cluster(u, depth, p=0.3, nmin=None, iters=20, eps=1e-8):
     labels = np.zeros(N, dtype=np.int32)
     lib().orc_cluster(_d(u), N, d, depth, p, nmin, iters, eps, C.byref(t), _i(labels))
     return tree_to_dict(t), labels
+
+
+def two_means(u, iters=20):
+    """k-means split (k = 2) of all points u (n x d) as one tree node: (ca, cb, side)."""
+    u = _f64(u)
+    n, d = u.shape
+    ca, cb = np.zeros(d), np.zeros(d)
+    side = np.zeros(n, dtype=np.int32)
+    lib().orc_two_means(_d(u), n, d, iters, _d(ca), _d(cb), _i(side))
+    return ca, cb, side
 
 
 def correct(m, corr, K, T, wlogL, nlogL, P, hist, hist_n):

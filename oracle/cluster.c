@@ -147,8 +147,10 @@ static double logaddexp2(double a, double b) {
   return mx + log1p(exp(-fabs(a - b)));
 }
 
-/* 2-means of the points idx[0..n-1]; side[k] = 0 (first centre) or 1. */
-static void two_means(const double* u, int d, const int* idx, int n, int iters, int* side) {
+/* 2-means of the points idx[0..n-1]; side[k] = 0 (first centre) or 1.
+ * ca_out / cb_out (may be NULL): the final centres. */
+static void two_means(const double* u, int d, const int* idx, int n, int iters, int* side, double* ca_out,
+                      double* cb_out) {
   double mu[ORC_MAXD] = {0}, ca[ORC_MAXD], cb[ORC_MAXD];
   for (int k = 0; k < n; ++k)
     for (int i = 0; i < d; ++i) mu[i] += u[(long)idx[k] * d + i];
@@ -189,6 +191,17 @@ static void two_means(const double* u, int d, const int* idx, int n, int iters, 
     }
     if (!changed) break;
   }
+  if (ca_out) memcpy(ca_out, ca, sizeof(double) * d);
+  if (cb_out) memcpy(cb_out, cb, sizeof(double) * d);
+}
+
+/* The split of one node holding all n points (Sec. 2.1): side per point and
+ * the two centres, as the tree build computes them. */
+void orc_two_means(const double* u, int n, int d, int iters, double* ca, double* cb, int* side) {
+  int* idx = (int*)malloc(sizeof(int) * (size_t)n);
+  for (int k = 0; k < n; ++k) idx[k] = k;
+  two_means(u, d, idx, n, iters, side, ca, cb);
+  free(idx);
 }
 
 static int level_of(int n) {
@@ -241,7 +254,7 @@ int orc_cluster(const double* u, int N, int d, int depth, double p, int nmin,
       t->logV[n] = -INFINITY;
     }
     if (level_of(n) < depth && cnt >= 2) {
-      two_means(u, d, idx, cnt, kmeans_iters, side);
+      two_means(u, d, idx, cnt, kmeans_iters, side, NULL, NULL);
       for (int k = 0; k < cnt; ++k) nodeof[idx[k]] = 2 * n + 1 + side[k];
     }
   }

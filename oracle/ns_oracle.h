@@ -103,6 +103,9 @@ void orc_select(const double* logL, int N, int* order);
 /* ---- linear algebra and clustering (Sec. 2.1) ------------------------------ */
 int orc_jacobi_eig(int d, const double* A, double* evals, double* evecs);
 int orc_cholesky(int d, const double* A, double* L);
+/* k-means split (k = 2) of n points u (n x d), as one tree node: side[k] and
+ * the final centres ca, cb (d each). */
+void orc_two_means(const double* u, int n, int d, int iters, double* ca, double* cb, int* side);
 /* eigen-clip + Cholesky; returns log volume sum log L_ii, writes L */
 double orc_regularise(int d, const double* cov, double eps, double* Lout, int* clipped);
 

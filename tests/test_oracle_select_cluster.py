@@ -107,3 +107,22 @@ def test_four_separated_modes_give_four_clusters():
         Lc = tree["chol"][n]
         assert np.allclose(Lc @ Lc.T, S, rtol=1e-10, atol=1e-14)
         assert np.allclose(tree["centre"][n], X[labels == n].mean(0), atol=1e-14)
+
+
+def test_two_means_split_of_separated_blobs():
+    """The node split alone (oracle.two_means): two well separated blobs are
+    recovered exactly, the first centre is the blob of the point farthest from
+    the mean, and the centres are the blob means."""
+    rng = np.random.default_rng(21)
+    a = rng.normal(0.25, 0.03, (70, 4))
+    b = rng.normal(0.75, 0.03, (50, 4))
+    u = np.concatenate([a, b])
+    mu = u.mean(axis=0)
+    first = int(np.argmax(((u - mu) ** 2).sum(axis=1)))
+    ca, cb, side = oracle.two_means(u, 20)
+    truth = np.r_[np.zeros(70, dtype=int), np.ones(50, dtype=int)]
+    if truth[first] == 1:
+        truth = 1 - truth
+    assert np.array_equal(side, truth)
+    assert np.allclose(ca, u[side == 0].mean(axis=0), rtol=0, atol=1e-12)
+    assert np.allclose(cb, u[side == 1].mean(axis=0), rtol=0, atol=1e-12)
