@@ -14,6 +14,12 @@ time of ns_run, inputs and live set already on the device); evaluations per
 second are reported beside it.  Every run's log Z is checked against the
 oracle's mean on the same workload (|dlogZ| < 2 combined sigma) and against
 the transfer-matrix quadrature value.
+
+Other modes (one JSON line each): --workload 4 / 5 (27-d emulator runs, with
+--prec f32|bf16x3 and --no-screen), --lik-sweep (the batched emulator
+likelihood at 200 ... 25,600 rows per call), --select-sweep (worst-1000
+selection at N = 2^16 ... 2^24) and --cluster-sweep (one cluster-tree node at
+N = 2^16 ... 2^24).
 """
 import argparse
 import json
@@ -90,6 +96,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--select-sweep", action="store_true",
                     help="worst-1000 selection alone at N = 2^16 ... 2^24 (HBM streaming passes)")
+    ap.add_argument("--cluster-sweep", action="store_true",
+                    help="one cluster-tree node (mean, covariance, 2-means) at N = 2^16 ... 2^24, d = 10")
     ap.add_argument("--lik-sweep", action="store_true",
                     help="batched emulator likelihood alone at M = 200 ... 25600 rows per call")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -119,6 +127,8 @@ def main():
         return bench_lik_sweep(args, np, torch, native, workloads)
     if args.select_sweep:
         return bench_select_sweep(args, np, torch, native)
+    if args.cluster_sweep:
+        return bench_cluster_sweep(args, np, torch, native)
     if args.workload in (4, 5):
         return bench_emulator(args, np, torch, native, workloads)
     spec = workloads.likelihood(2)
@@ -270,6 +280,48 @@ def bench_select_sweep(args, np, torch, native):
     print(json.dumps({"metric": "worst-m selection, N sweep", "dtype": "f64", "data": "synthetic",
                       "peak_gbs": HBM_PEAK / 1e9, "config": {"workload": "select worst 1000 of N(-100,30^2)"},
                       "sweep": res}))
+
+
+def bench_cluster_sweep(args, np, torch, native):
+    """ns_cluster_split (mean, covariance, k-means split of one node) on N
+    points in d = 10 (two Gaussian blobs, sd 0.05, clipped to the unit cube;
+    FP32) at N = 2^16 ... 2^24, timed with torch events on its stream.  Each
+    pass streams the N x d FP32 points (the Lloyd passes also read and write
+    one side byte per point); the achieved rate counts 4 N d bytes per pass."""
+    d, iters = 10, 20
+    work = torch.empty(native.ns_cluster_split_work_bytes(), dtype=torch.uint8, device="cuda:0")
+    gen = torch.Generator().manual_seed(0)
+    res = []
+    for lg in (16, 18, 20, 22, 24):
+        N = 1 << lg
+        c = torch.rand((2, d), generator=gen, dtype=torch.float64) * 0.6 + 0.2
+        lab = torch.randint(0, 2, (N,), generator=gen)
+        u = (c[lab] + 0.05 * torch.randn((N, d), generator=gen, dtype=torch.float64)).clamp(0, 1)
+        u = u.to(torch.float32).to("cuda:0")
+        mean = torch.zeros(d, dtype=torch.float64, device="cuda:0")
+        cov = torch.zeros((d, d), dtype=torch.float64, device="cuda:0")
+        cen = torch.zeros((2, 32), dtype=torch.float64, device="cuda:0")
+        side = torch.zeros(N, dtype=torch.uint8, device="cuda:0")
+        passes = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+        native.ns_cluster_split(u, iters, mean, cov, cen, side, work, passes)
+        torch.cuda.synchronize()
+        reps = max(5, min(100, (1 << 26) // N))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            native.ns_cluster_split(u, iters, mean, cov, cen, side, work, passes)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3 / reps
+        npass = int(passes.item())
+        bw = npass * 4.0 * N * d / t
+        res.append({"N": N, "d": d, "us_per_call": 1e6 * t, "passes": npass, "hbm_gbs": bw / 1e9,
+                    "hbm_frac": bw / HBM_PEAK})
+        print(f"[bench] cluster N=2^{lg}: {1e6 * t:.1f} us, {npass} passes, {bw / 1e9:.0f} GB/s",
+              file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "cluster-tree node (mean, covariance, 2-means), N sweep", "dtype": "f64",
+                      "data": "synthetic", "peak_gbs": HBM_PEAK / 1e9,
+                      "config": {"workload": "two blobs in [0,1]^10, FP32 points"}, "sweep": res}))
 
 
 def bench_lik_sweep(args, np, torch, native, workloads):

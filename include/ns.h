@@ -212,6 +212,38 @@ ns_status ns_loglike_batch(ns_ctx* c, const double* d_u, int64_t n, double* d_ou
  * as -inf, -0 as +0).  d_logL: N doubles, d_order: N ints (device).  N <= 8192. */
 ns_status ns_select_order(const double* d_logL, int N, int* d_order, void* hip_stream);
 
+/* Algorithm 1 "sorted" at scale: the m entries with the smallest (logL, index)
+ * (NaN counts as -inf, -0 as +0), ascending, the same order as the first m of
+ * ns_select_order, for 1 <= N <= 2^31 - 1 and 1 <= m <= min(N, 4096).  A
+ * radix select over the FP64 order key (and, for ties, the index) makes one
+ * streaming pass over d_logL per resolved 12-bit digit until at most 8192
+ * entries remain at or below the resolved prefix, then one collect pass and
+ * a sort of those candidates.  d_logL: N doubles, 16-byte aligned (device);
+ * d_slots: m ints (device, written); d_work: ns_select_worst_work_bytes()
+ * bytes of device workspace, 256-byte aligned, caller-owned, overwritten
+ * (calls that overlap in time must not share it); d_passes (device, may be
+ * NULL): receives the number of passes made over d_logL.  Enqueued on
+ * hip_stream; NS_EINVAL on bad sizes or alignment. */
+size_t ns_select_worst_work_bytes(void);
+/* One node of the cluster tree (Sec. 2.1) for large point sets: mean,
+ * unbiased covariance and the k-means split (k = 2; start at the point
+ * farthest from the mean and the point farthest from that one, lowest index
+ * on ties; a point joins the first centre on a distance tie; Lloyd updates
+ * until no assignment changes or after iters updates; an empty side keeps its
+ * centre), as the tree kernels compute them per node, for 2 <= N <= 2^31 - 1
+ * and 1 <= d <= 32.  Every statistic is one streaming pass over d_u.  d_u:
+ * N x d FP32, row major (device); d_mean: d doubles; d_cov: d x d doubles
+ * (row stride d); d_centres: 2 x 32 doubles (row 0 the first centre);
+ * d_side: N bytes (0 or 1); d_work: ns_cluster_split_work_bytes() bytes of
+ * device workspace, 256-byte aligned, caller-owned (calls that overlap in time
+ * must not share it); d_passes (may be NULL): passes made over d_u.  Enqueued
+ * on hip_stream; NS_EINVAL on bad sizes or alignment. */
+size_t ns_cluster_split_work_bytes(void);
+ns_status ns_cluster_split(const float* d_u, int64_t N, int d, int iters, double* d_mean, double* d_cov,
+                           double* d_centres, uint8_t* d_side, void* d_work, int* d_passes, void* hip_stream);
+ns_status ns_select_worst(const double* d_logL, int64_t N, int m, int* d_slots, void* d_work, int* d_passes,
+                          void* hip_stream);
+
 /* Algorithms 1 and 2 on explicit arrays (device): d_wlogL (m, ascending),
  * d_nlogL (m), d_P (m thresholds), d_hist (T*m, row t, column = chain),
  * d_hist_n (m).  Outputs (device, m each): accepted and rejected entries as

@@ -1,0 +1,319 @@
+// k_select_large.hip -- the m worst of N likelihoods for N far beyond one
+// workgroup (Algorithm 1's selection, "sorted", at scale).
+//
+// Radix select on the composite (order key, index): the FP64 order key is
+// resolved from its top bits in 12-bit digits (then 4), and when the key alone
+// cannot separate the m-th entry (ties) the index follows in 12-bit digits.
+// Every digit costs one streaming pass over logL: each workgroup builds a
+// histogram of the digit among the entries that share the resolved prefix (in
+// LDS) and writes it out; a small kernel sums the partial histograms and its
+// last workgroup picks the bin that holds the m-th entry.  Once at most kSelCap entries lie at or
+// below the resolved prefix, one more pass collects them and a single
+// workgroup sorts them by (key, index) and writes the first m indices.  The
+// result equals a stable sort of (canon(logL), index).
+#include <algorithm>
+#include "ns_device.hpp"
+#include "ns_select_large.hpp"
+
+namespace ns {
+
+constexpr int kRBits = 12, kRBins = 1 << kRBits;
+constexpr int kSelCap = 8192;      // candidates sorted by the last kernel
+constexpr int kSelMaxM = 4096;
+constexpr int kSelLevels = 9;      // key digits 52, 40, 28, 16, 4, 0; index digits 20, 8, 0
+constexpr int kSelGroups = 512;    // workgroups of a histogram pass (one partial histogram each)
+
+struct SelState {
+  unsigned long long kprefix;  // resolved key bits (those at and above kshift)
+  unsigned int sprefix;        // resolved index bits (at and above sshift)
+  int kshift;                  // 64: no key bit resolved yet
+  int sshift;                  // 32: no index bit resolved yet
+  int below;                   // entries strictly below the resolved prefix
+  int done;                    // at most kSelCap entries at or below the prefix
+  unsigned int ticket;         // workgroups finished in the current pass
+  int ncand;                   // entries collected
+  int passes;                  // streaming passes over logL so far
+};
+
+struct SelWork {
+  SelState st;
+  unsigned int pad[48];
+  unsigned int hist[kRBins];
+  unsigned int part[kSelGroups][kRBins];
+  unsigned long long ckey[kSelCap];
+  int cidx[kSelCap];
+};
+
+__host__ __device__ constexpr size_t sel_work_bytes() { return sizeof(SelWork); }
+
+struct Level {
+  int slot_phase, shift, width;
+};
+__host__ __device__ inline Level sel_level(int l) {
+  const Level L[kSelLevels] = {{0, 52, 12}, {0, 40, 12}, {0, 28, 12}, {0, 16, 12}, {0, 4, 12}, {0, 0, 4},
+                               {1, 20, 12}, {1, 8, 12}, {1, 0, 8}};
+  return L[l];
+}
+
+// entry relative to the resolved prefix: -1 below, 0 in it, 1 above
+__device__ __forceinline__ int sel_rel(unsigned long long key, unsigned int idx, const SelState& s) {
+  if (s.kshift == 64) return 0;
+  const unsigned long long kh = key >> s.kshift;
+  if (kh != s.kprefix) return kh < s.kprefix ? -1 : 1;
+  if (s.sshift == 32) return 0;
+  const unsigned int ih = idx >> s.sshift;
+  if (ih != s.sprefix) return ih < s.sprefix ? -1 : 1;
+  return 0;
+}
+
+__global__ void k_rsel_init(long N, int m, SelWork* w) {
+  for (int b = threadIdx.x; b < kRBins; b += blockDim.x) w->hist[b] = 0u;
+  if (threadIdx.x == 0) {
+    SelState s{};
+    s.kprefix = 0ull;
+    s.sprefix = 0u;
+    s.kshift = 64;
+    s.sshift = 32;
+    s.below = 0;
+    s.done = N <= kSelCap ? 1 : 0;
+    s.ticket = 0u;
+    s.ncand = 0;
+    s.passes = 0;
+    w->st = s;
+  }
+}
+
+// One digit, pass 1 of 2: each workgroup counts the digit of the entries in
+// the resolved prefix (LDS histogram) and writes its partial histogram.  Each
+// thread loads eight pairs of likelihoods (16-byte loads) before counting them;
+// lanes of a wave with the same digit are merged into one LDS atomic for up to
+// four distinct digits (likelihoods often share their leading bits), the rest
+// add one by one.
+__global__ void __launch_bounds__(256)
+k_rsel_hist(const double* __restrict__ logL, long N, int level, SelWork* __restrict__ w) {
+  __shared__ unsigned int lh[kRBins];
+  if (w->st.done) return;
+  const SelState s = w->st;
+  const Level L = sel_level(level);
+  const unsigned int mask = (1u << L.width) - 1u;
+  const int lane = threadIdx.x & 63;
+  for (int b = threadIdx.x; b < kRBins; b += blockDim.x) lh[b] = 0u;
+  __syncthreads();
+  const long npair = (N + 1) >> 1;
+  const long stride = static_cast<long>(gridDim.x) * blockDim.x;
+  const long span = (npair + stride - 1) / stride * stride;   // whole waves run every iteration
+  const double2* lp = reinterpret_cast<const double2*>(logL);
+  for (long p0 = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x; p0 < span; p0 += 8 * stride) {
+    double2 v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const long p = min(p0 + q * stride, npair - 1);
+      if (2 * p + 1 < N) {
+        v[q] = lp[p];
+      } else {
+        v[q].x = logL[2 * p];
+        v[q].y = 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const long i = 2 * (p0 + q * stride) + h;
+        bool pend = false;
+        unsigned int dg = 0u;
+        if (p0 + q * stride < npair && i < N) {
+          const unsigned long long key = order_key(h ? v[q].y : v[q].x);
+          if (sel_rel(key, static_cast<unsigned int>(i), s) == 0) {
+            pend = true;
+            dg = L.slot_phase ? ((static_cast<unsigned int>(i) >> L.shift) & mask)
+                              : static_cast<unsigned int>((key >> L.shift) & mask);
+          }
+        }
+        uint64_t act = __ballot(pend);
+        for (int r = 0; r < 4 && act; ++r) {
+          const int lead = __builtin_ctzll(act);
+          const unsigned int dl = __shfl(dg, lead);
+          const uint64_t same = __ballot(pend && dg == dl);
+          if (lane == lead) atomicAdd(&lh[dl], static_cast<unsigned int>(__popcll(same)));
+          if (pend && dg == dl) pend = false;
+          act = __ballot(pend);
+        }
+        if (pend) atomicAdd(&lh[dg], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  unsigned int* out = w->part[blockIdx.x];
+  for (int b = threadIdx.x; b < kRBins; b += blockDim.x) out[b] = lh[b];
+}
+
+// One digit, pass 2 of 2: the partial histograms summed per bin (in
+// workgroup order); the last workgroup to finish picks the bin that holds the
+// m-th entry and advances the resolved prefix.
+__global__ void __launch_bounds__(256)
+k_rsel_reduce(int groups, int m, int level, SelWork* __restrict__ w) {
+  __shared__ int s_last;
+  __shared__ unsigned int qs[256];
+  if (w->st.done) return;
+  // 64 bins per workgroup (gridDim.x * 64 == kRBins); the four waves take
+  // every fourth partial, then their four sums are added in wave order
+  const int b = blockIdx.x * 64 + (threadIdx.x & 63), qq = threadIdx.x >> 6;
+  unsigned int t = 0u;
+  for (int g0 = qq; g0 < groups; g0 += 4 * 8) {
+    unsigned int v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = w->part[min(g0 + 4 * j, groups - 1)][b];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (g0 + 4 * j < groups) t += v[j];
+  }
+  qs[threadIdx.x] = t;
+  __syncthreads();
+  if (qq == 0) w->hist[b] = ((qs[threadIdx.x] + qs[64 + threadIdx.x]) + qs[128 + threadIdx.x]) + qs[192 + threadIdx.x];
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = atomicAdd(&w->st.ticket, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  const SelState s = w->st;
+  const Level L = sel_level(level);
+  // last workgroup: inclusive scan of the histogram (16 bins per thread, then
+  // the 256 thread totals), first bin where below + cum >= m
+  __shared__ unsigned int tsum[256];
+  __shared__ int s_bin, s_before;
+  const int tt = threadIdx.x;
+  unsigned int hb[16], run = 0u;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    hb[q] = atomicAdd(&w->hist[16 * tt + q], 0u);
+    run += hb[q];
+  }
+  tsum[tt] = run;
+  if (tt == 0) s_bin = -1;
+  __syncthreads();
+  unsigned int before = 0u;
+  for (int q = 0; q < tt; ++q) before += tsum[q];
+  const long need = static_cast<long>(m) - s.below;
+  unsigned int c = before;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    if (static_cast<long>(c) < need && static_cast<long>(c + hb[q]) >= need) {
+      s_bin = 16 * tt + q;
+      s_before = static_cast<int>(c);
+    }
+    c += hb[q];
+  }
+  __syncthreads();
+  if (tt == 0) {
+    const int bin = s_bin;
+    const unsigned int cnt = atomicAdd(&w->hist[bin], 0u);
+    SelState n = s;
+    if (L.slot_phase) {
+      n.sprefix = (n.sshift == 32) ? static_cast<unsigned int>(bin) : ((n.sprefix << L.width) | bin);
+      n.sshift = L.shift;
+    } else {
+      n.kprefix = (n.kshift == 64) ? static_cast<unsigned long long>(bin)
+                                   : ((n.kprefix << L.width) | static_cast<unsigned long long>(bin));
+      n.kshift = L.shift;
+    }
+    n.below = s.below + s_before;
+    n.done = (static_cast<long>(n.below) + cnt <= kSelCap) ? 1 : 0;
+    n.ticket = 0u;
+    n.passes = s.passes + 1;
+    w->st = n;
+  }
+}
+
+// Every entry at or below the resolved prefix (at most kSelCap) into the
+// candidate list, one atomic per wave.
+__global__ void __launch_bounds__(256)
+k_rsel_collect(const double* __restrict__ logL, long N, SelWork* __restrict__ w) {
+  const SelState s = w->st;
+  const long stride = static_cast<long>(gridDim.x) * blockDim.x;
+  const int lane = threadIdx.x & 63;
+  const long n_up = (N + 63) / 64 * 64;   // whole waves run every iteration (ballots)
+  for (long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n_up; i += stride) {
+    unsigned long long key = 0ull;
+    bool take = false;
+    if (i < N) {
+      key = order_key(logL[i]);
+      take = sel_rel(key, static_cast<unsigned int>(i), s) <= 0;
+    }
+    const unsigned long long bal = __ballot(take);
+    if (!bal) continue;
+    int base = 0;
+    if (lane == 0) base = atomicAdd(&w->st.ncand, __popcll(bal));
+    base = __shfl(base, 0);
+    if (take) {
+      const int pos = base + __popcll(bal & ((1ull << lane) - 1ull));
+      if (pos < kSelCap) {
+        w->ckey[pos] = key;
+        w->cidx[pos] = static_cast<int>(i);
+      }
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&w->st.passes, 1);
+}
+
+// The candidates sorted by (key, index) in LDS (bitonic), first m indices out.
+__global__ void __launch_bounds__(1024)
+k_rsel_sort(int m, SelWork* __restrict__ w, int* __restrict__ out, int* __restrict__ passes) {
+  __shared__ unsigned long long K[kSelCap];
+  __shared__ int I[kSelCap];
+  const int n = min(w->st.ncand, kSelCap);
+  int P = 1;
+  while (P < n) P <<= 1;
+  for (int q = threadIdx.x; q < P; q += blockDim.x) {
+    K[q] = q < n ? w->ckey[q] : ~0ull;
+    I[q] = q < n ? w->cidx[q] : 0x7fffffff;
+  }
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int q = threadIdx.x; q < P; q += blockDim.x) {
+        const int r = q ^ j;
+        if (r > q) {
+          const bool up = (q & k) == 0;
+          const bool gt = K[q] > K[r] || (K[q] == K[r] && I[q] > I[r]);
+          if (gt == up) {
+            const unsigned long long tk = K[q]; K[q] = K[r]; K[r] = tk;
+            const int ti = I[q]; I[q] = I[r]; I[r] = ti;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int q = threadIdx.x; q < m; q += blockDim.x) out[q] = I[q];
+  if (passes && threadIdx.x == 0) *passes = w->st.passes;
+}
+
+size_t select_large_work_bytes() { return sel_work_bytes(); }
+
+hipError_t launch_select_large(const double* logL, long N, int m, int* out, void* work, int* passes,
+                               hipStream_t s) {
+  if (m < 1 || m > kSelMaxM || m > N) return hipErrorInvalidValue;
+  SelWork* w = static_cast<SelWork*>(work);
+  hipLaunchKernelGGL(k_rsel_init, dim3(1), dim3(256), 0, s, N, m, w);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long npair = (N + 1) / 2;
+  const int grid = static_cast<int>(std::min<long>(kSelGroups, std::max<long>(1, (npair + 1023) / 1024)));
+  for (int l = 0; l < kSelLevels; ++l) {
+    hipLaunchKernelGGL(k_rsel_hist, dim3(grid), dim3(256), 0, s, logL, N, l, w);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rsel_reduce, dim3(kRBins / 64), dim3(256), 0, s, grid, m, l, w);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int cgrid = static_cast<int>(std::min<long>(2048, std::max<long>(1, (N + 255) / 256)));
+  hipLaunchKernelGGL(k_rsel_collect, dim3(cgrid), dim3(256), 0, s, logL, N, w);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rsel_sort, dim3(1), dim3(1024), 0, s, m, w, out, passes);
+  return hipGetLastError();
+}
+
+}  // namespace ns

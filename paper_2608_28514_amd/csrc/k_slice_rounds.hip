@@ -390,12 +390,20 @@ __global__ void k_rows_from_points(long n, int d, const double* __restrict__ u, 
                                    T* __restrict__ pts, float* __restrict__ xin, int* __restrict__ flag) {
   const long k = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  for (int i = 0; i < d; ++i) {
-    const T yi = static_cast<T>(u[k * d + i]);
+  // the row's coordinates loaded together, the box test on the registers
+  double y[kMaxD];
+#pragma unroll
+  for (int i = 0; i < kMaxD; ++i) y[i] = i < d ? u[k * d + i] : 0.0;
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < kMaxD; ++i) {
+    if (i >= d) continue;
+    const T yi = static_cast<T>(y[i]);
     pts[k * d + i] = yi;
     xin[k * d + i] = p.lo_f[i] + p.span_f[i] * static_cast<float>(yi);
+    ok &= (yi >= T(0)) & (yi <= T(1));
   }
-  flag[k] = in_box(pts + k * d, d) ? 1 : 0;
+  flag[k] = ok ? 1 : 0;
 }
 
 hipError_t launch_rows_from_points(long n, int d, const double* u, const RoundsParams& p, int state_f32,

@@ -14,6 +14,8 @@
 #include "ns_internal.hpp"
 #include "ns_gemm.hpp"
 #include "ns_rounds.hpp"
+#include "ns_select_large.hpp"
+#include "ns_cluster_large.hpp"
 #include "ns_surrogate.hpp"
 
 using namespace ns;
@@ -1118,6 +1120,35 @@ ns_status ns_loglike_batch(ns_ctx* c, const double* d_u, int64_t n, double* d_ou
     NS_TRY(hipMemcpyAsync(d_out + k0, c->rb.rlogL, sizeof(double) * nn, hipMemcpyDeviceToDevice,
                           c->stream));
   }
+  return NS_OK;
+}
+
+size_t ns_select_worst_work_bytes(void) { return select_large_work_bytes(); }
+
+size_t ns_cluster_split_work_bytes(void) { return cluster_split_work_bytes(); }
+
+ns_status ns_cluster_split(const float* d_u, int64_t N, int d, int iters, double* d_mean, double* d_cov,
+                           double* d_centres, uint8_t* d_side, void* d_work, int* d_passes, void* hip_stream) {
+  ns_ctx* c = nullptr;
+  if (!d_u || !d_mean || !d_cov || !d_centres || !d_side || !d_work || N < 2 || N > 2147483647LL || d < 1 ||
+      d > kMaxD || iters < 0)
+    return inval(nullptr, "ns_cluster_split: bad arguments");
+  if (reinterpret_cast<uintptr_t>(d_work) % 256 != 0 || reinterpret_cast<uintptr_t>(d_u) % 4 != 0)
+    return inval(nullptr, "ns_cluster_split: d_work must be 256-byte aligned");
+  NS_TRY(launch_cluster_split(d_u, static_cast<long>(N), d, iters, d_mean, d_cov, d_centres, d_side, d_work,
+                              d_passes, static_cast<hipStream_t>(hip_stream)));
+  return NS_OK;
+}
+
+ns_status ns_select_worst(const double* d_logL, int64_t N, int m, int* d_slots, void* d_work, int* d_passes,
+                          void* hip_stream) {
+  ns_ctx* c = nullptr;
+  if (!d_logL || !d_slots || !d_work || N < 1 || N > 2147483647LL || m < 1 || m > 4096 || m > N)
+    return inval(nullptr, "ns_select_worst: bad arguments");
+  if (reinterpret_cast<uintptr_t>(d_logL) % 16 != 0 || reinterpret_cast<uintptr_t>(d_work) % 256 != 0)
+    return inval(nullptr, "ns_select_worst: d_logL must be 16-byte and d_work 256-byte aligned");
+  NS_TRY(launch_select_large(d_logL, static_cast<long>(N), m, d_slots, d_work, d_passes,
+                             static_cast<hipStream_t>(hip_stream)));
   return NS_OK;
 }
 

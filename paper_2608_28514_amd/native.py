@@ -106,6 +106,10 @@ def lib():
             "ns_stats": [vp, C.POINTER(NsStats)],
             "ns_loglike_batch": [vp, vp, C.c_int64, vp],
             "ns_select_order": [vp, C.c_int, vp, vp],
+            "ns_select_worst_work_bytes": [],
+            "ns_select_worst": [vp, C.c_int64, C.c_int, vp, vp, vp, vp],
+            "ns_cluster_split_work_bytes": [],
+            "ns_cluster_split": [vp, C.c_int64, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp],
             "ns_correct_batch": [C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp,
                                  vp, vp, vp, vp],
             "ns_philox": [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int64, vp,
@@ -124,6 +128,8 @@ def lib():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = C.c_int
+        L.ns_select_worst_work_bytes.restype = C.c_size_t
+        L.ns_cluster_split_work_bytes.restype = C.c_size_t
         L.ns_last_error.argtypes = [vp]
         L.ns_last_error.restype = C.c_char_p
         L.ns_free.argtypes = [vp]
@@ -290,6 +296,33 @@ def ns_loglike_batch(ctx, d_u, d_out):
     """d_u: torch float64 (n, d) on the device; d_out: torch float64 (n,)."""
     _check(lib().ns_loglike_batch(ctx, _ptr(d_u), int(d_out.numel()), _ptr(d_out)), ctx,
            "ns_loglike_batch")
+
+
+def ns_select_worst(d_logL, m, d_slots, d_work, d_passes=None, stream=None):
+    """The m worst entries of d_logL (torch float64, device) into d_slots
+    (torch int32, device), ascending; d_work: a device buffer of at least
+    ns_select_worst_work_bytes() bytes; d_passes: optional int32 device tensor."""
+    _check(lib().ns_select_worst(_ptr(d_logL), int(d_logL.numel()), int(m), _ptr(d_slots), _ptr(d_work),
+                                 _ptr(d_passes) if d_passes is not None else None, _stream(stream)),
+           None, "ns_select_worst")
+
+
+def ns_select_worst_work_bytes():
+    return int(lib().ns_select_worst_work_bytes())
+
+
+def ns_cluster_split(d_u, iters, d_mean, d_cov, d_centres, d_side, d_work, d_passes=None, stream=None):
+    """One cluster-tree node of the points d_u (torch float32 (N, d), device):
+    mean (d), covariance (d, d), centres (2, 32) and side (N, uint8)."""
+    N, d = d_u.shape
+    _check(lib().ns_cluster_split(_ptr(d_u), int(N), int(d), int(iters), _ptr(d_mean), _ptr(d_cov),
+                                  _ptr(d_centres), _ptr(d_side), _ptr(d_work),
+                                  _ptr(d_passes) if d_passes is not None else None, _stream(stream)),
+           None, "ns_cluster_split")
+
+
+def ns_cluster_split_work_bytes():
+    return int(lib().ns_cluster_split_work_bytes())
 
 
 def ns_select_order(d_logL, d_order, stream=None):
