@@ -2,10 +2,19 @@
 // sets far beyond one workgroup: mean, unbiased covariance and the k-means
 // split (k = 2, Lloyd) of N points, as the tree kernels compute them per node.
 //
-// Every statistic is one streaming pass over the points: workgroups of one
-// wave take contiguous chunks, each lane accumulates its points in FP64, the
-// wave reduces with a fixed butterfly and writes one partial per workgroup; a
-// single workgroup then adds the partials in workgroup order (deterministic).
+// Every statistic is one streaming pass over the points: workgroups of four
+// waves take contiguous chunks and stage 256 points at a time in LDS (16-byte
+// loads, the next two tiles in flight while one is used; an odd point stride
+// in LDS so that lanes reading consecutive points hit distinct banks).  Lanes
+// accumulate in FP64, waves reduce with a fixed butterfly, one partial per
+// workgroup is written, and a single workgroup adds the partials in workgroup
+// order (deterministic).
+// For d <= 16 the mean and covariance come from one pass of moments about the
+// first point c: S = sum (x - c), Q = sum (x - c)(x - c)^T (fused
+// multiply-adds), mean = c + S / N,
+// cov = (Q - S S^T / N) / (N - 1) (the same quantities as the centred
+// definition; the shift keeps the terms at the scale of the spread); for
+// d > 16 a centred pass follows the mean pass.
 // The split starts from the point farthest from the mean and the point
 // farthest from that one (lowest index on ties), assigns a point to the first
 // centre on a distance tie, and runs Lloyd updates until no assignment
@@ -17,8 +26,13 @@
 
 namespace ns {
 
-constexpr int kCLGroups = 2048;     // workgroups (one wave each) of a pass
-constexpr int kCLPart = 528;        // doubles per partial: max(d (d + 1) / 2, 2 d + 2) for d <= 32
+// amdgpu_waves_per_eu(4) on the moments pass: at most 128 VGPRs, four
+// workgroups per CU (for d <= 12; wider points keep their registers)
+#define NS_CL_OCC __attribute__((amdgpu_waves_per_eu(DM <= 12 ? 4 : 1)))
+
+constexpr int kCLGroups = 1024;     // workgroups of a pass
+constexpr int kCLTile = 256;        // points staged per step (one per thread)
+constexpr int kCLPart = 528;        // doubles per partial: max(d + d (d + 1) / 2 (d <= 16), d (d + 1) / 2, 2 d + 2)
 
 struct CLState {
   double ca[kMaxD], cb[kMaxD];
@@ -27,12 +41,18 @@ struct CLState {
   int n0, n1;
 };
 
+constexpr int kCLFan = 32;          // partial rows per workgroup of a reduction kernel
+constexpr int kCLFirst = kCLGroups / kCLFan;
+
 struct CLWork {
   CLState st;
-  double pad[8];
-  double part[kCLGroups][kCLPart];
-  double pv[kCLGroups];
-  long pi[kCLGroups];
+  unsigned int tt;                  // finished workgroups of a reduction kernel
+  unsigned int pad0;
+  double pad[7];
+  double part[kCLGroups][kCLPart];  // one partial per workgroup
+  double gpart[kCLFirst][kCLPart];  // one partial per group
+  double pv[kCLGroups], gpv[kCLFirst];
+  long pi[kCLGroups], gpi[kCLFirst];
 };
 
 size_t cluster_split_work_bytes() { return sizeof(CLWork); }
@@ -42,158 +62,383 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// chunk of workgroup g: points [lo, hi)
+// Ticket of a reduction level: true in the workgroup that finishes it (the
+// counter is reset there for the next pass).
+__device__ __forceinline__ bool last_in(unsigned int* ctr, int n, int* s_go) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *s_go = atomicAdd(ctr, 1u) == static_cast<unsigned int>(n - 1);
+    if (*s_go) atomicExch(ctr, 0u);
+  }
+  __syncthreads();
+  if (!*s_go) return false;
+  __threadfence();
+  return true;
+}
+
+// Reduction kernels run on ceil(G / 32) workgroups after a pass wrote its G
+// partial rows.  red_sum: workgroup b adds rows 32 b .. 32 b + 31 of part in
+// order into gpart[b]; the last workgroup to finish adds the gpart rows in
+// order into tot (LDS) and returns true.
+__device__ bool red_sum(CLWork* w, int G, int nc, double* tot) {
+  __shared__ int s_go;
+  const int b = blockIdx.x, g0 = kCLFan * b, gsz = min(kCLFan, G - g0), ng = gridDim.x;
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    double a = 0.0;
+    for (int j0 = 0; j0 < gsz; j0 += 16) {
+      double v[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] = j0 + j < gsz ? w->part[g0 + j0 + j][c] : 0.0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (j0 + j < gsz) a = (j0 + j == 0) ? v[j] : a + v[j];
+    }
+    w->gpart[b][c] = a;
+  }
+  if (!last_in(&w->tt, ng, &s_go)) return false;
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    double a = 0.0;
+    for (int j0 = 0; j0 < ng; j0 += 16) {
+      double v[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] = j0 + j < ng ? w->gpart[j0 + j][c] : 0.0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (j0 + j < ng) a = (j0 + j == 0) ? v[j] : a + v[j];
+    }
+    tot[c] = a;
+  }
+  __syncthreads();
+  return true;
+}
+
+// the same for the farthest-point partials (pv, pi): largest value, lowest
+// index on ties; the result in *bv, *bi of the returning workgroup (thread 0).
+// Each level: thread j < 32 loads entry j, thread 0 scans them in order.
+__device__ bool red_argmax(CLWork* w, int G, double* bv, long* bi) {
+  __shared__ int s_go;
+  __shared__ double sv[kCLFan];
+  __shared__ long si[kCLFan];
+  const int b = blockIdx.x, g0 = kCLFan * b, gsz = min(kCLFan, G - g0), ng = gridDim.x;
+  auto scan = [&](int n, double* v, long* ix) {
+    *v = -1.0;
+    *ix = 0x7fffffffffffffffL;
+    for (int j = 0; j < n; ++j)
+      if (sv[j] > *v || (sv[j] == *v && si[j] < *ix)) { *v = sv[j]; *ix = si[j]; }
+  };
+  if (threadIdx.x < gsz) { sv[threadIdx.x] = w->pv[g0 + threadIdx.x]; si[threadIdx.x] = w->pi[g0 + threadIdx.x]; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double v;
+    long ix;
+    scan(gsz, &v, &ix);
+    w->gpv[b] = v;
+    w->gpi[b] = ix;
+  }
+  if (!last_in(&w->tt, ng, &s_go)) return false;
+  if (threadIdx.x < ng) { sv[threadIdx.x] = w->gpv[threadIdx.x]; si[threadIdx.x] = w->gpi[threadIdx.x]; }
+  __syncthreads();
+  if (threadIdx.x == 0) scan(ng, bv, bi);
+  return true;
+}
+
+// chunk of workgroup g: points [lo, hi), lo a multiple of 4 (so that tiles
+// start on 16-byte boundaries of an aligned array)
 __device__ __forceinline__ void chunk_of(long N, long* lo, long* hi) {
-  const long per = (N + gridDim.x - 1) / gridDim.x;
+  long per = (N + gridDim.x - 1) / gridDim.x;
+  per = (per + 3) & ~3L;
   *lo = min(N, static_cast<long>(blockIdx.x) * per);
   *hi = min(N, *lo + per);
 }
 
+// LDS floats of a tile: 256 points at stride d | 1, or the 16-byte copy of
+// 256 d floats (d odd), whichever is longer
 template <int DM>
-__device__ __forceinline__ double sqdist_pt(const float* x, const double* c, int d) {
-  double s = 0.0;
-#pragma unroll
-  for (int i = 0; i < DM; ++i)
-    if (i < d) {
-      const double q = static_cast<double>(x[i]) - c[i];
-      s += q * q;
-    }
-  return s;
+constexpr int tile_quads() { return (DM + 3) / 4; }   // float4 loads per thread and tile
+template <int DM>
+constexpr int tile_floats() {
+  return tile_quads<DM>() * 4 * kCLTile > kCLTile * (DM + 1) ? tile_quads<DM>() * 4 * kCLTile : kCLTile * (DM + 1);
 }
 
-
-// Sum over the G partials of columns [c0, c0 + nc) (nc <= 32) by 256 threads:
-// thread t adds partials t, t + 256, ... (eight loads in flight), then a
-// fixed binary tree over the 256 threads.  out (LDS): out[c] for c < nc.
-__device__ void sum_partials(const CLWork* w, int groups, int c0, int nc, double* red /* 256 x 33 */,
-                             double* out) {
-  const int t = threadIdx.x;
-  double acc[32];
+// Loads of one tile: the nf = nt d floats from flat index f0 (a multiple of 4)
+// as float4 r[q] = floats 4 (t + 256 q) .. + 3; floats past nf read as 0.
+template <int QF>
+__device__ __forceinline__ void tile_fetch(const float* __restrict__ u, long f0, int nf, bool al, float4 (&r)[QF]) {
 #pragma unroll
-  for (int c = 0; c < 32; ++c) acc[c] = 0.0;
-  for (int g0 = t; g0 < groups; g0 += 8 * 256) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int g = g0 + 256 * j;
-      if (g >= groups) break;
-      const double* row = w->part[g] + c0;
-#pragma unroll
-      for (int c = 0; c < 32; ++c)
-        if (c < nc) acc[c] += row[c];
+  for (int q = 0; q < QF; ++q) {
+    const int e = 4 * (static_cast<int>(threadIdx.x) + kCLTile * q);
+    const float* p = u + f0 + e;
+    if (al && e + 4 <= nf) {
+      r[q] = *reinterpret_cast<const float4*>(p);
+    } else {
+      r[q].x = e < nf ? p[0] : 0.f;
+      r[q].y = e + 1 < nf ? p[1] : 0.f;
+      r[q].z = e + 2 < nf ? p[2] : 0.f;
+      r[q].w = e + 3 < nf ? p[3] : 0.f;
     }
   }
+}
+
+// Stores a fetched tile in LDS, point t at xs + t ds with ds = d | 1.  For
+// even d flat float e goes to e + e / d, the quotient by a multiply-shift
+// (exact for e < 2^13, d <= 32).
+template <int QF>
+__device__ __forceinline__ void tile_put(float* xs, int nf, int d, const float4 (&r)[QF]) {
+  if (d & 1) {
 #pragma unroll
-  for (int c = 0; c < 32; ++c)
-    if (c < nc) red[t * 33 + c] = acc[c];
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (t < off)
-      for (int c = 0; c < nc; ++c) red[t * 33 + c] += red[(t + off) * 33 + c];
+    for (int q = 0; q < QF; ++q) {
+      const int e = 4 * (static_cast<int>(threadIdx.x) + kCLTile * q);
+      if (e < nf) *reinterpret_cast<float4*>(xs + e) = r[q];
+    }
+  } else {
+    const unsigned int mg = ((1u << 20) + d - 1) / d;
+#pragma unroll
+    for (int q = 0; q < QF; ++q) {
+      const int e = 4 * (static_cast<int>(threadIdx.x) + kCLTile * q);
+      const float v[4] = {r[q].x, r[q].y, r[q].z, r[q].w};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const unsigned int el = static_cast<unsigned int>(e + c);
+        if (static_cast<int>(el) < nf) xs[el + ((el * mg) >> 20)] = v[c];
+      }
+    }
+  }
+}
+
+// The launcher rounds d up to an even DM (d <= 16), so d >= DM - 1 there:
+// told to the compiler, every coordinate guard but the last folds away.
+template <int DM>
+__device__ __forceinline__ void assume_dm(int d) {
+  if constexpr (DM <= 16) __builtin_assume(d >= DM - 1 && d <= DM);
+}
+
+// Tile layouts in LDS.  PutF: the floats, point t at xs + t (d | 1).
+struct PutF {
+  float* xs;
+  int d;
+  template <int QF>
+  __device__ __forceinline__ void operator()(int nf, const float4 (&r)[QF]) const { tile_put<QF>(xs, nf, d, r); }
+};
+
+// PutShift: the coordinates as doubles minus the shift cs (LDS, d entries),
+// point t at xd + t (d | 1)
+struct PutShift {
+  double* xd;
+  const double* cs;
+  int d;
+  template <int QF>
+  __device__ __forceinline__ void operator()(int nf, const float4 (&r)[QF]) const {
+    const unsigned int mg = ((1u << 20) + d - 1) / d, pad = (d & 1) ? 0u : 1u;
+#pragma unroll
+    for (int q = 0; q < QF; ++q) {
+      const int e = 4 * (static_cast<int>(threadIdx.x) + kCLTile * q);
+      const float v[4] = {r[q].x, r[q].y, r[q].z, r[q].w};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const unsigned int el = static_cast<unsigned int>(e + c);
+        if (static_cast<int>(el) < nf) {
+          const unsigned int pt = (el * mg) >> 20;
+          xd[el + pt * pad] = static_cast<double>(v[c]) - cs[el - pt * static_cast<unsigned int>(d)];
+        }
+      }
+    }
+  }
+};
+
+// Streams points [lo, hi) through LDS, 256 at a time: body(k0, nt, pv) runs
+// with points k0 .. k0 + nt - 1 stored by put while the next two tiles load.
+// pre (may be null): one byte per point fetched with its tile and handed to
+// body as pv (thread t: point k0 + t).
+template <int QF, class Put, class Body>
+__device__ __forceinline__ void stream_tiles(const float* __restrict__ u, int d, long lo, long hi, const Put& put,
+                                             const unsigned char* pre, Body&& body) {
+  const bool al = (reinterpret_cast<uintptr_t>(u) & 15) == 0;
+  const long n = hi - lo;
+  const long ntile = (n + kCLTile - 1) / kCLTile;
+  auto nf = [&](long k) { return static_cast<int>(min(static_cast<long>(kCLTile), n - k * kCLTile)) * d; };
+  auto fetch = [&](long k, float4 (&r)[QF], int& pb) {
+    tile_fetch<QF>(u, (lo + k * kCLTile) * d, nf(k), al, r);
+    const long i = lo + k * kCLTile + threadIdx.x;
+    pb = (pre != nullptr && i < hi) ? static_cast<int>(pre[i]) : 0;
+  };
+  float4 ra[QF], rb[QF];
+  int pa = 0, pb = 0;
+  if (ntile > 0) fetch(0, ra, pa);
+  if (ntile > 1) fetch(1, rb, pb);
+  for (long k = 0; k < ntile; k += 2) {
     __syncthreads();
+    put(nf(k), ra);
+    const int va = pa;
+    __syncthreads();
+    if (k + 2 < ntile) fetch(k + 2, ra, pa);
+    body(lo + k * kCLTile, nf(k) / d, va);
+    if (k + 1 < ntile) {
+      __syncthreads();
+      put(nf(k + 1), rb);
+      const int vb = pb;
+      __syncthreads();
+      if (k + 3 < ntile) fetch(k + 3, rb, pb);
+      body(lo + (k + 1) * kCLTile, nf(k + 1) / d, vb);
+    }
   }
-  if (t < nc) out[t] = red[t];
-  __syncthreads();
 }
 
-// pass: coordinate sums (mean).  DM: the dimension rounded up to 2, 4, 8, 16 or 32.
+// The moment list of a point x (coordinates minus the shift, zero past d):
+// entries S_0 .. S_{DM-1}, then Q_ij (j <= i) row by row.  Wave W of the
+// workgroup owns the entries e with e % 4 == W, in slot e / 4.
 template <int DM>
-__global__ void __launch_bounds__(64) k_cl_sum(const float* __restrict__ u, long N, int d, CLWork* __restrict__ w) {
-  long lo, hi;
-  chunk_of(N, &lo, &hi);
-  const int lane = threadIdx.x;
-  double s[DM];
-#pragma unroll
-  for (int i = 0; i < DM; ++i) s[i] = 0.0;
-  for (long k0 = lo + lane; k0 < hi; k0 += 4 * 64) {
-    // four points' coordinates loaded before they are added (in point order)
-    float xv[4][DM];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const long k = min(k0 + 64 * j, hi - 1);
-#pragma unroll
-      for (int i = 0; i < DM; ++i) xv[j][i] = i < d ? u[k * d + i] : 0.f;
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (k0 + 64 * j < hi)
-#pragma unroll
-        for (int i = 0; i < DM; ++i)
-          if (i < d) s[i] += static_cast<double>(xv[j][i]);
-  }
+constexpr int stats_slots() { return (DM + DM * (DM + 1) / 2 + 3) / 4; }
+
+template <int DM, int W>
+__device__ __forceinline__ void stats_acc(const double (&x)[DM], int d, double (&acc)[stats_slots<DM>()]) {
 #pragma unroll
   for (int i = 0; i < DM; ++i)
-    if (i < d) {
-      const double t = wave_sum(s[i]);
-      if (lane == 0) w->part[blockIdx.x][i] = t;
-    }
-}
-
-__global__ void __launch_bounds__(256)
-k_cl_mean(long N, int d, int groups, double* __restrict__ mean, CLWork* __restrict__ w) {
-  __shared__ double red[256 * 33];
-  __shared__ double tot[32];
-  sum_partials(w, groups, 0, d, red, tot);
-  const int i = threadIdx.x;
-  if (i < d) mean[i] = tot[i] / static_cast<double>(N);
-  if (i == 0) {
-    w->st.done = 0;
-    w->st.passes = 1;
-    w->st.iters_used = 0;
-  }
-}
-
-// pass: centred outer products (lower triangle, row by row), d <= 12: every
-// lane keeps the whole triangle of its points in registers, then the wave
-// reduces each entry with the fixed butterfly
-template <int DM>
-__global__ void __launch_bounds__(64)
-k_cl_cov_reg(const float* __restrict__ u, long N, int d, const double* __restrict__ mean, CLWork* __restrict__ w) {
-  constexpr int NP = DM * (DM + 1) / 2;
-  long lo, hi;
-  chunk_of(N, &lo, &hi);
-  const int lane = threadIdx.x;
-  double mu[DM];
-#pragma unroll
-  for (int i = 0; i < DM; ++i) mu[i] = i < d ? mean[i] : 0.0;
-  double acc[NP];
-#pragma unroll
-  for (int p = 0; p < NP; ++p) acc[p] = 0.0;
-  for (long k0 = lo + lane; k0 < hi; k0 += 2 * 64) {
-    float xv[2][DM];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const long k = min(k0 + 64 * j, hi - 1);
-#pragma unroll
-      for (int i = 0; i < DM; ++i) xv[j][i] = i < d ? u[k * d + i] : 0.f;
-    }
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      if (k0 + 64 * j >= hi) continue;
-      double x[DM];
-#pragma unroll
-      for (int i = 0; i < DM; ++i) x[i] = static_cast<double>(xv[j][i]) - mu[i];
-      int p = 0;
-#pragma unroll
-      for (int i = 0; i < DM; ++i)
-#pragma unroll
-        for (int jj = 0; jj <= i; ++jj, ++p)
-          if (i < d) acc[p] += x[i] * x[jj];
-    }
-  }
-  // entry (i, jj) of the DM triangle is entry i (i + 1) / 2 + jj of the d triangle too
-  int p = 0;
+    if (i % 4 == W) acc[i / 4] += x[i];
 #pragma unroll
   for (int i = 0; i < DM; ++i)
+    if (i < d)
 #pragma unroll
-    for (int jj = 0; jj <= i; ++jj, ++p)
-      if (i < d) {
-        const double t = wave_sum(acc[p]);
-        if (lane == 0) w->part[blockIdx.x][p] = t;
+      for (int j = 0; j <= i; ++j) {
+        const int e = DM + i * (i + 1) / 2 + j;
+        if (e % 4 == W) acc[e / 4] = __builtin_fma(x[i], x[j], acc[e / 4]);
       }
 }
 
-// pass: centred outer products (lower triangle, row by row), any d <= 32:
-// points staged in LDS, lanes own entries
+// wave W's entries over the points of a tile (shifted coordinates in LDS):
+// lane l takes points l, l + 64, l + 128, l + 192 (in that order)
+template <int DM, int W>
+__device__ __forceinline__ void stats_tile(const double* xd, int nt, int d, int ds, int lane,
+                                           double (&acc)[stats_slots<DM>()]) {
+#pragma unroll 1
+  for (int t = lane; t < nt; t += 64) {
+    double x[DM];
+#pragma unroll
+    for (int i = 0; i < DM; ++i) x[i] = i < d ? xd[t * ds + i] : 0.0;
+    stats_acc<DM, W>(x, d, acc);
+  }
+}
+
+// partial columns: S_i at i, Q_ij at d + i (i + 1) / 2 + j
+template <int DM, int W>
+__device__ __forceinline__ void stats_write(const double (&acc)[stats_slots<DM>()], int d, double* row, int lane) {
+#pragma unroll
+  for (int i = 0; i < DM; ++i)
+    if (i % 4 == W && i < d) {
+      const double v = wave_sum(acc[i / 4]);
+      if (lane == 0) row[i] = v;
+    }
+#pragma unroll
+  for (int i = 0; i < DM; ++i)
+    if (i < d)
+#pragma unroll
+      for (int j = 0; j <= i; ++j) {
+        const int e = DM + i * (i + 1) / 2 + j;
+        if (e % 4 == W) {
+          const double v = wave_sum(acc[e / 4]);
+          if (lane == 0) row[d + i * (i + 1) / 2 + j] = v;
+        }
+      }
+}
+
+// pass (d <= DM <= 16): moments about the first point.  Every wave takes all
+// points of a tile (lane l: points l, l + 64, l + 128, l + 192) for its share
+// of the entries.
+template <int DM>
+__global__ void __launch_bounds__(256) NS_CL_OCC
+k_cl_stats(const float* __restrict__ u, long N, int d, CLWork* __restrict__ w) {
+  constexpr int QF = tile_quads<DM>();
+  __shared__ double xd[kCLTile * (DM + 1)];
+  __shared__ double cs[DM];
+  long lo, hi;
+  assume_dm<DM>(d);
+  chunk_of(N, &lo, &hi);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, ds = d | 1;
+  if (threadIdx.x < d) cs[threadIdx.x] = static_cast<double>(u[threadIdx.x]);
+  __syncthreads();
+  double acc[stats_slots<DM>()];
+#pragma unroll
+  for (int q = 0; q < stats_slots<DM>(); ++q) acc[q] = 0.0;
+  stream_tiles<QF>(u, d, lo, hi, PutShift{xd, cs, d}, nullptr, [&](long, int nt, int) {
+    switch (wv) {
+      case 0: stats_tile<DM, 0>(xd, nt, d, ds, lane, acc); break;
+      case 1: stats_tile<DM, 1>(xd, nt, d, ds, lane, acc); break;
+      case 2: stats_tile<DM, 2>(xd, nt, d, ds, lane, acc); break;
+      default: stats_tile<DM, 3>(xd, nt, d, ds, lane, acc); break;
+    }
+  });
+  double* row = w->part[blockIdx.x];
+  switch (wv) {
+    case 0: stats_write<DM, 0>(acc, d, row, lane); break;
+    case 1: stats_write<DM, 1>(acc, d, row, lane); break;
+    case 2: stats_write<DM, 2>(acc, d, row, lane); break;
+    default: stats_write<DM, 3>(acc, d, row, lane); break;
+  }
+}
+
+// reduction of the moment partials; the last workgroup writes the mean and
+// the covariance
+__global__ void __launch_bounds__(256)
+k_cl_red_stats(const float* __restrict__ u, long N, int d, int G, double* __restrict__ mean,
+               double* __restrict__ cov, CLWork* __restrict__ w) {
+  __shared__ double tot[16 + 16 * 17 / 2];
+  const int np = d * (d + 1) / 2;
+  if (!red_sum(w, G, d + np, tot)) return;
+  const double n = static_cast<double>(N);
+  for (int q = threadIdx.x; q < np; q += blockDim.x) {
+    int ii = 0, jj = q;
+    while (jj > ii) { jj -= ii + 1; ++ii; }
+    const double v = (tot[d + q] - tot[ii] * tot[jj] / n) / (n - 1.0);
+    cov[ii * d + jj] = v;
+    cov[jj * d + ii] = v;
+  }
+  if (threadIdx.x < d) mean[threadIdx.x] = static_cast<double>(u[threadIdx.x]) + tot[threadIdx.x] / n;
+  if (threadIdx.x == 0) w->st.passes = 1;
+}
+
+// pass (d > 16): coordinate sums; the last workgroup writes the mean
+template <int DM>
+__global__ void __launch_bounds__(256)
+k_cl_sum(const float* __restrict__ u, long N, int d, CLWork* __restrict__ w) {
+  constexpr int QF = tile_quads<DM>();
+  __shared__ __align__(16) float xs[tile_floats<DM>()];
+  __shared__ double red[4][DM];
+  long lo, hi;
+  chunk_of(N, &lo, &hi);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, ds = d | 1;
+  double s[DM];
+#pragma unroll
+  for (int i = 0; i < DM; ++i) s[i] = 0.0;
+  stream_tiles<QF>(u, d, lo, hi, PutF{xs, d}, nullptr, [&](long, int nt, int) {
+    const int t = threadIdx.x;
+    if (t < nt)
+#pragma unroll
+      for (int i = 0; i < DM; ++i)
+        if (i < d) s[i] += static_cast<double>(xs[t * ds + i]);
+  });
+#pragma unroll
+  for (int i = 0; i < DM; ++i)
+    if (i < d) {
+      const double v = wave_sum(s[i]);
+      if (lane == 0) red[wv][i] = v;
+    }
+  __syncthreads();
+  const int i = threadIdx.x;
+  if (i < d) w->part[blockIdx.x][i] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
+}
+
+__global__ void __launch_bounds__(256)
+k_cl_red_mean(long N, int d, int G, double* __restrict__ mean, CLWork* __restrict__ w) {
+  __shared__ double tot[kMaxD];
+  if (!red_sum(w, G, d, tot)) return;
+  const int i = threadIdx.x;
+  if (i < d) mean[i] = tot[i] / static_cast<double>(N);
+  if (i == 0) w->st.passes = 1;
+}
+
+// pass (d > 16): centred outer products (lower triangle, row by row):
+// points staged in LDS, lanes own entries; workgroups of one wave, chunks as
+// above
 __global__ void __launch_bounds__(64)
 k_cl_cov(const float* __restrict__ u, long N, int d, const double* __restrict__ mean, CLWork* __restrict__ w) {
   __shared__ double xs[64][kMaxD + 1];
@@ -237,197 +482,182 @@ k_cl_cov(const float* __restrict__ u, long N, int d, const double* __restrict__ 
     if (lane + 64 * q < np) w->part[blockIdx.x][lane + 64 * q] = acc[q];
 }
 
-// one workgroup per block of 32 pairs
 __global__ void __launch_bounds__(256)
-k_cl_covred(long N, int d, int groups, double* __restrict__ cov, CLWork* __restrict__ w) {
-  __shared__ double red[256 * 33];
+k_cl_red_cov(long N, int d, int G, double* __restrict__ cov, CLWork* __restrict__ w) {
+  __shared__ double tot[kMaxD * (kMaxD + 1) / 2];
   const int np = d * (d + 1) / 2;
-  const int c0 = blockIdx.x * 32, nc = min(32, np - c0);
-  __shared__ double tot[32];
-  sum_partials(w, groups, c0, nc, red, tot);
-  const int q = threadIdx.x;
-  if (q < nc) {
-    int ii = 0, jj = c0 + q;
+  if (!red_sum(w, G, np, tot)) return;
+  for (int q = threadIdx.x; q < np; q += blockDim.x) {
+    int ii = 0, jj = q;
     while (jj > ii) { jj -= ii + 1; ++ii; }
     const double v = tot[q] / static_cast<double>(N - 1);
     cov[ii * d + jj] = v;
     cov[jj * d + ii] = v;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) w->st.passes += 1;
+  if (threadIdx.x == 0) w->st.passes += 1;
 }
 
 // pass: farthest point from ref (which = 0: the mean, 1: point ia), lowest index on ties
 template <int DM>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
 k_cl_far(const float* __restrict__ u, long N, int d, int which, const double* __restrict__ mean,
          CLWork* __restrict__ w) {
+  constexpr int QF = tile_quads<DM>();
+  __shared__ __align__(16) float xs[tile_floats<DM>()];
   __shared__ double ref[kMaxD];
+  __shared__ double sv[4];
+  __shared__ long si[4];
   long lo, hi;
+  assume_dm<DM>(d);
   chunk_of(N, &lo, &hi);
-  const int lane = threadIdx.x;
-  if (lane < d) ref[lane] = which == 0 ? mean[lane] : static_cast<double>(u[static_cast<long>(w->st.ia) * d + lane]);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, ds = d | 1;
+  if (threadIdx.x < d)
+    ref[threadIdx.x] = which == 0 ? mean[threadIdx.x]
+                                  : static_cast<double>(u[static_cast<long>(w->st.ia) * d + threadIdx.x]);
   __syncthreads();
   double bv = -1.0;
   long bi = 0x7fffffffffffffffL;
-  for (long k0 = lo + lane; k0 < hi; k0 += 4 * 64) {
-    float xv[4][DM];
+  stream_tiles<QF>(u, d, lo, hi, PutF{xs, d}, nullptr, [&](long k0, int nt, int) {
+    const int t = threadIdx.x;
+    if (t < nt) {
+      double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const long k = min(k0 + 64 * j, hi - 1);
-#pragma unroll
-      for (int i = 0; i < DM; ++i) xv[j][i] = i < d ? u[k * d + i] : 0.f;
+      for (int i = 0; i < DM; ++i)
+        if (i < d) {
+          const double q = static_cast<double>(xs[t * ds + i]) - ref[i];
+          s += q * q;
+        }
+      if (s > bv) { bv = s; bi = k0 + t; }
     }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const long k = k0 + 64 * j;
-      if (k >= hi) continue;
-      const double s = sqdist_pt<DM>(xv[j], ref, d);
-      if (s > bv) { bv = s; bi = k; }
-    }
-  }
+  });
   for (int o = 32; o > 0; o >>= 1) {
     const double ov = __shfl_xor(bv, o);
     const long oi = __shfl_xor(bi, o);
     if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
   }
-  if (lane == 0) {
+  if (lane == 0) { sv[wv] = bv; si[wv] = bi; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < 4; ++q)
+      if (sv[q] > bv || (sv[q] == bv && si[q] < bi)) { bv = sv[q]; bi = si[q]; }
     w->pv[blockIdx.x] = bv;
     w->pi[blockIdx.x] = bi;
   }
 }
 
+// reduction of the farthest-point partials; the last workgroup makes the
+// chosen point a start centre
 __global__ void __launch_bounds__(256)
-k_cl_farred(const float* __restrict__ u, int d, int groups, int which, CLWork* __restrict__ w) {
+k_cl_red_far(const float* __restrict__ u, int d, int G, int which, CLWork* __restrict__ w) {
   __shared__ long s_i;
-  __shared__ double sv[256];
-  __shared__ long si[256];
-  const int t = threadIdx.x;
-  double bv = -1.0;
-  long bi = 0x7fffffffffffffffL;
-  for (int g0 = t; g0 < groups; g0 += 8 * 256) {
-    double v[8];
-    long ix[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int g = min(g0 + 256 * j, groups - 1);
-      v[j] = w->pv[g];
-      ix[j] = w->pi[g];
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-      if (g0 + 256 * j < groups && (v[j] > bv || (v[j] == bv && ix[j] < bi))) { bv = v[j]; bi = ix[j]; }
-  }
-  sv[t] = bv;
-  si[t] = bi;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (t < off && (sv[t + off] > sv[t] || (sv[t + off] == sv[t] && si[t + off] < si[t]))) {
-      sv[t] = sv[t + off];
-      si[t] = si[t + off];
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-    s_i = si[0];
-    if (which == 0) w->st.ia = static_cast<int>(si[0]); else w->st.ib = static_cast<int>(si[0]);
+  double bv;
+  long bi;
+  if (!red_argmax(w, G, &bv, &bi)) return;
+  if (threadIdx.x == 0) {
+    s_i = bi;
+    if (which == 0) w->st.ia = static_cast<int>(bi); else w->st.ib = static_cast<int>(bi);
     w->st.passes += 1;
   }
   __syncthreads();
-  const int i = threadIdx.x;
-  if (i < d) {
-    const double v = static_cast<double>(u[s_i * d + i]);
-    if (which == 0) w->st.ca[i] = v; else w->st.cb[i] = v;
+  if (threadIdx.x < d) {
+    const double v = static_cast<double>(u[s_i * d + threadIdx.x]);
+    if (which == 0) w->st.ca[threadIdx.x] = v; else w->st.cb[threadIdx.x] = v;
   }
 }
 
 // Lloyd pass r: assign with the current centres (pass 0: the start pair),
 // note changes, and sum the coordinates of each side
 template <int DM>
-__global__ void __launch_bounds__(64)
-k_cl_lloyd(const float* __restrict__ u, long N, int d, int r, unsigned char* __restrict__ side,
-           CLWork* __restrict__ w) {
+__global__ void __launch_bounds__(256)
+k_cl_lloyd(const float* __restrict__ u, long N, int d, int r, unsigned char* side, CLWork* __restrict__ w) {
+  constexpr int QF = tile_quads<DM>();
+  __shared__ __align__(16) float xs[tile_floats<DM>()];
   __shared__ double ca[kMaxD], cb[kMaxD];
+  __shared__ double red[4][2 * DM + 2];
   if (w->st.done) return;
   long lo, hi;
+  assume_dm<DM>(d);
   chunk_of(N, &lo, &hi);
-  const int lane = threadIdx.x;
-  if (lane < d) { ca[lane] = w->st.ca[lane]; cb[lane] = w->st.cb[lane]; }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, ds = d | 1;
+  if (threadIdx.x < d) { ca[threadIdx.x] = w->st.ca[threadIdx.x]; cb[threadIdx.x] = w->st.cb[threadIdx.x]; }
   __syncthreads();
   double sa[DM], sb[DM];
 #pragma unroll
   for (int i = 0; i < DM; ++i) { sa[i] = 0.0; sb[i] = 0.0; }
   int n1 = 0, ch = 0;
-  for (long k0 = lo + lane; k0 < hi; k0 += 2 * 64) {
-    // two points' coordinates and previous sides loaded together
-    float xv[2][DM];
-    int prev[2];
+  stream_tiles<QF>(u, d, lo, hi, PutF{xs, d}, r > 0 ? side : nullptr, [&](long k0, int nt, int prev) {
+    const int t = threadIdx.x;
+    if (t < nt) {
+      double x[DM];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const long k = min(k0 + 64 * j, hi - 1);
-#pragma unroll
-      for (int i = 0; i < DM; ++i) xv[j][i] = i < d ? u[k * d + i] : 0.f;
-      prev[j] = r > 0 ? side[k] : 0;
-    }
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const long k = k0 + 64 * j;
-      if (k >= hi) continue;
-      const double da = sqdist_pt<DM>(xv[j], ca, d), db = sqdist_pt<DM>(xv[j], cb, d);
-      const int s = da <= db ? 0 : 1;
-      if (r > 0 && prev[j] != s) ch = 1;
-      side[k] = static_cast<unsigned char>(s);
-      n1 += s;
+      for (int i = 0; i < DM; ++i) x[i] = i < d ? static_cast<double>(xs[t * ds + i]) : 0.0;
+      double da = 0.0, db = 0.0;
 #pragma unroll
       for (int i = 0; i < DM; ++i)
         if (i < d) {
-          const double xi = static_cast<double>(xv[j][i]);
-          if (s) sb[i] += xi; else sa[i] += xi;
+          const double qa = x[i] - ca[i], qb = x[i] - cb[i];
+          da += qa * qa;
+          db += qb * qb;
+        }
+      const int sd = da <= db ? 0 : 1;
+      if (r > 0 && prev != sd) ch = 1;
+      side[k0 + t] = static_cast<unsigned char>(sd);
+      n1 += sd;
+      // each side's sum takes the coordinate or an exact zero
+#pragma unroll
+      for (int i = 0; i < DM; ++i)
+        if (i < d) {
+          sa[i] += sd ? 0.0 : x[i];
+          sb[i] += sd ? x[i] : 0.0;
         }
     }
-  }
-  double* out = w->part[blockIdx.x];
+  });
 #pragma unroll
   for (int i = 0; i < DM; ++i)
     if (i < d) {
       const double ta = wave_sum(sa[i]), tb = wave_sum(sb[i]);
-      if (lane == 0) { out[i] = ta; out[d + i] = tb; }
+      if (lane == 0) { red[wv][i] = ta; red[wv][d + i] = tb; }
     }
-  double fn = static_cast<double>(n1), fc = static_cast<double>(ch);
-  fn = wave_sum(fn);
-  fc = wave_sum(fc);
-  if (lane == 0) { out[2 * d] = fn; out[2 * d + 1] = fc; }
+  const double fn = wave_sum(static_cast<double>(n1)), fc = wave_sum(static_cast<double>(ch));
+  if (lane == 0) { red[wv][2 * d] = fn; red[wv][2 * d + 1] = fc; }
+  __syncthreads();
+  const int c = threadIdx.x;
+  if (c < 2 * d + 2) w->part[blockIdx.x][c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
 }
 
-// after Lloyd pass r: stop when nothing changed (r > 0) or after `iters`
-// updates; otherwise the centres become the side means (one more update)
+// reduction after Lloyd pass r; the last workgroup stops the split when
+// nothing changed (r > 0) or after `iters` updates, and otherwise makes the
+// side means the centres (one more update)
 __global__ void __launch_bounds__(256)
-k_cl_update(long N, int d, int groups, int r, int iters, double* __restrict__ centres, CLWork* __restrict__ w) {
-  __shared__ double red[256 * 33];
-  __shared__ int s_stop;
+k_cl_red_lloyd(long N, int d, int G, int r, int iters, double* __restrict__ centres, CLWork* __restrict__ w) {
+  __shared__ double tot[2 * kMaxD + 2];
   if (w->st.done) return;
-  const int i = threadIdx.x;
-  __shared__ double cnt[32], sa[32], sb[32];
-  sum_partials(w, groups, 2 * d, 2, red, cnt);   // side-1 count, changed flags
-  sum_partials(w, groups, 0, d, red, sa);
-  sum_partials(w, groups, d, d, red, sb);
-  const double n1 = cnt[0], n0 = static_cast<double>(N) - n1;
-  if (i == 0) {
-    s_stop = (r > 0 && cnt[1] == 0.0) || r == iters;
+  if (!red_sum(w, G, 2 * d + 2, tot)) return;
+  const int c = threadIdx.x;
+  const double n1v = tot[2 * d], n0v = static_cast<double>(N) - n1v;
+  const bool stop = (r > 0 && tot[2 * d + 1] == 0.0) || r == iters;
+  if (!stop && c < d) {
+    if (n0v > 0.0) w->st.ca[c] = tot[c] / n0v;
+    if (n1v > 0.0) w->st.cb[c] = tot[d + c] / n1v;
+  }
+  if (stop && c < d) { centres[c] = w->st.ca[c]; centres[kMaxD + c] = w->st.cb[c]; }
+  if (c == 0) {
     w->st.passes += 1;
-    w->st.n1 = static_cast<int>(n1);
-    w->st.n0 = static_cast<int>(n0);
+    w->st.n1 = static_cast<int>(n1v);
+    w->st.n0 = static_cast<int>(n0v);
+    w->st.iters_used = stop ? r : r + 1;
+    if (stop) w->st.done = 1;
   }
-  __syncthreads();
-  if (!s_stop && i < d) {
-    if (n0 > 0.0) w->st.ca[i] = sa[i] / n0;
-    if (n1 > 0.0) w->st.cb[i] = sb[i] / n1;
-  }
-  __syncthreads();
-  if (s_stop) {
-    if (i < d) { centres[i] = w->st.ca[i]; centres[kMaxD + i] = w->st.cb[i]; }
-    if (i == 0) { w->st.done = 1; w->st.iters_used = r; }
-  } else if (i == 0) {
-    w->st.iters_used = r + 1;
+}
+
+// start of a node: the reduction ticket and the stop flag cleared
+__global__ void k_cl_init(CLWork* __restrict__ w) {
+  const int t = threadIdx.x;
+  if (t == 0) {
+    w->tt = 0u;
+    w->st.done = 0;
+    w->st.passes = 0;
+    w->st.iters_used = 0;
   }
 }
 
@@ -439,35 +669,47 @@ hipError_t launch_cluster_split(const float* u, long N, int d, int iters, double
                                 double* centres, unsigned char* side, void* work, int* passes, hipStream_t s) {
   if (N < 2 || d < 1 || d > kMaxD || iters < 0) return hipErrorInvalidValue;
   CLWork* w = static_cast<CLWork*>(work);
-  const int G = static_cast<int>(std::min<long>(kCLGroups, std::max<long>(1, (N + 255) / 256)));
-  const int DM = d <= 2 ? 2 : d <= 4 ? 4 : d <= 8 ? 8 : d <= 16 ? 16 : 32;
-#define NS_CL_DM(K, ...)                                                                   \
-  switch (DM) {                                                                              \
-    case 2: hipLaunchKernelGGL(K<2>, dim3(G), dim3(64), 0, s, __VA_ARGS__); break;           \
-    case 4: hipLaunchKernelGGL(K<4>, dim3(G), dim3(64), 0, s, __VA_ARGS__); break;           \
-    case 8: hipLaunchKernelGGL(K<8>, dim3(G), dim3(64), 0, s, __VA_ARGS__); break;           \
-    case 16: hipLaunchKernelGGL(K<16>, dim3(G), dim3(64), 0, s, __VA_ARGS__); break;         \
-    default: hipLaunchKernelGGL(K<32>, dim3(G), dim3(64), 0, s, __VA_ARGS__); break;         \
+  const int G = static_cast<int>(std::min<long>(kCLGroups, std::max<long>(1, (N + kCLTile - 1) / kCLTile)));
+  // the dimension rounded up to even (24 and 32 beyond 16): register arrays of that length
+  const int DM = d <= 16 ? (d + 1) & ~1 : d <= 24 ? 24 : 32;
+#define NS_CL_CASE(K, M, ...) \
+  case M: hipLaunchKernelGGL(K<M>, dim3(G), dim3(256), 0, s, __VA_ARGS__); break;
+#define NS_CL_DM(K, ...)                                                                           \
+  switch (DM) {                                                                                      \
+    NS_CL_CASE(K, 2, __VA_ARGS__) NS_CL_CASE(K, 4, __VA_ARGS__) NS_CL_CASE(K, 6, __VA_ARGS__)       \
+    NS_CL_CASE(K, 8, __VA_ARGS__) NS_CL_CASE(K, 10, __VA_ARGS__) NS_CL_CASE(K, 12, __VA_ARGS__)     \
+    NS_CL_CASE(K, 14, __VA_ARGS__) NS_CL_CASE(K, 16, __VA_ARGS__) NS_CL_CASE(K, 24, __VA_ARGS__)    \
+    default: hipLaunchKernelGGL(K<32>, dim3(G), dim3(256), 0, s, __VA_ARGS__); break;                \
   }
-  NS_CL_DM(k_cl_sum, u, N, d, w)
-  hipLaunchKernelGGL(k_cl_mean, dim3(1), dim3(256), 0, s, N, d, G, mean, w);
-  // the register triangle for d <= 12 (78 accumulators at most), LDS beyond
-  if (d <= 2) hipLaunchKernelGGL(k_cl_cov_reg<2>, dim3(G), dim3(64), 0, s, u, N, d, mean, w);
-  else if (d <= 4) hipLaunchKernelGGL(k_cl_cov_reg<4>, dim3(G), dim3(64), 0, s, u, N, d, mean, w);
-  else if (d <= 8) hipLaunchKernelGGL(k_cl_cov_reg<8>, dim3(G), dim3(64), 0, s, u, N, d, mean, w);
-  else if (d <= 12) hipLaunchKernelGGL(k_cl_cov_reg<12>, dim3(G), dim3(64), 0, s, u, N, d, mean, w);
-  else hipLaunchKernelGGL(k_cl_cov, dim3(G), dim3(64), 0, s, u, N, d, mean, w);
-  hipLaunchKernelGGL(k_cl_covred, dim3((d * (d + 1) / 2 + 31) / 32), dim3(256), 0, s, N, d, G, cov, w);
+#define NS_CL_DM16(K, ...)                                                                         \
+  switch (DM) {                                                                                      \
+    NS_CL_CASE(K, 2, __VA_ARGS__) NS_CL_CASE(K, 4, __VA_ARGS__) NS_CL_CASE(K, 6, __VA_ARGS__)       \
+    NS_CL_CASE(K, 8, __VA_ARGS__) NS_CL_CASE(K, 10, __VA_ARGS__) NS_CL_CASE(K, 12, __VA_ARGS__)     \
+    NS_CL_CASE(K, 14, __VA_ARGS__) default: hipLaunchKernelGGL(K<16>, dim3(G), dim3(256), 0, s, __VA_ARGS__); break; \
+  }
+  const int R = (G + kCLFan - 1) / kCLFan;   // reduction workgroups
+  hipLaunchKernelGGL(k_cl_init, dim3(1), dim3(64), 0, s, w);
+  if (d <= 16) {
+    NS_CL_DM16(k_cl_stats, u, N, d, w)
+    hipLaunchKernelGGL(k_cl_red_stats, dim3(R), dim3(256), 0, s, u, N, d, G, mean, cov, w);
+  } else {
+    hipLaunchKernelGGL(k_cl_sum<32>, dim3(G), dim3(256), 0, s, u, N, d, w);
+    hipLaunchKernelGGL(k_cl_red_mean, dim3(R), dim3(256), 0, s, N, d, G, mean, w);
+    hipLaunchKernelGGL(k_cl_cov, dim3(G), dim3(64), 0, s, u, N, d, mean, w);
+    hipLaunchKernelGGL(k_cl_red_cov, dim3(R), dim3(256), 0, s, N, d, G, cov, w);
+  }
   for (int which = 0; which < 2; ++which) {
     NS_CL_DM(k_cl_far, u, N, d, which, mean, w)
-    hipLaunchKernelGGL(k_cl_farred, dim3(1), dim3(256), 0, s, u, d, G, which, w);
+    hipLaunchKernelGGL(k_cl_red_far, dim3(R), dim3(256), 0, s, u, d, G, which, w);
   }
   for (int r = 0; r <= iters; ++r) {
     NS_CL_DM(k_cl_lloyd, u, N, d, r, side, w)
-    hipLaunchKernelGGL(k_cl_update, dim3(1), dim3(256), 0, s, N, d, G, r, iters, centres, w);
+    hipLaunchKernelGGL(k_cl_red_lloyd, dim3(R), dim3(256), 0, s, N, d, G, r, iters, centres, w);
   }
   hipLaunchKernelGGL(k_cl_finish, dim3(1), dim3(64), 0, s, passes, w);
 #undef NS_CL_DM
+#undef NS_CL_DM16
+#undef NS_CL_CASE
   return hipGetLastError();
 }
 
