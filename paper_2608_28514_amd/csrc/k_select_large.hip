@@ -84,26 +84,26 @@ __global__ void k_rsel_init(long N, int m, SelWork* w) {
 }
 
 // One digit, pass 1 of 2: each workgroup counts the digit of the entries in
-// the resolved prefix (LDS histogram) and writes its partial histogram.  Each
-// thread loads eight pairs of likelihoods (16-byte loads) before counting them;
-// lanes of a wave with the same digit are merged into one LDS atomic for up to
-// four distinct digits (likelihoods often share their leading bits), the rest
-// add one by one.
-__global__ void __launch_bounds__(256)
+// the resolved prefix and writes its partial histogram.  Each thread loads
+// eight pairs of likelihoods (16-byte loads) before counting them.  The LDS
+// histogram is kept in four copies, lane l adding to copy l & 3: lanes of a
+// wave that share a digit (likelihoods often share their leading bits) then
+// meet at most 16 to an address; the copies are summed at the end.
+// Workgroups of 1024 threads (16 waves).
+__global__ void __launch_bounds__(1024)
 k_rsel_hist(const double* __restrict__ logL, long N, int level, SelWork* __restrict__ w) {
-  __shared__ unsigned int lh[kRBins];
+  __shared__ unsigned int lh[4][kRBins];
   if (w->st.done) return;
   const SelState s = w->st;
   const Level L = sel_level(level);
   const unsigned int mask = (1u << L.width) - 1u;
-  const int lane = threadIdx.x & 63;
-  for (int b = threadIdx.x; b < kRBins; b += blockDim.x) lh[b] = 0u;
+  unsigned int* my = lh[threadIdx.x & 3];
+  for (int b = threadIdx.x; b < 4 * kRBins; b += blockDim.x) (&lh[0][0])[b] = 0u;
   __syncthreads();
   const long npair = (N + 1) >> 1;
   const long stride = static_cast<long>(gridDim.x) * blockDim.x;
-  const long span = (npair + stride - 1) / stride * stride;   // whole waves run every iteration
   const double2* lp = reinterpret_cast<const double2*>(logL);
-  for (long p0 = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x; p0 < span; p0 += 8 * stride) {
+  for (long p0 = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x; p0 < npair; p0 += 8 * stride) {
     double2 v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -120,32 +120,20 @@ k_rsel_hist(const double* __restrict__ logL, long N, int level, SelWork* __restr
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const long i = 2 * (p0 + q * stride) + h;
-        bool pend = false;
-        unsigned int dg = 0u;
         if (p0 + q * stride < npair && i < N) {
           const unsigned long long key = order_key(h ? v[q].y : v[q].x);
           if (sel_rel(key, static_cast<unsigned int>(i), s) == 0) {
-            pend = true;
-            dg = L.slot_phase ? ((static_cast<unsigned int>(i) >> L.shift) & mask)
-                              : static_cast<unsigned int>((key >> L.shift) & mask);
+            const unsigned int dg = L.slot_phase ? ((static_cast<unsigned int>(i) >> L.shift) & mask)
+                                                 : static_cast<unsigned int>((key >> L.shift) & mask);
+            atomicAdd(&my[dg], 1u);
           }
         }
-        uint64_t act = __ballot(pend);
-        for (int r = 0; r < 4 && act; ++r) {
-          const int lead = __builtin_ctzll(act);
-          const unsigned int dl = __shfl(dg, lead);
-          const uint64_t same = __ballot(pend && dg == dl);
-          if (lane == lead) atomicAdd(&lh[dl], static_cast<unsigned int>(__popcll(same)));
-          if (pend && dg == dl) pend = false;
-          act = __ballot(pend);
-        }
-        if (pend) atomicAdd(&lh[dg], 1u);
       }
     }
   }
   __syncthreads();
   unsigned int* out = w->part[blockIdx.x];
-  for (int b = threadIdx.x; b < kRBins; b += blockDim.x) out[b] = lh[b];
+  for (int b = threadIdx.x; b < kRBins; b += blockDim.x) out[b] = ((lh[0][b] + lh[1][b]) + lh[2][b]) + lh[3][b];
 }
 
 // One digit, pass 2 of 2: the partial histograms summed per bin (in
@@ -160,12 +148,12 @@ k_rsel_reduce(int groups, int m, int level, SelWork* __restrict__ w) {
   // every fourth partial, then their four sums are added in wave order
   const int b = blockIdx.x * 64 + (threadIdx.x & 63), qq = threadIdx.x >> 6;
   unsigned int t = 0u;
-  for (int g0 = qq; g0 < groups; g0 += 4 * 8) {
-    unsigned int v[8];
+  for (int g0 = qq; g0 < groups; g0 += 4 * 32) {
+    unsigned int v[32];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = w->part[min(g0 + 4 * j, groups - 1)][b];
+    for (int j = 0; j < 32; ++j) v[j] = w->part[min(g0 + 4 * j, groups - 1)][b];
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
+    for (int j = 0; j < 32; ++j)
       if (g0 + 4 * j < groups) t += v[j];
   }
   qs[threadIdx.x] = t;
@@ -179,22 +167,29 @@ k_rsel_reduce(int groups, int m, int level, SelWork* __restrict__ w) {
   __threadfence();
   const SelState s = w->st;
   const Level L = sel_level(level);
-  // last workgroup: inclusive scan of the histogram (16 bins per thread, then
-  // the 256 thread totals), first bin where below + cum >= m
-  __shared__ unsigned int tsum[256];
+  // last workgroup: inclusive scan of the histogram (16 bins per thread, the
+  // thread totals scanned within each wave, then the four wave totals), first
+  // bin where below + cum >= m
+  __shared__ unsigned int wsum[4];
   __shared__ int s_bin, s_before;
-  const int tt = threadIdx.x;
+  const int tt = threadIdx.x, ln = tt & 63, wq = tt >> 6;
   unsigned int hb[16], run = 0u;
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     hb[q] = atomicAdd(&w->hist[16 * tt + q], 0u);
     run += hb[q];
   }
-  tsum[tt] = run;
+  unsigned int inc = run;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned int y = __shfl_up(inc, o);
+    if (ln >= o) inc += y;
+  }
+  if (ln == 63) wsum[wq] = inc;
   if (tt == 0) s_bin = -1;
   __syncthreads();
-  unsigned int before = 0u;
-  for (int q = 0; q < tt; ++q) before += tsum[q];
+  unsigned int before = inc - run;
+  for (int q = 0; q < wq; ++q) before += wsum[q];
   const long need = static_cast<long>(m) - s.below;
   unsigned int c = before;
 #pragma unroll
@@ -299,9 +294,9 @@ hipError_t launch_select_large(const double* logL, long N, int m, int* out, void
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long npair = (N + 1) / 2;
-  const int grid = static_cast<int>(std::min<long>(kSelGroups, std::max<long>(1, (npair + 1023) / 1024)));
+  const int grid = static_cast<int>(std::min<long>(kSelGroups, std::max<long>(1, (npair + 2047) / 2048)));
   for (int l = 0; l < kSelLevels; ++l) {
-    hipLaunchKernelGGL(k_rsel_hist, dim3(grid), dim3(256), 0, s, logL, N, l, w);
+    hipLaunchKernelGGL(k_rsel_hist, dim3(grid), dim3(1024), 0, s, logL, N, l, w);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rsel_reduce, dim3(kRBins / 64), dim3(256), 0, s, grid, m, l, w);
