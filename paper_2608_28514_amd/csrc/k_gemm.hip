@@ -25,6 +25,19 @@ namespace ns {
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 
+// rows per call from which the hidden and output layers use 32 x 64 blocks
+constexpr int kFragWideRows = 4096;
+
+// Workgroups are dealt to the eight XCDs round-robin (workgroup b on XCD
+// b % 8), each XCD with its own L2.  The block a workgroup computes is taken
+// from a renumbering that gives every XCD a contiguous range of blocks, so the
+// column blocks of one row block (which share its activation fragments) run
+// on the same XCD; the last G % 8 workgroups keep their own number.
+__device__ __forceinline__ int xcd_block(int b, int G) {
+  const int q = G >> 3;
+  return b < 8 * q ? (b & 7) * q + (b >> 3) : b;
+}
+
 constexpr int kTM = 64, kTN = 64, kTK = 32;
 constexpr int kLdsK = kTK + 4;  // padded row stride (floats)
 
@@ -335,7 +348,8 @@ k_dense_frag(int M, int N, int K, const __bf16* __restrict__ A, long aplane, con
   if (gate && *gate == 0) return;
   if (dM) M = min(M, *dM);
   const int nbc = N >> 5;
-  const int rb = blockIdx.x / nbc, cb = blockIdx.x - rb * nbc;
+  const int bx = xcd_block(blockIdx.x, gridDim.x);
+  const int rb = bx / nbc, cb = bx - rb * nbc;
   if (rb * 16 >= M) return;
   const int lane = threadIdx.x;
   const int S = K >> 5;
@@ -412,6 +426,121 @@ k_dense_frag(int M, int N, int K, const __bf16* __restrict__ A, long aplane, con
     const int rr = lane & 15, g = lane >> 4;
     for (int p = 0; p < 3; ++p)
       *reinterpret_cast<bf16x8*>(out + p * cplane + o) = *reinterpret_cast<const bf16x8*>(&tile[p][rr][8 * g]);
+  }
+}
+
+// The same layer for many rows: one wave per 32 x 64 output block (two row
+// blocks of 16, four column tiles of 16), single-term weights (WS = 1).  Per
+// K step of 32 the wave loads six activation fragments and four weight
+// fragments (10 KB) for 24 MFMAs, twice the work per loaded byte of the 16 x 32
+// block; every 16 x 16 tile accumulates its products in the same order as
+// k_dense_frag, so the outputs are identical.  rows16: row blocks of 16 that
+// exist (the second row block of the last wave may not).
+template <bool CHI2>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+k_dense_frag_w(int M, int N, int K, const __bf16* __restrict__ A, long aplane, const __bf16* __restrict__ Wf,
+               const float* __restrict__ bias, int act, __bf16* __restrict__ out, long cplane,
+               const double* __restrict__ data, const double* __restrict__ isig, double* __restrict__ part,
+               long pstride, const int* __restrict__ gate, const int* __restrict__ dM) {
+  if (gate && *gate == 0) return;
+  if (dM) M = min(M, *dM);
+  const int nbw = N >> 6;
+  const int bx = xcd_block(blockIdx.x, gridDim.x);
+  const int rw = bx / nbw, cw = bx - rw * nbw;
+  if (rw * 32 >= M) return;
+  const bool two = rw * 32 + 16 < M;   // second row block present
+  const int lane = threadIdx.x;
+  const int S = K >> 5;
+  const __bf16* ap0 = A + static_cast<long>(2 * rw) * S * 512 + lane * 8;
+  const __bf16* ap1 = ap0 + static_cast<long>(S) * 512;
+  const __bf16* bp = Wf + static_cast<long>(4 * cw) * S * 512 + lane * 8;
+  const long bstep = static_cast<long>(S) * 512;
+  f32x4 acc[2][4];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[r][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  bf16x8 a0[2][3], a1[2][3], a2[2][3], b0[4], b1[4], b2[4];
+  auto load = [&](int s, bf16x8 (&a)[2][3], bf16x8 (&b)[4]) {
+    const long o = static_cast<long>(s) * 512;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) a[0][p] = *reinterpret_cast<const bf16x8*>(ap0 + p * aplane + o);
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+      a[1][p] = two ? *reinterpret_cast<const bf16x8*>(ap1 + p * aplane + o) : a[0][p];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const bf16x8*>(bp + j * bstep + o);
+  };
+  auto step = [&](const bf16x8 (&a)[2][3], const bf16x8 (&b)[4]) {
+    // activation terms by decreasing pa (the weight has one term)
+#pragma unroll
+    for (int pa = 2; pa >= 0; --pa)
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r][pa], b[j], acc[r][j], 0, 0, 0);
+  };
+  // two steps of loads in flight
+  load(0, a0, b0);
+  if (S > 1) load(1, a1, b1);
+  for (int s = 0; s < S; s += 3) {
+    if (s + 2 < S) load(s + 2, a2, b2);
+    step(a0, b0);
+    if (s + 1 >= S) break;
+    if (s + 3 < S) load(s + 3, a0, b0);
+    step(a1, b1);
+    if (s + 2 >= S) break;
+    if (s + 4 < S) load(s + 4, a1, b1);
+    step(a2, b2);
+  }
+  const int nl = lane & 15;
+  if (CHI2) {
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) {
+      const int n0 = cw * 64 + c2 * 32 + nl;
+      const float bz0 = bias ? bias[n0] : 0.f, bz1 = bias ? bias[n0 + 16] : 0.f;
+      const double d0 = data[n0], d1 = data[n0 + 16], s0 = isig[n0], s1 = isig[n0 + 16];
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+        for (int i = 0; i < 4; ++i) {
+          const double e0 = (static_cast<double>(acc[r][2 * c2][i] + bz0) - d0) * s0;
+          const double e1 = (static_cast<double>(acc[r][2 * c2 + 1][i] + bz1) - d1) * s1;
+          double t = e0 * e0 + e1 * e1;
+          for (int o = 8; o > 0; o >>= 1) t += __shfl_xor(t, o);
+          const int row = (2 * rw + r) * 16 + 4 * (lane >> 4) + i;
+          if (nl == 0 && row < M) part[static_cast<long>(2 * cw + c2) * pstride + row] = t;
+        }
+    }
+  } else {
+    __shared__ __attribute__((aligned(16))) __bf16 tile[3][16][32 + 8];
+    const int nbc = N >> 5;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (r == 1 && !two) break;
+#pragma unroll
+      for (int c2 = 0; c2 < 2; ++c2) {
+        const int n0 = cw * 64 + c2 * 32 + nl;
+        const float bz0 = bias ? bias[n0] : 0.f, bz1 = bias ? bias[n0 + 16] : 0.f;
+        for (int i = 0; i < 4; ++i) {
+          const int rr = 4 * (lane >> 4) + i;
+          for (int t = 0; t < 2; ++t) {
+            const float x = act_fwd(act, acc[r][2 * c2 + t][i] + (t ? bz1 : bz0));
+            const __bf16 h = to_bf16(x);
+            const float r1 = x - from_bf16(h);
+            const __bf16 md = to_bf16(r1);
+            tile[0][rr][t * 16 + nl] = h;
+            tile[1][rr][t * 16 + nl] = md;
+            tile[2][rr][t * 16 + nl] = to_bf16(r1 - from_bf16(md));
+          }
+        }
+        __syncthreads();
+        const long o = (static_cast<long>(2 * rw + r) * nbc + 2 * cw + c2) * 512 + lane * 8;
+        const int rr = lane & 15, g = lane >> 4;
+        for (int p = 0; p < 3; ++p)
+          *reinterpret_cast<bf16x8*>(out + p * cplane + o) = *reinterpret_cast<const bf16x8*>(&tile[p][rr][8 * g]);
+        __syncthreads();
+      }
+    }
   }
 }
 
@@ -499,6 +628,15 @@ hipError_t emu_forward_logL(const NetDev& net, int M, const __bf16* Xf, long xpl
       hipLaunchKernelGGL((k_dense_frag<false, 3>), grid, dim3(64), 0, s, M, N, K, in, inplane, net.Wf[0],
                          static_cast<long>(N) * 32, net.b[0], net.act, out, plane, nullptr, nullptr, nullptr, 0L,
                          gate, dM);
+    } else if (M >= kFragWideRows && N % 64 == 0) {
+      // many rows: 32 x 64 blocks per wave (the same sums, more reuse per load)
+      const dim3 gw(static_cast<unsigned>(((M + 31) / 32) * (N / 64)));
+      if (l < L - 1)
+        hipLaunchKernelGGL((k_dense_frag_w<false>), gw, dim3(64), 0, s, M, N, K, in, inplane, net.Wf[l], net.b[l],
+                           net.act, out, plane, nullptr, nullptr, nullptr, 0L, gate, dM);
+      else
+        hipLaunchKernelGGL((k_dense_frag_w<true>), gw, dim3(64), 0, s, M, N, K, in, inplane, net.Wf[l], net.b[l],
+                           kActNone, nullptr, 0L, data, isig, part, static_cast<long>(M), gate, dM);
     } else if (l < L - 1) {
       hipLaunchKernelGGL((k_dense_frag<false, 1>), grid, dim3(64), 0, s, M, N, K, in, inplane, net.Wf[l], 0L,
                          net.b[l], net.act, out, plane, nullptr, nullptr, nullptr, 0L, gate, dM);

@@ -86,19 +86,21 @@ __global__ void k_rsel_init(long N, int m, SelWork* w) {
 // One digit, pass 1 of 2: each workgroup counts the digit of the entries in
 // the resolved prefix and writes its partial histogram.  Each thread loads
 // eight pairs of likelihoods (16-byte loads) before counting them.  The LDS
-// histogram is kept in four copies, lane l adding to copy l & 3: lanes of a
-// wave that share a digit (likelihoods often share their leading bits) then
-// meet at most 16 to an address; the copies are summed at the end.
+// histogram is kept in four interleaved copies (bin b, copy c at 4 b + c, so
+// the copies of a bin sit in four banks), lane l adding to copy l & 3: lanes
+// of a wave that share a digit (likelihoods often share their leading bits)
+// then meet at most 16 to an address; the copies are summed at the end.
 // Workgroups of 1024 threads (16 waves).
 __global__ void __launch_bounds__(1024)
 k_rsel_hist(const double* __restrict__ logL, long N, int level, SelWork* __restrict__ w) {
-  __shared__ unsigned int lh[4][kRBins];
+  __shared__ uint4 lh4[kRBins];
+  unsigned int* lh = reinterpret_cast<unsigned int*>(lh4);
   if (w->st.done) return;
   const SelState s = w->st;
   const Level L = sel_level(level);
   const unsigned int mask = (1u << L.width) - 1u;
-  unsigned int* my = lh[threadIdx.x & 3];
-  for (int b = threadIdx.x; b < 4 * kRBins; b += blockDim.x) (&lh[0][0])[b] = 0u;
+  const unsigned int cp = threadIdx.x & 3;
+  for (int b = threadIdx.x; b < kRBins; b += blockDim.x) lh4[b] = make_uint4(0u, 0u, 0u, 0u);
   __syncthreads();
   const long npair = (N + 1) >> 1;
   const long stride = static_cast<long>(gridDim.x) * blockDim.x;
@@ -125,7 +127,7 @@ k_rsel_hist(const double* __restrict__ logL, long N, int level, SelWork* __restr
           if (sel_rel(key, static_cast<unsigned int>(i), s) == 0) {
             const unsigned int dg = L.slot_phase ? ((static_cast<unsigned int>(i) >> L.shift) & mask)
                                                  : static_cast<unsigned int>((key >> L.shift) & mask);
-            atomicAdd(&my[dg], 1u);
+            atomicAdd(&lh[4 * dg + cp], 1u);
           }
         }
       }
@@ -133,7 +135,10 @@ k_rsel_hist(const double* __restrict__ logL, long N, int level, SelWork* __restr
   }
   __syncthreads();
   unsigned int* out = w->part[blockIdx.x];
-  for (int b = threadIdx.x; b < kRBins; b += blockDim.x) out[b] = ((lh[0][b] + lh[1][b]) + lh[2][b]) + lh[3][b];
+  for (int b = threadIdx.x; b < kRBins; b += blockDim.x) {
+    const uint4 c = lh4[b];
+    out[b] = ((c.x + c.y) + c.z) + c.w;
+  }
 }
 
 // One digit, pass 2 of 2: the partial histograms summed per bin (in
@@ -145,7 +150,9 @@ k_rsel_reduce(int groups, int m, int level, SelWork* __restrict__ w) {
   __shared__ unsigned int qs[256];
   if (w->st.done) return;
   // 64 bins per workgroup (gridDim.x * 64 == kRBins); the four waves take
-  // every fourth partial, then their four sums are added in wave order
+  // every fourth partial (32 loads in flight), then their four sums are added
+  // in wave order.  (Fewer workgroups: each one's agent-scope fence below
+  // writes back the L2.)
   const int b = blockIdx.x * 64 + (threadIdx.x & 63), qq = threadIdx.x >> 6;
   unsigned int t = 0u;
   for (int g0 = qq; g0 < groups; g0 += 4 * 32) {

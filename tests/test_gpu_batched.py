@@ -327,3 +327,27 @@ def test_direct_rounds_equal_compacted_rounds():
     assert np.array_equal(da["u"], db["u"])
     for k in ("evals", "oob", "stepout_caps", "shrink_caps", "steps", "dead"):
         assert sa[k] == sb[k], k
+
+
+@pytest.mark.parametrize("M,widths", [(4096, (27, 128, 64, 128)), (6001, (27, 64, 128, 64))])
+def test_wide_blocks_equal_narrow_blocks(M, widths):
+    """Calls of 4096 rows or more run the hidden and output layers on 32 x 64
+    blocks per wave; each output tile sums its products in the same order, so
+    the likelihoods equal those of the same rows in calls below 4096 rows,
+    bit for bit (ragged row counts: a last wave with one row block)."""
+    spec = W.emulator(seed=7, widths=widths, noise_frac=0.05)
+    rng = np.random.default_rng(M)
+    u = rng.uniform(size=(M, widths[0]))
+    s = native.Sampler(spec, 64, prec="bf16x3", state="f32", seed=0, tree_depth=1)
+    d_u = torch.tensor(u, device=DEV)
+    wide = torch.zeros(M, dtype=torch.float64, device=DEV)
+    native.ns_loglike_batch(s.ctx, d_u, wide)
+    cut = 2039
+    narrow = torch.zeros(M, dtype=torch.float64, device=DEV)
+    for a in range(0, M, cut):
+        native.ns_loglike_batch(s.ctx, d_u[a:a + cut].contiguous(), narrow[a:a + cut])
+    native.ns_sync(s.ctx)
+    s.close()
+    got, ref = wide.cpu().numpy(), narrow.cpu().numpy()
+    assert np.all(np.isfinite(got))
+    assert np.array_equal(got, ref)

@@ -67,3 +67,57 @@ def test_cluster_split_rejects_bad_arguments():
         u = torch.zeros(shape, dtype=torch.float32, device=DEV)
         with pytest.raises(native.NsError):
             native.ns_cluster_split(u, 20, mean, cov, cen, side, work)
+
+
+@pytest.mark.parametrize("N,d", [(3001, 1), (5000, 7), (20000, 16), (20000, 17), (9000, 32)])
+def test_cluster_split_every_width(N, d):
+    """Every register width of the tiled passes (even and odd d, the moments
+    pass up to d = 16, the centred pair of passes beyond)."""
+    rng = np.random.default_rng(N + 31 * d)
+    u = _points("two", N, d, rng)
+    u64 = u.astype(np.float64)
+    mean, cov, cen, side, passes = _gpu(u)
+    assert np.all(np.abs(mean - u64.mean(axis=0)) <= 1e-12 * np.maximum(1.0, np.abs(mean)))
+    ref = np.atleast_2d(np.cov(u64, rowvar=False, ddof=1))
+    assert np.max(np.abs(cov - ref)) <= 1e-10 * max(1e-300, np.max(np.abs(ref)))
+    ca, cb, oside = oracle.two_means(u64, 20)
+    assert np.array_equal(side, oside)
+    assert np.all(np.abs(cen[0] - ca) <= 1e-12) and np.all(np.abs(cen[1] - cb) <= 1e-12)
+
+
+def test_cluster_split_unaligned_points():
+    """Points that start 4 bytes past a 16-byte boundary take the scalar
+    tile loads; the results match the aligned call."""
+    N, d = 10007, 6
+    rng = np.random.default_rng(5)
+    u = _points("two", N, d, rng)
+    base = torch.zeros(N * d + 1, dtype=torch.float32, device=DEV)
+    base[1:] = torch.tensor(u.reshape(-1), device=DEV)
+    du = base[1:].view(N, d)
+    assert du.data_ptr() % 16 == 4
+    work = torch.empty(native.ns_cluster_split_work_bytes(), dtype=torch.uint8, device=DEV)
+    mean = torch.zeros(d, dtype=torch.float64, device=DEV)
+    cov = torch.zeros((d, d), dtype=torch.float64, device=DEV)
+    cen = torch.zeros((2, 32), dtype=torch.float64, device=DEV)
+    side = torch.zeros(N, dtype=torch.uint8, device=DEV)
+    native.ns_cluster_split(du, 20, mean, cov, cen, side, work)
+    torch.cuda.synchronize()
+    m2, c2, e2, s2, _ = _gpu(u)
+    assert np.array_equal(mean.cpu().numpy(), m2) and np.array_equal(cov.cpu().numpy(), c2)
+    assert np.array_equal(cen.cpu().numpy()[:, :d], e2)
+    assert np.array_equal(side.cpu().numpy().astype(np.int32), s2)
+
+
+@pytest.mark.parametrize("iters", [0, 1, 3])
+def test_cluster_split_iteration_cap(iters):
+    """The Lloyd cap: after `iters` updates the split stops with the centres
+    of the last update, as the oracle's loop does."""
+    N, d = 30000, 4
+    rng = np.random.default_rng(iters)
+    u = _points("one", N, d, rng)
+    u64 = u.astype(np.float64)
+    mean, cov, cen, side, passes = _gpu(u, iters=iters)
+    ca, cb, oside = oracle.two_means(u64, iters)
+    assert np.array_equal(side, oside)
+    assert np.all(np.abs(cen[0] - ca) <= 1e-12) and np.all(np.abs(cen[1] - cb) <= 1e-12)
+    assert passes <= 3 + iters + 1
