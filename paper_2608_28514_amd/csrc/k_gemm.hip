@@ -26,7 +26,10 @@ typedef __attribute__((ext_vector_type(4))) float f32x4;
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 
 // rows per call from which the hidden and output layers use 32 x 64 blocks
+// per wave; workgroup tiles (64 x 128 for hidden layers, 128 x 128 for the
+// output layer) once a layer has this many of them (one per CU)
 constexpr int kFragWideRows = 4096;
+constexpr int kFragTileMin = 256;
 
 // Workgroups are dealt to the eight XCDs round-robin (workgroup b on XCD
 // b % 8), each XCD with its own L2.  The block a workgroup computes is taken
@@ -544,6 +547,158 @@ k_dense_frag_w(int M, int N, int K, const __bf16* __restrict__ A, long aplane, c
   }
 }
 
+// The same layer for many rows on (64 RW) x 128 output tiles per workgroup
+// (four waves; wave w: row blocks RW w .. RW w + RW - 1 of the tile, all eight
+// column tiles), single-term weights.  Per K step of 32 the workgroup copies
+// its 12 RW activation fragments and 8 weight fragments into one of two LDS
+// buffers (one 16-byte load per thread and fragment row of the copy, issued
+// two steps ahead) while the waves run 24 RW MFMAs each out of the other;
+// every 16 x 16 tile sums its products in the same order as k_dense_frag
+// (identical outputs).
+template <int RW>
+constexpr int tile_frags() { return 12 * RW + 8; }
+
+template <bool CHI2, int RW>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_dense_frag_t(int M, int N, int K, const __bf16* __restrict__ A, long aplane, const __bf16* __restrict__ Wf,
+               const float* __restrict__ bias, int act, __bf16* __restrict__ out, long cplane,
+               const double* __restrict__ data, const double* __restrict__ isig, double* __restrict__ part,
+               long pstride, const int* __restrict__ gate, const int* __restrict__ dM) {
+  constexpr int F = tile_frags<RW>(), NA = 12 * RW, Q = F / 4;   // fragments per step; 16-byte loads per thread
+  constexpr int TR = 4 * RW;                                      // row blocks per tile
+  __shared__ __attribute__((aligned(16))) bf16x8 lds[2][F * 64];
+  if (gate && *gate == 0) return;
+  if (dM) M = min(M, *dM);
+  const int nbt = N >> 7;
+  const int bx = xcd_block(blockIdx.x, gridDim.x);
+  const int rt = bx / nbt, ct = bx - rt * nbt;
+  if (rt * 16 * TR >= M) return;
+  const int nrb = (M + 15) >> 4;                 // row blocks that exist
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int S = K >> 5;
+  // copy assignment: chunk c = tid + 256 i (i < Q) of the 64 F 16-byte chunks
+  // of a step; fragment f = c / 64: activation row block f / 3, plane f % 3
+  // for f < 12 RW, weight column tile f - 12 RW after that
+  const bf16x8* gsrc[Q];
+  bool have[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int c = tid + 256 * i, f = c >> 6, within = (c & 63) * 8;
+    if (f < NA) {
+      const int rbl = f / 3, p = f - 3 * rbl, rbg = rt * TR + rbl;
+      have[i] = rbg < nrb;
+      gsrc[i] = reinterpret_cast<const bf16x8*>(A + p * aplane + static_cast<long>(min(rbg, nrb - 1)) * S * 512 +
+                                                within);
+    } else {
+      have[i] = true;
+      gsrc[i] = reinterpret_cast<const bf16x8*>(Wf + static_cast<long>(ct * 8 + f - NA) * S * 512 + within);
+    }
+  }
+  bf16x8 st0[Q], st1[Q];
+  auto fetch = [&](int s, bf16x8 (&st)[Q]) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) st[i] = have[i] ? gsrc[i][s * 64] : bf16x8{};
+  };
+  auto put = [&](int buf, const bf16x8 (&st)[Q]) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lds[buf][tid + 256 * i] = st[i];
+  };
+  f32x4 acc[RW][8];
+#pragma unroll
+  for (int r = 0; r < RW; ++r)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[r][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto compute = [&](int buf) {
+    bf16x8 a[RW][3], b[8];
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+      for (int p = 0; p < 3; ++p) a[r][p] = lds[buf][((RW * wv + r) * 3 + p) * 64 + lane];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) b[j] = lds[buf][(NA + j) * 64 + lane];
+    // activation terms by decreasing pa (the weight has one term)
+#pragma unroll
+    for (int pa = 2; pa >= 0; --pa)
+#pragma unroll
+      for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r][pa], b[j], acc[r][j], 0, 0, 0);
+  };
+  // step k's loads go to st[k & 1]; step s + 2 is fetched before step s runs
+  fetch(0, st0);
+  if (S > 1) fetch(1, st1);
+  put(0, st0);
+  __syncthreads();
+  for (int s = 0; s < S; s += 2) {
+    if (s + 2 < S) fetch(s + 2, st0);
+    compute(0);
+    if (s + 1 >= S) break;
+    put(1, st1);
+    __syncthreads();
+    if (s + 3 < S) fetch(s + 3, st1);
+    compute(1);
+    if (s + 2 < S) put(0, st0);
+    __syncthreads();
+  }
+  // the epilogue reuses the LDS: every wave is past its last reads
+  __syncthreads();
+  const int nl = lane & 15;
+  if (CHI2) {
+#pragma unroll
+    for (int c2 = 0; c2 < 4; ++c2) {
+      const int n0 = ct * 128 + c2 * 32 + nl;
+      const float bz0 = bias ? bias[n0] : 0.f, bz1 = bias ? bias[n0 + 16] : 0.f;
+      const double d0 = data[n0], d1 = data[n0 + 16], s0 = isig[n0], s1 = isig[n0 + 16];
+#pragma unroll
+      for (int r = 0; r < RW; ++r)
+        for (int i = 0; i < 4; ++i) {
+          const double e0 = (static_cast<double>(acc[r][2 * c2][i] + bz0) - d0) * s0;
+          const double e1 = (static_cast<double>(acc[r][2 * c2 + 1][i] + bz1) - d1) * s1;
+          double t = e0 * e0 + e1 * e1;
+          for (int o = 8; o > 0; o >>= 1) t += __shfl_xor(t, o);
+          const int row = (rt * TR + RW * wv + r) * 16 + 4 * (lane >> 4) + i;
+          if (nl == 0 && row < M) part[static_cast<long>(ct * 4 + c2) * pstride + row] = t;
+        }
+    }
+  } else {
+    // per wave: a 3 x 16 x 40 bf16 transposition tile in the (now idle) LDS
+    __bf16 (*tile)[16][40] =
+        reinterpret_cast<__bf16 (*)[16][40]>(reinterpret_cast<unsigned char*>(&lds[0][0]) + wv * (3 * 16 * 40 * 2));
+    const int nbc = N >> 5;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int rbg = rt * TR + RW * wv + r;
+      if (rbg >= nrb) break;
+#pragma unroll
+      for (int c2 = 0; c2 < 4; ++c2) {
+        const int n0 = ct * 128 + c2 * 32 + nl;
+        const float bz0 = bias ? bias[n0] : 0.f, bz1 = bias ? bias[n0 + 16] : 0.f;
+        for (int i = 0; i < 4; ++i) {
+          const int rr = 4 * (lane >> 4) + i;
+          for (int t = 0; t < 2; ++t) {
+            const float x = act_fwd(act, acc[r][2 * c2 + t][i] + (t ? bz1 : bz0));
+            const __bf16 h = to_bf16(x);
+            const float r1 = x - from_bf16(h);
+            const __bf16 md = to_bf16(r1);
+            tile[0][rr][t * 16 + nl] = h;
+            tile[1][rr][t * 16 + nl] = md;
+            tile[2][rr][t * 16 + nl] = to_bf16(r1 - from_bf16(md));
+          }
+        }
+        // only this wave reads its tile (no workgroup barrier: waves leave the
+        // loop at different row blocks); the fence completes its LDS writes
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        const long o = (static_cast<long>(rbg) * nbc + ct * 4 + c2) * 512 + lane * 8;
+        const int rr = lane & 15, g = lane >> 4;
+        for (int p = 0; p < 3; ++p)
+          *reinterpret_cast<bf16x8*>(out + p * cplane + o) = *reinterpret_cast<const bf16x8*>(&tile[p][rr][8 * g]);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+      }
+    }
+  }
+}
+
 // logL[r] = -1/2 sum_q part[q pstride + r] (q ascending); NaN -> -inf.
 __global__ void k_chi2_sum(int M, int nb, const double* __restrict__ part, long pstride, double* __restrict__ logL,
                            const int* __restrict__ gate, const int* __restrict__ dM) {
@@ -628,6 +783,16 @@ hipError_t emu_forward_logL(const NetDev& net, int M, const __bf16* Xf, long xpl
       hipLaunchKernelGGL((k_dense_frag<false, 3>), grid, dim3(64), 0, s, M, N, K, in, inplane, net.Wf[0],
                          static_cast<long>(N) * 32, net.b[0], net.act, out, plane, nullptr, nullptr, nullptr, 0L,
                          gate, dM);
+    } else if (l == L - 1 && N % 128 == 0 && ((M + 127) / 128) * (N / 128) >= kFragTileMin) {
+      // many rows, output layer: 128 x 128 tiles per workgroup, operands in LDS
+      const dim3 gt(static_cast<unsigned>(((M + 127) / 128) * (N / 128)));
+      hipLaunchKernelGGL((k_dense_frag_t<true, 2>), gt, dim3(256), 0, s, M, N, K, in, inplane, net.Wf[l], net.b[l],
+                         kActNone, nullptr, 0L, data, isig, part, static_cast<long>(M), gate, dM);
+    } else if (l < L - 1 && N % 128 == 0 && ((M + 63) / 64) * (N / 128) >= kFragTileMin) {
+      // many rows, hidden layer: 64 x 128 tiles per workgroup, operands in LDS
+      const dim3 gt(static_cast<unsigned>(((M + 63) / 64) * (N / 128)));
+      hipLaunchKernelGGL((k_dense_frag_t<false, 1>), gt, dim3(256), 0, s, M, N, K, in, inplane, net.Wf[l], net.b[l],
+                         net.act, out, plane, nullptr, nullptr, nullptr, 0L, gate, dM);
     } else if (M >= kFragWideRows && N % 64 == 0) {
       // many rows: 32 x 64 blocks per wave (the same sums, more reuse per load)
       const dim3 gw(static_cast<unsigned>(((M + 31) / 32) * (N / 64)));

@@ -351,3 +351,27 @@ def test_wide_blocks_equal_narrow_blocks(M, widths):
     got, ref = wide.cpu().numpy(), narrow.cpu().numpy()
     assert np.all(np.isfinite(got))
     assert np.array_equal(got, ref)
+
+
+def test_tiled_layers_equal_narrow_blocks():
+    """Layers with at least 256 tiles of 128 x 128 (here the 27-512-512-512-1024
+    emulator at 8,155 rows: a ragged last tile) run on workgroup tiles with
+    the operands staged in LDS; the likelihoods equal those of calls below
+    4096 rows, bit for bit."""
+    M, widths = 8155, (27, 512, 512, 512, 1024)
+    spec = W.emulator(seed=9, widths=widths, noise_frac=0.05)
+    rng = np.random.default_rng(M)
+    u = rng.uniform(size=(M, widths[0]))
+    s = native.Sampler(spec, 64, prec="bf16x3", state="f32", seed=0, tree_depth=1)
+    d_u = torch.tensor(u, device=DEV)
+    tiled = torch.zeros(M, dtype=torch.float64, device=DEV)
+    native.ns_loglike_batch(s.ctx, d_u, tiled)
+    cut = 3001
+    narrow = torch.zeros(M, dtype=torch.float64, device=DEV)
+    for a in range(0, M, cut):
+        native.ns_loglike_batch(s.ctx, d_u[a:a + cut].contiguous(), narrow[a:a + cut])
+    native.ns_sync(s.ctx)
+    s.close()
+    got, ref = tiled.cpu().numpy(), narrow.cpu().numpy()
+    assert np.all(np.isfinite(got))
+    assert np.array_equal(got, ref)
