@@ -8,8 +8,8 @@
 // histogram of the digit among the entries that share the resolved prefix (in
 // LDS) and writes it out; a small kernel sums the partial histograms and its
 // last workgroup picks the bin that holds the m-th entry.  Once at most kSelCap entries lie at or
-// below the resolved prefix, one more pass collects them and a single
-// workgroup sorts them by (key, index) and writes the first m indices.  The
+// below the resolved prefix, one more pass collects them, and each candidate's
+// rank among them by (key, index) places the first m indices.  The
 // result equals a stable sort of (canon(logL), index).
 #include <algorithm>
 #include "ns_device.hpp"
@@ -259,36 +259,37 @@ k_rsel_collect(const double* __restrict__ logL, long N, SelWork* __restrict__ w)
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&w->st.passes, 1);
 }
 
-// The candidates sorted by (key, index) in LDS (bitonic), first m indices out.
-__global__ void __launch_bounds__(1024)
-k_rsel_sort(int m, SelWork* __restrict__ w, int* __restrict__ out, int* __restrict__ passes) {
-  __shared__ unsigned long long K[kSelCap];
-  __shared__ int I[kSelCap];
+// The candidates ranked by (key, index): one wave per candidate (grid-stride
+// over the candidates) counts the candidates before it, eight loads per lane
+// in flight; a candidate of rank r < m writes its index to out[r].  Keys
+// with their indices are distinct, so the ranks are 0 .. n - 1.
+__global__ void __launch_bounds__(256)
+k_rsel_rank(int m, const SelWork* __restrict__ w, int* __restrict__ out, int* __restrict__ passes) {
   const int n = min(w->st.ncand, kSelCap);
-  int P = 1;
-  while (P < n) P <<= 1;
-  for (int q = threadIdx.x; q < P; q += blockDim.x) {
-    K[q] = q < n ? w->ckey[q] : ~0ull;
-    I[q] = q < n ? w->cidx[q] : 0x7fffffff;
-  }
-  __syncthreads();
-  for (int k = 2; k <= P; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int q = threadIdx.x; q < P; q += blockDim.x) {
-        const int r = q ^ j;
-        if (r > q) {
-          const bool up = (q & k) == 0;
-          const bool gt = K[q] > K[r] || (K[q] == K[r] && I[q] > I[r]);
-          if (gt == up) {
-            const unsigned long long tk = K[q]; K[q] = K[r]; K[r] = tk;
-            const int ti = I[q]; I[q] = I[r]; I[r] = ti;
-          }
-        }
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), nwaves = gridDim.x * (blockDim.x >> 6);
+  for (int c = wave; c < n; c += nwaves) {
+    const unsigned long long kc = w->ckey[c];
+    const int ic = w->cidx[c];
+    int before = 0;
+    for (int j0 = 0; j0 < n; j0 += 8 * 64) {
+      unsigned long long kj[8];
+      int ij[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int j = min(j0 + 64 * q + lane, n - 1);
+        kj[q] = w->ckey[j];
+        ij[q] = w->cidx[j];
       }
-      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const bool lt = j0 + 64 * q + lane < n && (kj[q] < kc || (kj[q] == kc && ij[q] < ic));
+        before += __popcll(__ballot(lt));
+      }
     }
-  for (int q = threadIdx.x; q < m; q += blockDim.x) out[q] = I[q];
-  if (passes && threadIdx.x == 0) *passes = w->st.passes;
+    if (lane == 0 && before < m) out[before] = ic;
+  }
+  if (passes && blockIdx.x == 0 && threadIdx.x == 0) *passes = w->st.passes;
 }
 
 size_t select_large_work_bytes() { return sel_work_bytes(); }
@@ -314,7 +315,7 @@ hipError_t launch_select_large(const double* logL, long N, int m, int* out, void
   hipLaunchKernelGGL(k_rsel_collect, dim3(cgrid), dim3(256), 0, s, logL, N, w);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_rsel_sort, dim3(1), dim3(1024), 0, s, m, w, out, passes);
+  hipLaunchKernelGGL(k_rsel_rank, dim3(256), dim3(256), 0, s, m, w, out, passes);
   return hipGetLastError();
 }
 
