@@ -665,6 +665,25 @@ __global__ void k_cl_finish(int* __restrict__ passes, CLWork* __restrict__ w) {
   if (threadIdx.x == 0 && passes) *passes = w->st.passes;
 }
 
+// Workgroups of 256 threads of kernel k resident at once on the current
+// device (CUs times the occupancy), cached per device and width; 0 if the
+// runtime cannot tell.
+template <int DM>
+static int lloyd_resident() {
+  static int cache[16] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return 0;
+  if (cache[dev] == 0) {
+    int cus = 0, nb = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_cl_lloyd<DM>), 256, 0) !=
+            hipSuccess)
+      return 0;
+    cache[dev] = cus * nb;
+  }
+  return cache[dev];
+}
+
 hipError_t launch_cluster_split(const float* u, long N, int d, int iters, double* mean, double* cov,
                                 double* centres, unsigned char* side, void* work, int* passes, hipStream_t s) {
   if (N < 2 || d < 1 || d > kMaxD || iters < 0) return hipErrorInvalidValue;
@@ -674,6 +693,8 @@ hipError_t launch_cluster_split(const float* u, long N, int d, int iters, double
   const int DM = d <= 16 ? (d + 1) & ~1 : d <= 24 ? 24 : 32;
 #define NS_CL_CASE(K, M, ...) \
   case M: hipLaunchKernelGGL(K<M>, dim3(G), dim3(256), 0, s, __VA_ARGS__); break;
+#define NS_CL_CASE_G(K, GG, M, ...) \
+  case M: hipLaunchKernelGGL(K<M>, dim3(GG), dim3(256), 0, s, __VA_ARGS__); break;
 #define NS_CL_DM(K, ...)                                                                           \
   switch (DM) {                                                                                      \
     NS_CL_CASE(K, 2, __VA_ARGS__) NS_CL_CASE(K, 4, __VA_ARGS__) NS_CL_CASE(K, 6, __VA_ARGS__)       \
@@ -702,14 +723,38 @@ hipError_t launch_cluster_split(const float* u, long N, int d, int iters, double
     NS_CL_DM(k_cl_far, u, N, d, which, mean, w)
     hipLaunchKernelGGL(k_cl_red_far, dim3(R), dim3(256), 0, s, u, d, G, which, w);
   }
+  // the Lloyd passes hold more registers: their grid is what the device keeps
+  // resident at once (one round of workgroups, no tail)
+  int res = 0;
+  switch (DM) {
+    case 2: res = lloyd_resident<2>(); break;
+    case 4: res = lloyd_resident<4>(); break;
+    case 6: res = lloyd_resident<6>(); break;
+    case 8: res = lloyd_resident<8>(); break;
+    case 10: res = lloyd_resident<10>(); break;
+    case 12: res = lloyd_resident<12>(); break;
+    case 14: res = lloyd_resident<14>(); break;
+    case 16: res = lloyd_resident<16>(); break;
+    case 24: res = lloyd_resident<24>(); break;
+    default: res = lloyd_resident<32>(); break;
+  }
+  const int GL = res > 0 ? std::min(G, res) : G, RL = (GL + kCLFan - 1) / kCLFan;
   for (int r = 0; r <= iters; ++r) {
-    NS_CL_DM(k_cl_lloyd, u, N, d, r, side, w)
-    hipLaunchKernelGGL(k_cl_red_lloyd, dim3(R), dim3(256), 0, s, N, d, G, r, iters, centres, w);
+    switch (DM) {
+      NS_CL_CASE_G(k_cl_lloyd, GL, 2, u, N, d, r, side, w) NS_CL_CASE_G(k_cl_lloyd, GL, 4, u, N, d, r, side, w)
+      NS_CL_CASE_G(k_cl_lloyd, GL, 6, u, N, d, r, side, w) NS_CL_CASE_G(k_cl_lloyd, GL, 8, u, N, d, r, side, w)
+      NS_CL_CASE_G(k_cl_lloyd, GL, 10, u, N, d, r, side, w) NS_CL_CASE_G(k_cl_lloyd, GL, 12, u, N, d, r, side, w)
+      NS_CL_CASE_G(k_cl_lloyd, GL, 14, u, N, d, r, side, w) NS_CL_CASE_G(k_cl_lloyd, GL, 16, u, N, d, r, side, w)
+      NS_CL_CASE_G(k_cl_lloyd, GL, 24, u, N, d, r, side, w)
+      default: hipLaunchKernelGGL(k_cl_lloyd<32>, dim3(GL), dim3(256), 0, s, u, N, d, r, side, w); break;
+    }
+    hipLaunchKernelGGL(k_cl_red_lloyd, dim3(RL), dim3(256), 0, s, N, d, GL, r, iters, centres, w);
   }
   hipLaunchKernelGGL(k_cl_finish, dim3(1), dim3(64), 0, s, passes, w);
 #undef NS_CL_DM
 #undef NS_CL_DM16
 #undef NS_CL_CASE
+#undef NS_CL_CASE_G
   return hipGetLastError();
 }
 
