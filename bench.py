@@ -18,8 +18,9 @@ the transfer-matrix quadrature value.
 Other modes (one JSON line each): --workload 4 / 5 (27-d emulator runs, with
 --prec f32|bf16x3 and --no-screen), --lik-sweep (the batched emulator
 likelihood at 200 ... 25,600 rows per call), --select-sweep (worst-1000
-selection at N = 2^16 ... 2^24) and --cluster-sweep (one cluster-tree node at
-N = 2^16 ... 2^24).
+selection at N = 2^16 ... 2^24), --cluster-sweep (one cluster-tree node at
+N = 2^16 ... 2^24) and --train-sweep (a dense network's training step at
+batch 1,024 ... 65,536).
 """
 import argparse
 import json
@@ -100,6 +101,8 @@ def main():
                     help="one cluster-tree node (mean, covariance, 2-means) at N = 2^16 ... 2^24, d = 10")
     ap.add_argument("--lik-sweep", action="store_true",
                     help="batched emulator likelihood alone at M = 200 ... 25600 rows per call")
+    ap.add_argument("--train-sweep", action="store_true",
+                    help="network training step alone (forward + backward) at batch 1024 ... 65536")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -129,6 +132,8 @@ def main():
         return bench_select_sweep(args, np, torch, native)
     if args.cluster_sweep:
         return bench_cluster_sweep(args, np, torch, native)
+    if args.train_sweep:
+        return bench_train_sweep(args, np, torch, native)
     if args.workload in (4, 5):
         return bench_emulator(args, np, torch, native, workloads)
     spec = workloads.likelihood(2)
@@ -322,6 +327,64 @@ def bench_cluster_sweep(args, np, torch, native):
     print(json.dumps({"metric": "cluster-tree node (mean, covariance, 2-means), N sweep", "dtype": "f64",
                       "data": "synthetic", "peak_gbs": HBM_PEAK / 1e9,
                       "config": {"workload": "two blobs in [0,1]^10, FP32 points"}, "sweep": res}))
+
+
+def bench_train_sweep(args, np, torch, native):
+    """One training step of a dense network on the library's kernels
+    (ns_mlp_forward keeping the pre-activations and hidden outputs, then
+    ns_mlp_backward for dW, db; no input gradient), for the learned pre-screen
+    (27-256-256-1, SiLU) and the 27-d emulator shape (27-512-512-512-1024,
+    tanh), at batch B, in bfloat16 MFMA and FP32 FMA.  Timed with torch events
+    on the stream the calls run on.  Work per sample: 2 sum_l w_l w_{l+1}
+    forward, the same for dW and again for the input gradients of every layer
+    but the first."""
+    nets = [("screen 27-256-256-1 silu", (27, 256, 256, 1), "silu", (1024, 4096, 16384, 65536)),
+            ("emulator 27-512-512-512-1024 tanh", (27, 512, 512, 512, 1024), "tanh", (1024, 4096, 16384))]
+    gen = torch.Generator().manual_seed(0)
+    res = []
+    for name, widths, act, batches in nets:
+        Ws = [((torch.rand((widths[l], widths[l + 1]), generator=gen) * 2 - 1) *
+               math.sqrt(6.0 / (widths[l] + widths[l + 1]))).to("cuda:0") for l in range(len(widths) - 1)]
+        bs = [torch.zeros(widths[l + 1], device="cuda:0") for l in range(len(widths) - 1)]
+        desc = native.mlp_desc(Ws, bs, act)
+        prods = [widths[l] * widths[l + 1] for l in range(len(widths) - 1)]
+        flops = 2 * sum(prods) + 2 * sum(prods) + 2 * sum(prods[1:])
+        for prec in ("bf16", "f32"):
+            peak = BF16_PEAK if prec == "bf16" else FP32_PEAK
+            for B in batches:
+                X = torch.rand((B, widths[0]), generator=gen).to("cuda:0")
+                tot = B * sum(widths[1:])
+                Z = torch.empty(tot, device="cuda:0")
+                H = torch.empty(tot, device="cuda:0")
+                Y = torch.empty((B, widths[-1]), device="cuda:0")
+                dY = torch.randn((B, widths[-1]), generator=gen).to("cuda:0")
+                dWs = [torch.empty_like(w) for w in Ws]
+                dbs = [torch.empty_like(b) for b in bs]
+                work = torch.empty(2 * B * max(widths), device="cuda:0")
+
+                def step():
+                    native.ns_mlp_forward(desc, prec, X, Y, Z, H)
+                    native.ns_mlp_backward(desc, prec, X, Z, H, dY, dWs, dbs, None, work)
+
+                step()
+                torch.cuda.synchronize()
+                reps = max(5, min(200, (1 << 22) // B))
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    step()
+                e1.record()
+                torch.cuda.synchronize()
+                t = e0.elapsed_time(e1) * 1e-3 / reps
+                tf = B * flops / t
+                res.append({"net": name, "prec": prec, "batch": B, "us_per_step": 1e6 * t,
+                            "tflops": tf / 1e12, "frac": tf / peak})
+                print(f"[bench] train {name} {prec} B={B}: {1e6 * t:.1f} us, {tf / 1e12:.1f} TFLOP/s "
+                      f"({100 * tf / peak:.1f} % of peak)", file=sys.stderr, flush=True)
+                del X, Z, H, Y, dY, work
+    print(json.dumps({"metric": "dense network training step (forward + backward), batch sweep",
+                      "dtype": "bf16 / f32", "data": "synthetic",
+                      "peaks_tflops": {"bf16": BF16_PEAK / 1e12, "f32": FP32_PEAK / 1e12}, "sweep": res}))
 
 
 def bench_lik_sweep(args, np, torch, native, workloads):

@@ -94,22 +94,47 @@ k_gemm(int M, int N, int K, const float* __restrict__ A, long sar, long sak,
     for (int jx = 0; jx < 2; ++jx) macc[i][jx] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   const int wave = tid >> 6, lane = tid & 63;
-  for (int k0 = k_begin; k0 < k_end; k0 += kTK) {
-    // stage A (64 x 32) and B^T (64 x 32) as FP32
-    // the unit-stride index runs fastest across threads (coalesced loads)
-    for (int q = tid; q < kTM * kTK; q += 256) {
+  // stage A (64 x 32) and B^T (64 x 32) as FP32: element q = tid + 256 i of a
+  // tile, the unit-stride index running fastest across threads (coalesced);
+  // the loads of the next K step are issued before the current one is used
+  constexpr int kQ = kTM * kTK / 256;
+  float va[kQ], vb[kQ];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const int q = tid + 256 * i;
       const int r = (sak == 1) ? q / kTK : q % kTM;
       const int k = (sak == 1) ? q % kTK : q / kTM;
       const int gr = m0 + r, gk = k0 + k;
-      As[r * kLdsK + k] = (gr < M && gk < k_end) ? A[gr * sar + gk * sak] : 0.f;
+      va[i] = (gr < M && gk < k_end) ? A[gr * sar + gk * sak] : 0.f;
     }
-    for (int q = tid; q < kTN * kTK; q += 256) {
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const int q = tid + 256 * i;
       const int r = (sbk == 1) ? q / kTK : q % kTN;
       const int k = (sbk == 1) ? q % kTK : q / kTN;
       const int gn = n0 + r, gk = k0 + k;
-      Bs[r * kLdsK + k] = (gn < N && gk < k_end) ? B[gn * sbn + gk * sbk] : 0.f;
+      vb[i] = (gn < N && gk < k_end) ? B[gn * sbn + gk * sbk] : 0.f;
+    }
+  };
+  if (k_begin < k_end) fetch(k_begin);
+  for (int k0 = k_begin; k0 < k_end; k0 += kTK) {
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const int q = tid + 256 * i;
+      const int r = (sak == 1) ? q / kTK : q % kTM;
+      const int k = (sak == 1) ? q % kTK : q / kTM;
+      As[r * kLdsK + k] = va[i];
+    }
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const int q = tid + 256 * i;
+      const int r = (sbk == 1) ? q / kTK : q % kTN;
+      const int k = (sbk == 1) ? q % kTK : q / kTN;
+      Bs[r * kLdsK + k] = vb[i];
     }
     __syncthreads();
+    if (k0 + kTK < k_end) fetch(k0 + kTK);
     if (MODE == kF32) {
       const int tr = tid >> 4, tc = tid & 15;
       for (int k = 0; k < kTK; ++k) {
@@ -229,7 +254,9 @@ hipError_t launch_gemm_splitk(int mode, int M, int N, int K, const float* A, lon
   if (M <= 0 || N <= 0) return hipSuccess;
   const int tiles = ((N + kTN - 1) / kTN) * ((M + kTM - 1) / kTM);
   int S = 1;
-  while (tiles * S < 256 && K / (S * 2) >= 256 && static_cast<long>(2 * S) * M * N <= work_elems) S *= 2;
+  // split the reduction until about four workgroups per CU run (chunks of at
+  // least 256 rows of K)
+  while (tiles * S < 1024 && K / (S * 2) >= 256 && static_cast<long>(2 * S) * M * N <= work_elems) S *= 2;
   if (S == 1)
     return launch_gemm(mode, M, N, K, A, sar, sak, B, sbn, sbk, nullptr, kActNone, C, N, nullptr, 0,
                        nullptr, s);

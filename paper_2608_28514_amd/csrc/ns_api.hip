@@ -296,7 +296,7 @@ static hipError_t mlp_fwd_impl(const ns_mlp_desc* net, int mode, const float* X,
 }
 
 // red_work (may be null): workspace for split-K weight gradients and chunked
-// bias sums (red_elems floats); without it the plain kernels run.
+// bias sums (red_elems floats); without it the free half of `work` is used.
 static hipError_t mlp_bwd_impl(const ns_mlp_desc* net, int mode, const float* X, long B, const float* Zs,
                                const float* Hs, const float* dY, float* const* dW, float* const* db,
                                float* dX, float* work, hipStream_t s, float* red_work = nullptr,
@@ -319,15 +319,14 @@ static hipError_t mlp_bwd_impl(const ns_mlp_desc* net, int mode, const float* X,
       dz = dZ;
     }
     const float* hin = (l == 0) ? X : Hs + off[l - 1];
-    // dW = H^T dZ
-    if (red_work)
-      e = launch_gemm_splitk(mode, K, N, static_cast<int>(B), hin, 1, K, dz, 1, N, dW[l], red_work,
-                             red_elems, s);
-    else
-      e = launch_gemm(mode, K, N, static_cast<int>(B), hin, 1, K, dz, 1, N, nullptr, kActNone, dW[l], N,
-                      nullptr, 0, nullptr, s);
+    // dW = H^T dZ (split over the batch, partial planes summed in order), db =
+    // column sums of dZ (in chunks); without a workspace of its own the dH
+    // half of `work` serves: it is free until dH = dZ W^T below
+    float* rw = red_work ? red_work : dH;
+    const long re = red_work ? red_elems : B * maxw;
+    e = launch_gemm_splitk(mode, K, N, static_cast<int>(B), hin, 1, K, dz, 1, N, dW[l], rw, re, s);
     if (e != hipSuccess) return e;
-    e = launch_colsum(static_cast<int>(B), N, dz, db[l], s, red_work, red_elems);
+    e = launch_colsum(static_cast<int>(B), N, dz, db[l], s, rw, re);
     if (e != hipSuccess) return e;
     if (l > 0 || dX) {
       float* out = (l == 0) ? dX : dH;
