@@ -514,7 +514,8 @@ def bench_emulator(args, np, torch, native, workloads):
         "evals_per_s": evals / t_total, "net_rows_per_s": rows / t_total,
         "kernel_ms": {c: round(v[0], 3) for c, v in kern.items()},
         "kernel_launches": {c: v[1] for c, v in kern.items()},
-        "roofline": {"kernel": ("k_dense_frag (emulator layers, chi^2 fused) + k_chi2_rows"
+        "roofline": {"kernel": ("k_dense_frag (emulator layers, chi^2 partials fused; the row sums run in "
+                                "the next round's advance kernel)"
                                 if prec.startswith("bf16") else "k_gemm<F32> + k_chi2"),
                      "bound": "mfma" if prec.startswith("bf16") else "alu", "achieved": achieved / 1e12,
                      "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,

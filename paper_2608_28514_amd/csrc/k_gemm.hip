@@ -746,41 +746,6 @@ __global__ void k_chi2_sum(int M, int nb, const double* __restrict__ part, long 
   logL[r] = isnan(v) ? -INFINITY : v;
 }
 
-// Direct rounds: compacted row i (i < *crows) belongs to row cmap[i/P] P + i%P
-// of the round; its logL is -1/2 sum_q part[q pstride + i] (q ascending; NaN
-// -> -inf), or -inf when that row's flag is 0.  Adds the compacted row count
-// to *net_rows.
-__global__ void k_chi2_rows(int P, const double* __restrict__ part, int nb, long pstride,
-                            const int* __restrict__ crows, const int* __restrict__ cmap,
-                            const int* __restrict__ flag, double* __restrict__ rlogL,
-                            unsigned long long* __restrict__ net_rows, const int* __restrict__ gate) {
-  if (gate && *gate == 0) return;
-  const int n = *crows;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0 && net_rows) *net_rows += static_cast<unsigned long long>(n);
-  if (i >= n) return;
-  const long r = static_cast<long>(cmap[i / P]) * P + i % P;
-  double t = 0.0;
-  for (int q0 = 0; q0 < nb; q0 += 8) {
-    double v[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = part[min(q0 + j, nb - 1) * pstride + i];
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-      if (q0 + j < nb) t += v[j];
-  }
-  const double v = -0.5 * t;
-  rlogL[r] = (flag[r] == 0 || isnan(v)) ? -INFINITY : v;
-}
-
-hipError_t launch_chi2_rows(int M, int P, int nb, const double* part, const int* crows, const int* cmap,
-                            const int* flag, double* rlogL, unsigned long long* net_rows, const int* gate,
-                            hipStream_t s) {
-  if (M <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_chi2_rows, dim3((M + 255) / 256), dim3(256), 0, s, P, part, nb, static_cast<long>(M), crows,
-                     cmap, flag, rlogL, net_rows, gate);
-  return hipGetLastError();
-}
 
 bool emu_frag_eligible(const NetDev& net, int mode_first, int mode_rest) {
   if (mode_first != kF32 || mode_rest != kBF16S || net.n_layers < 2 || net.widths[0] > 32) return false;

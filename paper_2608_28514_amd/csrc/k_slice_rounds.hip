@@ -28,7 +28,9 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
                  int* __restrict__ gate, T* __restrict__ new_u, double* __restrict__ new_logL,
                  int* __restrict__ chain_stat, double* __restrict__ hist_logL,
                  T* __restrict__ hist_u, int* __restrict__ hist_n, const RunState* __restrict__ st,
-                 __bf16* __restrict__ xf, long xfplane, int* __restrict__ crows, int* __restrict__ cmap) {
+                 __bf16* __restrict__ xf, long xfplane, int* __restrict__ crows, int* __restrict__ cmap,
+                 int* __restrict__ cbase, const double* __restrict__ xpart, long xpstride, int xnb,
+                 unsigned long long* __restrict__ xnet_rows) {
   // Everything the round reads from memory is loaded at once: run and round
   // flags, thresholds, the chain state words and this chain's P result rows
   // (a load behind a branch on an earlier one would wait for it).
@@ -50,7 +52,28 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
     const long rr = row0 + min(lane, P - 1);   // rows past the chain's block are never used
     fl = flag[rr];
     sf = sflag ? sflag[rr] : 0;
-    rl = rlogL[rr];
+    if (xpart) {
+      // direct rounds: -1/2 sum_q of the row's chi^2 partials (q ascending;
+      // NaN -> -inf), -inf for rows not evaluated
+      const int base = cbase[j];
+      double t = 0.0;
+      if (base >= 0) {
+        const double* pp = xpart + base + min(lane, P - 1);
+        for (int q0 = 0; q0 < xnb; q0 += 8) {
+          double v[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) v[i] = pp[static_cast<long>(min(q0 + i, xnb - 1)) * xpstride];
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            if (q0 + i < xnb) t += v[i];
+        }
+      }
+      const double v = -0.5 * t;
+      rl = (base < 0 || fl == 0 || isnan(v)) ? -INFINITY : v;
+      if (j == 0 && lane == 0 && xnet_rows) *xnet_rows += static_cast<unsigned long long>(crows[round - 1]);
+    } else {
+      rl = rlogL[rr];
+    }
   }
   if (run_done) return;
   if (round > 0 && prev_gate == 0) return;   // every chain finished earlier
@@ -322,6 +345,7 @@ k_rounds_advance(int round, RoundsParams p, const T* __restrict__ u, const doubl
         s_crow = atomicAdd(&crows[round], P);
         cmap[s_crow / P] = j;
       }
+      cbase[j] = s_crow;
     }
   }
   __syncthreads();
@@ -372,7 +396,7 @@ hipError_t launch_rounds_advance(int round, const RoundsParams& p, const Shape& 
                        static_cast<ChainState<float>*>(r.cs), static_cast<float*>(r.pts), r.xin, r.flag,
                        r.rlogL, r.rthr, r.sflag, r.gate, static_cast<float*>(b.new_u), b.new_logL, b.chain_stat,
                        b.hist_logL, static_cast<float*>(b.hist_u), b.hist_n, b.st, r.xf_direct, r.xf_plane,
-                       r.crows, r.cmap);
+                       r.crows, r.cmap, r.cbase, r.xf_direct ? r.xpart : nullptr, r.xpstride, r.xnb, r.xnet_rows);
   else
     hipLaunchKernelGGL(k_rounds_advance<double>, dim3(p.m), dim3(64), 0, s, round, p,
                        static_cast<const double*>(b.u), b.logL, b.label, b.chol, b.seeds, b.tau, b.LW,
@@ -380,7 +404,8 @@ hipError_t launch_rounds_advance(int round, const RoundsParams& p, const Shape& 
                        r.flag, r.rlogL, r.rthr, r.sflag, r.gate, static_cast<double*>(b.new_u), b.new_logL,
                        b.chain_stat,
                        b.hist_logL, static_cast<double*>(b.hist_u), b.hist_n, b.st, r.xf_direct,
-                       r.xf_plane, r.crows, r.cmap);
+                       r.xf_plane, r.crows, r.cmap, r.cbase, r.xf_direct ? r.xpart : nullptr, r.xpstride, r.xnb,
+                       r.xnet_rows);
   return hipGetLastError();
 }
 

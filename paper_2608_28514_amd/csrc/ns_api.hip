@@ -233,7 +233,7 @@ static void free_all(ns_ctx* c) {
                   b.chain_stat, b.hist_logL, b.hist_u, b.hist_n, b.draws, b.nodeof, b.count,
                   b.accepted, b.split_ok, b.logV, b.logV_eff, b.centre, b.cov, b.chol, b.chol_f,
                   b.dead_u, b.dead_logL, b.st, c->d_out3, c->rb.cs, c->rb.pts, c->rb.xin,
-                  c->rb.flag, c->rb.rlogL, c->rb.gate, c->rb.crows, c->rb.cmap, c->rb.H0, c->rb.H1, c->rb.Y, c->rb.rthr,
+                  c->rb.flag, c->rb.rlogL, c->rb.gate, c->rb.crows, c->rb.cmap, c->rb.cbase, c->rb.H0, c->rb.H1, c->rb.Y, c->rb.rthr,
                   c->rb.sflag, c->d_sc, c->d_count, c->d_chunk, c->d_idx, c->d_aud, c->d_xc, c->d_xf, c->d_clogL,
                   c->d_yhat, c->sP, c->sG, c->sM, c->sV, c->s_norm, c->s_loss, c->s_Xb, c->s_yb,
                   c->s_Yb, c->s_Z, c->s_H, c->s_dY, c->s_work, c->s_red, c->s_H0, c->s_H1, c->rep_x, c->rep_y,
@@ -362,13 +362,11 @@ static ns_status eval_rows(ns_ctx* c, long n, const int* gate, bool allow_screen
   if (c->is_mlp && round >= 0 && c->rb.xf_direct) {
     // rows written by the advance kernel straight into compacted split planes
     const int* crows = c->rb.crows + round;
+    // (the next round's advance kernel sums the chi^2 partials of its rows)
     NS_TRY(emu_forward_logL(c->net, static_cast<int>(n), c->rb.xf_direct, c->rb.xf_plane,
                             reinterpret_cast<__bf16*>(c->rb.H0), reinterpret_cast<__bf16*>(c->rb.H1),
                             reinterpret_cast<double*>(c->rb.Y), c->mlp_data, c->mlp_isig, nullptr, gate, crows,
                             c->stream));
-    NS_TRY(launch_chi2_rows(static_cast<int>(n), c->rp.P, c->net.widths[c->net.n_layers] / 32,
-                            reinterpret_cast<const double*>(c->rb.Y), crows, c->rb.cmap, c->rb.flag,
-                            c->rb.rlogL, &c->d_sc->emu_rows, gate, c->stream));
     return NS_OK;
   }
   if (c->is_mlp) {
@@ -420,7 +418,14 @@ static ns_status run_rounds(ns_ctx* c, int m) {
   // screen needs it, so not while a surrogate is attached)
   c->rb.xf_direct = (c->is_mlp && c->emu_frag && !c->surr) ? c->d_xf : nullptr;
   c->rb.xf_plane = c->xf_plane;
-  if (c->rb.xf_direct) NS_TRY(launch_fill_int(c->rb.crows, c->rb.gate_cap, 0, c->stream));
+  c->rb.xpart = nullptr;
+  if (c->rb.xf_direct) {
+    NS_TRY(launch_fill_int(c->rb.crows, c->rb.gate_cap, 0, c->stream));
+    c->rb.xpart = reinterpret_cast<const double*>(c->rb.Y);
+    c->rb.xpstride = rows;
+    c->rb.xnb = c->net.widths[c->net.n_layers] / 32;
+    c->rb.xnet_rows = &c->d_sc->emu_rows;
+  }
   const int chunk = 48;
   int r = 0;
   for (;;) {
@@ -762,6 +767,7 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
     NS_INIT_HIP(dalloc(&rb.gate, rb.gate_cap));
     NS_INIT_HIP(dalloc(&rb.crows, rb.gate_cap));
     NS_INIT_HIP(dalloc(&rb.cmap, static_cast<size_t>(rb.rows_cap / rp.P + 1)));
+    NS_INIT_HIP(dalloc(&rb.cbase, static_cast<size_t>(rb.rows_cap / rp.P + 1)));
     NS_INIT_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_gate), sizeof(int), hipHostMallocDefault));
     if (c->is_mlp) {
       // hidden activations: FP32, or three bfloat16 planes (1.5x) on the split path

@@ -84,13 +84,6 @@ long emu_frag_plane(long M, int max_width);
 hipError_t emu_forward_logL(const NetDev& net, int M, const __bf16* Xf, long xplane, __bf16* P0, __bf16* P1,
                             double* part, const double* data, const double* isig, double* logL, const int* gate,
                             const int* dM, hipStream_t s);
-// Direct rounds (no compaction pass): the partials of emu_forward_logL over
-// M = *crows compacted rows (pstride M, the host bound), summed into the
-// round's rows: compacted row i is row cmap[i/P] P + i%P; flag 0 -> -inf.
-// net_rows (may be null) accumulates the compacted row count.
-hipError_t launch_chi2_rows(int M, int P, int nb, const double* part, const int* crows, const int* cmap,
-                            const int* flag, double* rlogL, unsigned long long* net_rows, const int* gate,
-                            hipStream_t s);
 // Host: W^T (N x K FP32, N % 16 == 0, K % 32 == 0) -> fragment-major bfloat16.
 void frag_layout_host(const float* Wt, int N, int K, __bf16* out);
 // Host: W^T (N x K0 FP32, K0 <= 32) -> three fragment-major planes (hi, mid,

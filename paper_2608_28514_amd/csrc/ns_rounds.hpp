@@ -48,6 +48,15 @@ struct RoundBufs {
   long xf_plane;
   int* crows;      // gate_cap entries
   int* cmap;       // m entries
+  // Direct rounds also leave each chain's first compacted row in cbase (-1:
+  // none), and the next round's advance kernel sums that chain's chi^2
+  // partials xpart[q xpstride + row], q < xnb, into its row likelihoods (and
+  // adds the round's compacted rows to *xnet_rows); xpart null: rlogL is read.
+  int* cbase;      // m entries
+  const double* xpart;
+  long xpstride;
+  int xnb;
+  unsigned long long* xnet_rows;
 };
 
 hipError_t launch_fill_int(int* p, long n, int v, hipStream_t s);
