@@ -117,7 +117,7 @@ def main():
         print(json.dumps({"copy_probe_bytes": 4 * n}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU only; run with --gpus 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
