@@ -6,11 +6,13 @@
 // cannot separate the m-th entry (ties) the index follows in 12-bit digits.
 // Every digit costs one streaming pass over logL: each workgroup builds a
 // histogram of the digit among the entries that share the resolved prefix (in
-// LDS) and writes it out; a small kernel sums the partial histograms and its
-// last workgroup picks the bin that holds the m-th entry.  Once at most kSelCap entries lie at or
-// below the resolved prefix, one more pass collects them, and each candidate's
-// rank among them by (key, index) places the first m indices.  The
-// result equals a stable sort of (canon(logL), index).
+// LDS) and writes it out; a small kernel sums the partial histograms, and
+// every workgroup of the next launch picks from the totals the bin that holds
+// the m-th entry (the same pick in each, so no workgroup waits on another and
+// no kernel needs a device-wide fence).  Once at most kSelCap entries lie at
+// or below the resolved prefix, one more pass collects them, and each
+// candidate's rank among them by (key, index) places the first m indices.
+// The result equals a stable sort of (canon(logL), index).
 #include <algorithm>
 #include "ns_device.hpp"
 #include "ns_select_large.hpp"
@@ -30,16 +32,18 @@ struct SelState {
   int sshift;                  // 32: no index bit resolved yet
   int below;                   // entries strictly below the resolved prefix
   int done;                    // at most kSelCap entries at or below the prefix
-  unsigned int ticket;         // workgroups finished in the current pass
-  int ncand;                   // entries collected
   int passes;                  // streaming passes over logL so far
 };
 
 struct SelWork {
-  SelState st;
-  unsigned int pad[48];
-  unsigned int hist[kRBins];
-  unsigned int part[kSelGroups][kRBins];
+  // slot[l]: the state before digit l (slot[0] from the init kernel, slot[l]
+  // written by workgroup 0 of digit l's histogram launch); slot[kSelLevels]:
+  // the final state, written by the collect pass
+  SelState slot[kSelLevels + 1];
+  int ncand;                   // entries collected
+  unsigned int pad[31];
+  alignas(16) unsigned int hist[kRBins];   // totals of the last summed digit
+  alignas(16) unsigned int part[kSelGroups][kRBins];
   unsigned long long ckey[kSelCap];
   int cidx[kSelCap];
 };
@@ -76,11 +80,73 @@ __global__ void k_rsel_init(long N, int m, SelWork* w) {
     s.sshift = 32;
     s.below = 0;
     s.done = N <= kSelCap ? 1 : 0;
-    s.ticket = 0u;
-    s.ncand = 0;
     s.passes = 0;
-    w->st = s;
+    w->slot[0] = s;
+    w->ncand = 0;
   }
+}
+
+// The pick of digit `level` from its totals (w->hist), by every thread of a
+// workgroup (NB consecutive bins per thread, NB * blockDim.x == kRBins): an
+// inclusive scan (thread totals within each wave, then the wave totals)
+// finds the first bin where below + cum >= m; each thread returns the
+// advanced state.
+template <int NB>
+__device__ SelState pick_digit(const SelState& s, int level, int m, const SelWork* __restrict__ w) {
+  __shared__ unsigned int wsum[16];
+  __shared__ int s_bin, s_before;
+  __shared__ unsigned int s_cnt;
+  const int tt = threadIdx.x, ln = tt & 63, wq = tt >> 6;
+  unsigned int hb[NB];
+#pragma unroll
+  for (int r = 0; r < NB / 4; ++r) {
+    const uint4 hv = reinterpret_cast<const uint4*>(w->hist)[NB / 4 * tt + r];
+    hb[4 * r] = hv.x;
+    hb[4 * r + 1] = hv.y;
+    hb[4 * r + 2] = hv.z;
+    hb[4 * r + 3] = hv.w;
+  }
+  unsigned int run = 0u;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) run += hb[q];
+  unsigned int inc = run;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned int y = __shfl_up(inc, o);
+    if (ln >= o) inc += y;
+  }
+  if (ln == 63) wsum[wq] = inc;
+  __syncthreads();
+  unsigned int before = inc - run;
+  for (int q = 0; q < wq; ++q) before += wsum[q];
+  const long need = static_cast<long>(m) - s.below;
+  unsigned int c = before;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    if (static_cast<long>(c) < need && static_cast<long>(c + hb[q]) >= need) {
+      s_bin = NB * tt + q;
+      s_before = static_cast<int>(c);
+      s_cnt = hb[q];
+    }
+    c += hb[q];
+  }
+  __syncthreads();
+  const Level L = sel_level(level);
+  const int bin = s_bin;
+  SelState n = s;
+  if (L.slot_phase) {
+    n.sprefix = (n.sshift == 32) ? static_cast<unsigned int>(bin) : ((n.sprefix << L.width) | bin);
+    n.sshift = L.shift;
+  } else {
+    n.kprefix = (n.kshift == 64) ? static_cast<unsigned long long>(bin)
+                                 : ((n.kprefix << L.width) | static_cast<unsigned long long>(bin));
+    n.kshift = L.shift;
+  }
+  n.below = s.below + s_before;
+  n.done = (static_cast<long>(n.below) + s_cnt <= kSelCap) ? 1 : 0;
+  n.passes = s.passes + 1;
+  __syncthreads();   // the LDS words above are reused by the next call
+  return n;
 }
 
 // One digit, pass 1 of 2: each workgroup counts the digit of the entries in
@@ -92,11 +158,16 @@ __global__ void k_rsel_init(long N, int m, SelWork* w) {
 // then meet at most 16 to an address; the copies are summed at the end.
 // Workgroups of 1024 threads (16 waves).
 __global__ void __launch_bounds__(1024)
-k_rsel_hist(const double* __restrict__ logL, long N, int level, SelWork* __restrict__ w) {
+k_rsel_hist(const double* __restrict__ logL, long N, int m, int level, SelWork* __restrict__ w) {
   __shared__ uint4 lh4[kRBins];
   unsigned int* lh = reinterpret_cast<unsigned int*>(lh4);
-  if (w->st.done) return;
-  const SelState s = w->st;
+  // the state before this digit: the previous digit's pick, made here
+  SelState s = w->slot[level > 0 ? level - 1 : 0];
+  if (level > 0) {
+    if (!s.done) s = pick_digit<kRBins / 1024>(s, level - 1, m, w);
+    if (blockIdx.x == 0 && threadIdx.x == 0) w->slot[level] = s;
+  }
+  if (s.done) return;
   const Level L = sel_level(level);
   const unsigned int mask = (1u << L.width) - 1u;
   const unsigned int cp = threadIdx.x & 3;
@@ -141,18 +212,15 @@ k_rsel_hist(const double* __restrict__ logL, long N, int level, SelWork* __restr
   }
 }
 
-// One digit, pass 2 of 2: the partial histograms summed per bin (in
-// workgroup order); the last workgroup to finish picks the bin that holds the
-// m-th entry and advances the resolved prefix.
+// One digit, pass 2 of 2: the partial histograms summed per bin into the
+// totals the next launch picks from.
 __global__ void __launch_bounds__(256)
-k_rsel_reduce(int groups, int m, int level, SelWork* __restrict__ w) {
-  __shared__ int s_last;
+k_rsel_reduce(int groups, int level, SelWork* __restrict__ w) {
   __shared__ unsigned int qs[256];
-  if (w->st.done) return;
+  if (w->slot[level].done) return;
   // 64 bins per workgroup (gridDim.x * 64 == kRBins); the four waves take
   // every fourth partial (32 loads in flight), then their four sums are added
-  // in wave order.  (Fewer workgroups: each one's agent-scope fence below
-  // writes back the L2.)
+  // in wave order.
   const int b = blockIdx.x * 64 + (threadIdx.x & 63), qq = threadIdx.x >> 6;
   unsigned int t = 0u;
   for (int g0 = qq; g0 < groups; g0 += 4 * 32) {
@@ -166,73 +234,20 @@ k_rsel_reduce(int groups, int m, int level, SelWork* __restrict__ w) {
   qs[threadIdx.x] = t;
   __syncthreads();
   if (qq == 0) w->hist[b] = ((qs[threadIdx.x] + qs[64 + threadIdx.x]) + qs[128 + threadIdx.x]) + qs[192 + threadIdx.x];
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) s_last = atomicAdd(&w->st.ticket, 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  const SelState s = w->st;
-  const Level L = sel_level(level);
-  // last workgroup: inclusive scan of the histogram (16 bins per thread, the
-  // thread totals scanned within each wave, then the four wave totals), first
-  // bin where below + cum >= m
-  __shared__ unsigned int wsum[4];
-  __shared__ int s_bin, s_before;
-  const int tt = threadIdx.x, ln = tt & 63, wq = tt >> 6;
-  unsigned int hb[16], run = 0u;
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    hb[q] = atomicAdd(&w->hist[16 * tt + q], 0u);
-    run += hb[q];
-  }
-  unsigned int inc = run;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const unsigned int y = __shfl_up(inc, o);
-    if (ln >= o) inc += y;
-  }
-  if (ln == 63) wsum[wq] = inc;
-  if (tt == 0) s_bin = -1;
-  __syncthreads();
-  unsigned int before = inc - run;
-  for (int q = 0; q < wq; ++q) before += wsum[q];
-  const long need = static_cast<long>(m) - s.below;
-  unsigned int c = before;
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    if (static_cast<long>(c) < need && static_cast<long>(c + hb[q]) >= need) {
-      s_bin = 16 * tt + q;
-      s_before = static_cast<int>(c);
-    }
-    c += hb[q];
-  }
-  __syncthreads();
-  if (tt == 0) {
-    const int bin = s_bin;
-    const unsigned int cnt = atomicAdd(&w->hist[bin], 0u);
-    SelState n = s;
-    if (L.slot_phase) {
-      n.sprefix = (n.sshift == 32) ? static_cast<unsigned int>(bin) : ((n.sprefix << L.width) | bin);
-      n.sshift = L.shift;
-    } else {
-      n.kprefix = (n.kshift == 64) ? static_cast<unsigned long long>(bin)
-                                   : ((n.kprefix << L.width) | static_cast<unsigned long long>(bin));
-      n.kshift = L.shift;
-    }
-    n.below = s.below + s_before;
-    n.done = (static_cast<long>(n.below) + cnt <= kSelCap) ? 1 : 0;
-    n.ticket = 0u;
-    n.passes = s.passes + 1;
-    w->st = n;
-  }
 }
 
 // Every entry at or below the resolved prefix (at most kSelCap) into the
 // candidate list, one atomic per wave.
 __global__ void __launch_bounds__(256)
-k_rsel_collect(const double* __restrict__ logL, long N, SelWork* __restrict__ w) {
-  const SelState s = w->st;
+k_rsel_collect(const double* __restrict__ logL, long N, int m, SelWork* __restrict__ w) {
+  // the last digit's pick, if the digits ran out before the count fell to kSelCap
+  SelState s = w->slot[kSelLevels - 1];
+  if (!s.done) s = pick_digit<kRBins / 256>(s, kSelLevels - 1, m, w);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    SelState f = s;
+    f.passes = s.passes + 1;   // this pass
+    w->slot[kSelLevels] = f;
+  }
   const long stride = static_cast<long>(gridDim.x) * blockDim.x;
   const int lane = threadIdx.x & 63;
   const long n_up = (N + 63) / 64 * 64;   // whole waves run every iteration (ballots)
@@ -246,7 +261,7 @@ k_rsel_collect(const double* __restrict__ logL, long N, SelWork* __restrict__ w)
     const unsigned long long bal = __ballot(take);
     if (!bal) continue;
     int base = 0;
-    if (lane == 0) base = atomicAdd(&w->st.ncand, __popcll(bal));
+    if (lane == 0) base = atomicAdd(&w->ncand, __popcll(bal));
     base = __shfl(base, 0);
     if (take) {
       const int pos = base + __popcll(bal & ((1ull << lane) - 1ull));
@@ -256,7 +271,6 @@ k_rsel_collect(const double* __restrict__ logL, long N, SelWork* __restrict__ w)
       }
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&w->st.passes, 1);
 }
 
 // The candidates ranked by (key, index): one wave per candidate (grid-stride
@@ -265,7 +279,7 @@ k_rsel_collect(const double* __restrict__ logL, long N, SelWork* __restrict__ w)
 // with their indices are distinct, so the ranks are 0 .. n - 1.
 __global__ void __launch_bounds__(256)
 k_rsel_rank(int m, const SelWork* __restrict__ w, int* __restrict__ out, int* __restrict__ passes) {
-  const int n = min(w->st.ncand, kSelCap);
+  const int n = min(w->ncand, kSelCap);
   const int lane = threadIdx.x & 63;
   const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), nwaves = gridDim.x * (blockDim.x >> 6);
   for (int c = wave; c < n; c += nwaves) {
@@ -289,7 +303,7 @@ k_rsel_rank(int m, const SelWork* __restrict__ w, int* __restrict__ out, int* __
     }
     if (lane == 0 && before < m) out[before] = ic;
   }
-  if (passes && blockIdx.x == 0 && threadIdx.x == 0) *passes = w->st.passes;
+  if (passes && blockIdx.x == 0 && threadIdx.x == 0) *passes = w->slot[kSelLevels].passes;
 }
 
 size_t select_large_work_bytes() { return sel_work_bytes(); }
@@ -304,15 +318,15 @@ hipError_t launch_select_large(const double* logL, long N, int m, int* out, void
   const long npair = (N + 1) / 2;
   const int grid = static_cast<int>(std::min<long>(kSelGroups, std::max<long>(1, (npair + 2047) / 2048)));
   for (int l = 0; l < kSelLevels; ++l) {
-    hipLaunchKernelGGL(k_rsel_hist, dim3(grid), dim3(1024), 0, s, logL, N, l, w);
+    hipLaunchKernelGGL(k_rsel_hist, dim3(grid), dim3(1024), 0, s, logL, N, m, l, w);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rsel_reduce, dim3(kRBins / 64), dim3(256), 0, s, grid, m, l, w);
+    hipLaunchKernelGGL(k_rsel_reduce, dim3(kRBins / 64), dim3(256), 0, s, grid, l, w);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   const int cgrid = static_cast<int>(std::min<long>(2048, std::max<long>(1, (N + 255) / 256)));
-  hipLaunchKernelGGL(k_rsel_collect, dim3(cgrid), dim3(256), 0, s, logL, N, w);
+  hipLaunchKernelGGL(k_rsel_collect, dim3(cgrid), dim3(256), 0, s, logL, N, m, w);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_rsel_rank, dim3(256), dim3(256), 0, s, m, w, out, passes);
