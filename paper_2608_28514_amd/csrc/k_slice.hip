@@ -10,8 +10,9 @@
 //  * shrinking: lane s takes the s-th proposal of the shrink sequence that
 //    follows if all earlier proposals are rejected (each rejection moves the
 //    bracket end on the proposal's side of x, which does not depend on L), so
-//    one round tests kShrinkSpec consecutive proposals and a ballot picks the
-//    first one with L > L_W[j].
+//    one round tests consecutive proposals (kShrinkFirst in the first round,
+//    kShrinkSpec in each later one) and a ballot picks the first one with
+//    L > L_W[j].
 // Every draw is addressed by its counter (chain, step, iteration, slot), so
 // the result is the same as the one-proposal-at-a-time algorithm: the extra
 // speculative evaluations are simply not counted as likelihood calls.  All
@@ -26,6 +27,7 @@
 namespace ns {
 
 constexpr int kShrinkSpec = 16;
+constexpr int kShrinkFirst = 4;  // proposals of the first shrink round
 constexpr int kShrinkPre = 32;  // shrink uniforms drawn ahead per iteration
 constexpr int kDrawExtra = 1 + kShrinkPre;  // draw block: d direction entries, a0, U_0..U_31
 
@@ -204,12 +206,16 @@ k_slice(SliceParams p, int d_arg, int TH, LikDev lik, const T* __restrict__ u,
     T a = a0 - static_cast<T>(ka) * w;
     T b = b0 + static_cast<T>(kb) * w;
 
-    // ---- shrinking against the chain's own threshold
+    // ---- shrinking against the chain's own threshold: a first round of
+    // kShrinkFirst proposals (almost every chain accepts one of its first few,
+    // and the rejection recurrence below runs over the whole round), then
+    // rounds of kShrinkSpec
     bool accepted = false;
-    for (int s0 = 0; s0 < p.max_shrink && !accepted; s0 += kShrinkSpec) {
-      const int S = min(kShrinkSpec, p.max_shrink - s0);
+    auto shrink_round = [&](auto spec_c, int s0) {
+      constexpr int SPEC = decltype(spec_c)::value;
+      const int S = min(SPEC, p.max_shrink - s0);
       const T* U = blk + d + 1 + s0;
-      if (s0 + kShrinkSpec > kShrinkPre) {
+      if (s0 + SPEC > kShrinkPre) {
         // beyond the pre-drawn uniforms: draw this round's on demand
         if (lane < S) {
           const Draw2 du = uniform2(p.seed, kSlotShrink0 + s0 + lane, static_cast<uint32_t>(j), step, c3);
@@ -221,12 +227,12 @@ k_slice(SliceParams p, int d_arg, int TH, LikDev lik, const T* __restrict__ u,
       // the rejection recurrence is the same for every lane: run it once on
       // register copies of the uniforms; lane s takes proposal s, and the
       // bracket after S rejections is kept for the next round
-      T Ur[kShrinkSpec];
+      T Ur[SPEC];
 #pragma unroll
-      for (int q = 0; q < kShrinkSpec; ++q) Ur[q] = U[q];
+      for (int q = 0; q < SPEC; ++q) Ur[q] = U[q];
       T aa = a, bb = b, t = T(0), aS = a, bS = b;
 #pragma unroll
-      for (int q = 0; q < kShrinkSpec; ++q) {
+      for (int q = 0; q < SPEC; ++q) {
         const T tq = aa + Ur[q] * (bb - aa);
         if (tq < T(0)) aa = tq; else bb = tq;
         if (q == lane) t = tq;
@@ -264,7 +270,10 @@ k_slice(SliceParams p, int d_arg, int TH, LikDev lik, const T* __restrict__ u,
         a = aS;
         b = bS;
       }
-    }
+    };
+    if (p.max_shrink > 0) shrink_round(std::integral_constant<int, kShrinkFirst>{}, 0);
+    for (int s0 = kShrinkFirst; s0 < p.max_shrink && !accepted; s0 += kShrinkSpec)
+      shrink_round(std::integral_constant<int, kShrinkSpec>{}, s0);
     if (!accepted) n_sh += l0;
     __syncthreads();
   }
