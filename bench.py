@@ -50,8 +50,8 @@ BF16_PEAK = 2.5e15                                          # MI355X dense BF16 
 SLICE_TRAFFIC = {
     "sources": ["paper_2608_28514_amd/csrc/k_slice.hip", "paper_2608_28514_amd/csrc/ns_device.hpp",
                 "paper_2608_28514_amd/csrc/ns_internal.hpp"],
-    "sha256": "743572fe1fbbd04ec2c2d7e96af54e2862739df48c0930e54e588930cfea174a",
-    "fetch_kib": 306.95, "fetch_scale": 2.0, "write_kib": 18.30, "write_scale": 1.0,
+    "sha256": "f25b04853910a423c7b68b7fcf73d8aed303ab83ed738ecb825572fcbc8c59cb",
+    "fetch_kib": 325.30, "fetch_scale": 2.0, "write_kib": 18.31, "write_scale": 1.0,
 }
 
 

@@ -4,15 +4,20 @@
 // One wavefront per chain.  Every lane holds the chain's point and direction
 // in registers (coordinate loops unrolled to a compile-time bound on d); the
 // Cholesky factor lives in LDS; the 64 lanes evaluate the likelihood speculatively:
-//  * stepping out: lanes 0-31 test the left offsets a0 - k w, lanes 32-63 the
-//    right offsets b0 + k w, k = 32r .. 32r+31, in one round; a ballot finds
-//    the first offset that leaves the slice {L > L_W[0]} (or the box);
+//  * stepping out: a ballot over the lanes that test the left offsets
+//    a0 - k w and the right offsets b0 + k w finds, on each side, the first
+//    offset that leaves the slice {L > L_W[0]} (or the box);
 //  * shrinking: lane s takes the s-th proposal of the shrink sequence that
 //    follows if all earlier proposals are rejected (each rejection moves the
-//    bracket end on the proposal's side of x, which does not depend on L), so
-//    one round tests consecutive proposals (kShrinkFirst in the first round,
-//    kShrinkSpec in each later one) and a ballot picks the first one with
-//    L > L_W[j].
+//    bracket end on the proposal's side of x, which does not depend on L), and
+//    a ballot picks the first one with L > L_W[j];
+//  * an iteration's first round does both at once: 16 lanes step out
+//    (k < 8 per side) while the other 48 take the first 3 shrink proposals of
+//    each of the 16 brackets with ka, kb < 4.  When the bracket reached is one
+//    of them (and, in this workload, most are) its group is the first shrink
+//    round; otherwise stepping out continues 32 offsets per side a round and
+//    shrinking starts with a round of kShrinkFirst proposals.  Later shrink
+//    rounds test kShrinkSpec proposals.
 // Every draw is addressed by its counter (chain, step, iteration, slot), so
 // the result is the same as the one-proposal-at-a-time algorithm: the extra
 // speculative evaluations are simply not counted as likelihood calls.  All
@@ -28,8 +33,15 @@ namespace ns {
 
 constexpr int kShrinkSpec = 16;
 constexpr int kShrinkFirst = 4;  // proposals of the first shrink round
+// The first round of an iteration: stepping-out offsets k < kSoFirst on each
+// side, and the first kSpecQ shrink proposals of each bracket (ka, kb) with
+// ka, kb < kSpecK, one lane each.
+constexpr int kSoFirst = 8, kSpecK = 4, kSpecQ = 3;
+constexpr uint32_t kSoMask = (1u << kSoFirst) - 1u;
+static_assert(2 * kSoFirst + kSpecK * kSpecK * kSpecQ <= 64, "first round exceeds a wave");
 constexpr int kShrinkPre = 32;  // shrink uniforms drawn ahead per iteration
 constexpr int kDrawExtra = 1 + kShrinkPre;  // draw block: d direction entries, a0, U_0..U_31
+static_assert(kSpecQ <= kShrinkPre, "speculative shrink uniforms must be pre-drawn");
 
 template <typename LT>
 struct BoxOf;
@@ -166,11 +178,70 @@ k_slice(SliceParams p, int d_arg, int TH, LikDev lik, const T* __restrict__ u,
     for (int i = 0; i < DM; ++i)
       if (i < d) v[i] = blk[i];
 
-    // ---- stepping out against the batch-worst threshold L_W[0]
+    // ---- first round: stepping out against the batch-worst threshold L_W[0]
+    // over the offsets k < kSoFirst of both sides (lanes 0 .. 2 kSoFirst - 1),
+    // together with the first kSpecQ shrink proposals of every bracket the
+    // stepping out can end in with ka, kb < kSpecK (the other lanes, one
+    // group per (ka, kb)).  The group of the bracket actually reached serves
+    // as the first shrink round and the others are discarded: its points are
+    // the ones the one-proposal-at-a-time algorithm evaluates (same bracket
+    // arithmetic, same uniforms), and the discarded evaluations are not
+    // counted.
     const T a0 = blk[d];
     const T b0 = a0 + w;
     int ka = -1, kb = -1;
-    for (int base = 0; ka < 0 || kb < 0; base += 32) {
+    uint64_t fmp, fmi;       // first-round ballots: pass, in the box
+    double fl = -INFINITY;   // this lane's first-round likelihood
+    T foff = T(0);           // this lane's first-round offset along v
+    {
+      const bool so = lane < 2 * kSoFirst;
+      const int gl = lane - 2 * kSoFirst;
+      const int qq = so ? 0 : gl % kSpecQ;
+      bool active;
+      if (so) {
+        const int k = lane % kSoFirst;
+        active = k < p.max_stepout;
+        foff = lane < kSoFirst ? a0 - static_cast<T>(k) * w : b0 + static_cast<T>(k) * w;
+      } else {
+        const int grp = gl / kSpecQ;
+        T aa = a0 - static_cast<T>(grp / kSpecK) * w, bb = b0 + static_cast<T>(grp % kSpecK) * w;
+#pragma unroll
+        for (int q = 0; q < kSpecQ; ++q) {
+          const T tq = aa + blk[d + 1 + q] * (bb - aa);
+          if (tq < T(0)) aa = tq; else bb = tq;
+          if (q == qq) foff = tq;
+        }
+        active = qq < p.max_shrink;
+      }
+      bool inb = false, pass = false;
+      if (active) {
+        inb = reg_line_in_box<T, DM>(x, v, foff, d);
+        if (inb) fl = clean_logL(LikAt<LT>::template eval_theta<DM, RegLineTheta<T, LT, DM>, EXACT, KIND>(lik, RegLineTheta<T, LT, DM>{x, v, foff, blo, bsp}));
+        pass = fl > (so ? tau_e : tau_j);
+      }
+      fmp = __ballot(pass);
+      fmi = __ballot(inb);
+      const uint64_t mo = __ballot(so && active && !inb);
+      for (int side = 0; side < 2; ++side) {
+        int& kk = side == 0 ? ka : kb;
+        const uint32_t bits = static_cast<uint32_t>(fmp >> (kSoFirst * side)) & kSoMask;
+        const uint32_t obits = static_cast<uint32_t>(mo >> (kSoFirst * side)) & kSoMask;
+        const int kf = (bits == kSoMask) ? kSoFirst : __builtin_ctz(~bits);
+        if (kf >= p.max_stepout) {                  // cap: k == E_max is never evaluated
+          n_evals += l0 * p.max_stepout;
+          n_so += l0;
+          kk = p.max_stepout;
+        } else if (kf < kSoFirst) {
+          n_evals += l0 * (kf + (((obits >> kf) & 1u) ? 0 : 1));
+          n_oob += l0 * static_cast<int>((obits >> kf) & 1u);
+          kk = kf;
+        } else {
+          n_evals += l0 * kSoFirst;
+        }
+      }
+    }
+    // further stepping out on a side the first round left open
+    for (int base = kSoFirst; ka < 0 || kb < 0; base += 32) {
       const bool left = lane < 32;
       const int k = base + (lane & 31);
       const bool active = (left ? ka < 0 : kb < 0) && k < p.max_stepout;
@@ -271,8 +342,53 @@ k_slice(SliceParams p, int d_arg, int TH, LikDev lik, const T* __restrict__ u,
         b = bS;
       }
     };
-    if (p.max_shrink > 0) shrink_round(std::integral_constant<int, kShrinkFirst>{}, 0);
-    for (int s0 = kShrinkFirst; s0 < p.max_shrink && !accepted; s0 += kShrinkSpec)
+    // the first round's group for (ka, kb), when there is one, is the first
+    // shrink round
+    const bool spec = ka < kSpecK && kb < kSpecK && p.max_shrink > 0;
+    int s_next = 0;
+    if (spec) {
+      const int g = 2 * kSoFirst + (ka * kSpecK + kb) * kSpecQ;
+      const int S = min(kSpecQ, p.max_shrink);
+      const uint32_t gm = (1u << S) - 1u;
+      const uint32_t gp = static_cast<uint32_t>(fmp >> g) & gm;
+      const uint32_t gi = static_cast<uint32_t>(fmi >> g) & gm;
+      const int upto = gp ? __builtin_ctz(gp) : S - 1;   // last proposal taken
+      const uint32_t taken = (2u << upto) - 1u;
+      n_evals += l0 * __popc(gi & taken);
+      n_oob += l0 * ((upto + 1) - __popc(gi & taken));
+      const int qs = lane - g;
+      if (last && qs >= 0 && qs <= upto && qs < TH - 1) {
+        hist_logL[static_cast<long>(qs) * m + j] = fl;
+        T* hu = hist_u + (static_cast<long>(j) * TH + qs) * d;
+#pragma unroll
+        for (int i = 0; i < DM; ++i)
+          if (i < d) hu[i] = x[i] + foff * v[i];
+      }
+      if (last) hn = l0 * min(upto + 1, TH - 1);
+      if (gp) {
+        accepted = true;
+        lx = __shfl(fl, g + upto);
+        const T tacc = __shfl(foff, g + upto);
+#pragma unroll
+        for (int i = 0; i < DM; ++i) x[i] = x[i] + tacc * v[i];
+      } else {
+        // the bracket after S rejections, as the group's lanes formed it
+        T aa = a, bb = b;
+#pragma unroll
+        for (int q = 0; q < kSpecQ; ++q)
+          if (q < S) {
+            const T tq = aa + blk[d + 1 + q] * (bb - aa);
+            if (tq < T(0)) aa = tq; else bb = tq;
+          }
+        a = aa;
+        b = bb;
+        s_next = S;
+      }
+    } else if (p.max_shrink > 0) {
+      shrink_round(std::integral_constant<int, kShrinkFirst>{}, 0);
+      s_next = kShrinkFirst;
+    }
+    for (int s0 = s_next; s0 < p.max_shrink && !accepted; s0 += kShrinkSpec)
       shrink_round(std::integral_constant<int, kShrinkSpec>{}, s0);
     if (!accepted) n_sh += l0;
     __syncthreads();
