@@ -244,6 +244,21 @@ ns_status ns_cluster_split(const float* d_u, int64_t N, int d, int iters, double
 ns_status ns_select_worst(const double* d_logL, int64_t N, int m, int* d_slots, void* d_work, int* d_passes,
                           void* hip_stream);
 
+/* The same selection as ns_select_worst, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): no workspace argument, and no allocation in the
+ * call.  The workspace is a static device array of ns_select_worst_work_bytes()
+ * bytes (about 8.5 MB) per device, held until the process ends; its address
+ * is looked up on the first call on a device.  Limits: 1 <= m <= min(N, 4096),
+ * N <= 2^31 - 1 (NS_EINVAL beyond, with the reason in ns_last_error(NULL)).
+ * d_logL (16-byte aligned), d_slots and d_passes (may be NULL) as in
+ * ns_select_worst, on the current device; hip_stream (NULL: the default
+ * stream) must belong to the current device.  All calls on one device share
+ * the workspace: calls that overlap in time on one device race, and the
+ * caller must order them (one stream, or events). */
+ns_status ns_select_worst_noalloc(const double* d_logL, int64_t N, int m, int* d_slots, int* d_passes,
+                                  void* hip_stream);
+
 /* Algorithms 1 and 2 on explicit arrays (device): d_wlogL (m, ascending),
  * d_nlogL (m), d_P (m thresholds), d_hist (T*m, row t, column = chain),
  * d_hist_n (m).  Outputs (device, m each): accepted and rejected entries as

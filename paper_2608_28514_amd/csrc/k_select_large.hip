@@ -14,6 +14,7 @@
 // candidate's rank among them by (key, index) places the first m indices.
 // The result equals a stable sort of (canon(logL), index).
 #include <algorithm>
+#include <mutex>
 #include "ns_device.hpp"
 #include "ns_select_large.hpp"
 
@@ -307,6 +308,35 @@ k_rsel_rank(int m, const SelWork* __restrict__ w, int* __restrict__ out, int* __
 }
 
 size_t select_large_work_bytes() { return sel_work_bytes(); }
+
+// Workspace of the allocation-free selection: one SelWork per device, held
+// until the process ends.  In host code `scratch` only names the symbol: its
+// device address, different on every device, comes from hipGetSymbolAddress
+// (made once per device, with that device current) and is the only handle
+// host code passes on.  Every call on a device shares this memory, so calls
+// that overlap in time on one device race; k_rsel_init clears what the
+// passes read before they write it.
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[sizeof(SelWork)];
+
+hipError_t select_large_static_work(void** out) {
+  static std::mutex mu;
+  static void* ptr[kScratchDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p || reinterpret_cast<uintptr_t>(p) % 256 != 0) return hipErrorInvalidSymbol;
+    ptr[dev] = p;
+  }
+  *out = ptr[dev];
+  return hipSuccess;
+}
 
 hipError_t launch_select_large(const double* logL, long N, int m, int* out, void* work, int* passes,
                                hipStream_t s) {

@@ -1157,6 +1157,30 @@ ns_status ns_select_worst(const double* d_logL, int64_t N, int m, int* d_slots, 
   return NS_OK;
 }
 
+ns_status ns_select_worst_noalloc(const double* d_logL, int64_t N, int m, int* d_slots, int* d_passes,
+                                  void* hip_stream) {
+  ns_ctx* c = nullptr;
+  if (!d_logL || !d_slots || N < 1 || N > 2147483647LL || m < 1 || m > N)
+    return inval(nullptr, "ns_select_worst_noalloc: bad arguments");
+  if (m > 4096)
+    return inval(nullptr, "ns_select_worst_noalloc: m exceeds 4096, the most the static workspace holds");
+  if (reinterpret_cast<uintptr_t>(d_logL) % 16 != 0)
+    return inval(nullptr, "ns_select_worst_noalloc: d_logL must be 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (s) {
+    int cur = -1;
+    hipDevice_t sdev = -1;
+    NS_TRY(hipGetDevice(&cur));
+    NS_TRY(hipStreamGetDevice(s, &sdev));
+    if (sdev != cur)
+      return inval(nullptr, "ns_select_worst_noalloc: the stream must belong to the current device");
+  }
+  void* work = nullptr;
+  NS_TRY(select_large_static_work(&work));
+  NS_TRY(launch_select_large(d_logL, static_cast<long>(N), m, d_slots, work, d_passes, s));
+  return NS_OK;
+}
+
 ns_status ns_select_order(const double* d_logL, int N, int* d_order, void* hip_stream) {
   ns_ctx* c = nullptr;
   if (!d_logL || !d_order || N < 1 || N > 8192) return inval(nullptr, "ns_select_order: bad arguments");

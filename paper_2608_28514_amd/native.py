@@ -108,6 +108,7 @@ def lib():
             "ns_select_order": [vp, C.c_int, vp, vp],
             "ns_select_worst_work_bytes": [],
             "ns_select_worst": [vp, C.c_int64, C.c_int, vp, vp, vp, vp],
+            "ns_select_worst_noalloc": [vp, C.c_int64, C.c_int, vp, vp, vp],
             "ns_cluster_split_work_bytes": [],
             "ns_cluster_split": [vp, C.c_int64, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp],
             "ns_correct_batch": [C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp,
@@ -305,6 +306,14 @@ def ns_select_worst(d_logL, m, d_slots, d_work, d_passes=None, stream=None):
     _check(lib().ns_select_worst(_ptr(d_logL), int(d_logL.numel()), int(m), _ptr(d_slots), _ptr(d_work),
                                  _ptr(d_passes) if d_passes is not None else None, _stream(stream)),
            None, "ns_select_worst")
+
+
+def ns_select_worst_noalloc(d_logL, m, d_slots, d_passes=None, stream=None):
+    """ns_select_worst without a workspace argument (the library's static
+    per-device workspace; nothing is allocated)."""
+    _check(lib().ns_select_worst_noalloc(_ptr(d_logL), int(d_logL.numel()), int(m), _ptr(d_slots),
+                                         _ptr(d_passes) if d_passes is not None else None, _stream(stream)),
+           None, "ns_select_worst_noalloc")
 
 
 def ns_select_worst_work_bytes():
