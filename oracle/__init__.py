@@ -93,6 +93,10 @@ def lib():
         L.orc_get_counters.argtypes = [C.c_void_p, _lp]
         L.orc_get_state.argtypes = [C.c_void_p, _dp, _dp, _lp, _ip]
         L.orc_get_last_batch.argtypes = [C.c_void_p, _ip, _dp, _dp, _dp, _lp, _dp, _dp, _ip]
+        L.orc_get_last_brackets.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _ip, _ip]
+        L.orc_get_last_brackets.restype = None
+        L.orc_slice_direction.argtypes = [C.c_uint64, C.c_int, C.c_uint32, C.c_int, _dp, C.c_int, _dp]
+        L.orc_slice_direction.restype = None
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_get_threads.restype = C.c_int
         L.orc_mlp_forward.argtypes = [C.c_int, _ip, _dp, _dp, C.c_int, _dp, C.c_long, _dp, _dp]
@@ -227,6 +231,25 @@ def cluster(u, depth, p=0.3, nmin=None, iters=20, eps=1e-8):
     return tree_to_dict(t), labels
 
 
+def make_tree(d, depth, accepted, centre):
+    """A hand-built cluster tree (heap indexed, 2^(depth+1) - 1 nodes) with the
+    given accepted flags and centres (n_nodes x d), for orc_nearest_centre."""
+    t = OrcTree()
+    t.depth, t.d = int(depth), int(d)
+    t.n_nodes = (1 << (depth + 1)) - 1
+    cen = np.asarray(centre, dtype=np.float64)
+    for n in range(t.n_nodes):
+        t.accepted[n] = int(accepted[n])
+        for i in range(d):
+            t.centre[n * MAXD + i] = float(cen[n, i])
+    return t
+
+
+def nearest_centre(tree, x):
+    """Accepted node whose centre is nearest to x (Sec. 2.1, last paragraph)."""
+    return int(lib().orc_nearest_centre(C.byref(tree), _d(_f64(x))))
+
+
 def two_means(u, iters=20):
     """k-means split (k = 2) of all points u (n x d) as one tree node: (ca, cb, side)."""
     u = _f64(u)
@@ -335,6 +358,17 @@ class Oracle:
         lib().orc_get_state(self.ctx, C.byref(a), C.byref(b), C.byref(s), C.byref(dn))
         return {"logZ_run": a.value, "A_run": b.value, "step": s.value, "done": bool(dn.value)}
 
+    def last_brackets(self, m):
+        """Per chain of the last step: start point x0 and direction v of the
+        last slice iteration, its stepped-out bracket [a, b] and the steps ka,
+        kb taken on each side (before shrinking)."""
+        d = self.d
+        out = {"x0": np.zeros((m, d)), "v": np.zeros((m, d)), "a": np.zeros(m), "b": np.zeros(m),
+               "ka": np.zeros(m, dtype=np.int32), "kb": np.zeros(m, dtype=np.int32)}
+        lib().orc_get_last_brackets(self.ctx, _d(out["x0"]), _d(out["v"]), _d(out["a"]), _d(out["b"]),
+                                    _i(out["ka"]), _i(out["kb"]))
+        return out
+
     def last_batch(self, m):
         T, d = self.T, self.d
         out = {"seeds": np.zeros(m, dtype=np.int32), "tau": np.zeros(m), "new_u": np.zeros((m, d)),
@@ -345,6 +379,18 @@ class Oracle:
                                  _d(out["new_logL"]), out["chain_evals"].ctypes.data_as(_lp),
                                  _d(out["hist_logL"]), _d(out["hist_u"]), _i(out["hist_n"]))
         return out
+
+
+def slice_direction(seed, chain, step, it, L):
+    """Direction v = L zhat of slice iteration `it` of a chain (Sec. 2.2); L is
+    a lower-triangular d x d Cholesky factor."""
+    L = _f64(L)
+    d = L.shape[0]
+    Lp = np.zeros((MAXD, MAXD))
+    Lp[:d, :d] = L
+    v = np.zeros(d)
+    lib().orc_slice_direction(int(seed), int(chain), int(step), int(it), _d(Lp), d, _d(v))
+    return v
 
 
 def set_threads(n):

@@ -18,10 +18,12 @@
  * eps * max(lambda_max, 1e-300) and the covariance is only rebuilt from the
  * clipped spectrum when some eigenvalue was actually raised.
  *
- * Pins: tests/test_oracle_cluster.py (brute-force optimal 2-partition on tiny
- * sets, reconstruction A = Q diag(l) Q^T, L L^T = Sigma', rank-deficient input
- * gets lambda_min = eps * lambda_max, separated blobs split, one Gaussian and a
- * uniform box do not).
+ * Pins: tests/test_oracle_select_cluster.py (brute-force optimal 2-partition
+ * on tiny sets, reconstruction A = Q diag(l) Q^T, L L^T = Sigma',
+ * rank-deficient input gets lambda_min = eps * lambda_max, separated blobs
+ * split, one Gaussian and a uniform box do not) and tests/test_oracle_pins.py
+ * (nearest accepted centre on a hand-built tree and during a run, lower node
+ * id on a tie).
  */
 #include <math.h>
 #include <stdlib.h>

@@ -21,6 +21,7 @@
  */
 #include <math.h>
 #include <stdlib.h>
+#include <omp.h>
 #include "ns_oracle.h"
 
 static double lik_mixture(const orc_lik* L, const double* th) {
@@ -67,6 +68,9 @@ static double lik_shell(const orc_lik* L, const double* th) {
   return -0.5 * r * r;
 }
 
+/* Layer l: z_j = (sum_i a_i W_ij) + b_j, the sum over inputs i in ascending
+ * order for every output j.  The loop runs over inputs on the outside and
+ * outputs inside (one accumulator per output), so W is read row by row. */
 static double lik_mlp(const orc_lik* L, const double* th) {
   int maxw = 0;
   for (int l = 0; l <= L->n_layers; ++l) if (L->widths[l] > maxw) maxw = L->widths[l];
@@ -77,10 +81,14 @@ static double lik_mlp(const orc_lik* L, const double* th) {
   const double* bias = L->biases;
   for (int l = 0; l < L->n_layers; ++l) {
     int nin = L->widths[l], nout = L->widths[l + 1];
+    for (int j = 0; j < nout; ++j) b[j] = 0.0;
+    for (int i = 0; i < nin; ++i) {
+      const double ai = a[i];
+      const double* Wi = W + (long)i * nout;
+      for (int j = 0; j < nout; ++j) b[j] += ai * Wi[j];
+    }
     for (int j = 0; j < nout; ++j) {
-      double s = 0.0;
-      for (int i = 0; i < nin; ++i) s += a[i] * W[(long)i * nout + j];
-      s += bias[j];
+      double s = b[j] + bias[j];
       b[j] = (l + 1 < L->n_layers) ? tanh(s) : s;
     }
     W += (long)nin * nout;
@@ -111,8 +119,11 @@ static double loglike_one(const orc_lik* L, const double* th) {
 void orc_loglike(const orc_lik* L, const double* lo, const double* hi,
                  const double* u, long n, double* out) {
   const int d = L->d;
-  double th[ORC_MAXD];
+  /* points are independent: spread them over the oracle's threads when not
+     already inside a parallel region (the chains of a step) */
+#pragma omp parallel for num_threads(orc_get_threads()) schedule(dynamic, 16) if (n > 1 && !omp_in_parallel())
   for (long k = 0; k < n; ++k) {
+    double th[ORC_MAXD];
     const double* x = u + k * d;
     int inbox = 1;
     for (int i = 0; i < d; ++i) {

@@ -9,8 +9,9 @@
  * `acts` keeps every layer's pre-activation z (B x widths[l+1], layers
  * concatenated) for the backward pass.
  *
- * Pins: tests/test_oracle_mlp.py checks the backward pass against FP64 central
- * finite differences of the forward pass, and the forward pass against a plain
+ * Pins: tests/test_oracle_mlp_quadrature.py checks the backward pass against
+ * FP64 central finite differences of the forward pass;
+ * tests/test_oracle_likelihood.py checks the forward pass against a plain
  * numpy matrix chain.
  */
 #include <math.h>

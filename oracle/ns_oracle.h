@@ -155,6 +155,13 @@ void orc_get_state(const orc_ctx* c, double* logZ_run, double* A_run, long* step
 /* last step: seeds, thresholds, new points / logL / chain evals, history */
 void orc_get_last_batch(const orc_ctx* c, int* seeds, double* tau, double* new_u, double* new_logL,
                         long* chain_evals, double* hist_logL, double* hist_u, int* hist_n);
+/* last step, per chain: the start point x0 and direction v of the last slice
+   iteration and its stepped-out bracket [a, b] (ka, kb steps per side), before
+   shrinking (test hooks) */
+void orc_get_last_brackets(const orc_ctx* c, double* x0, double* v, double* a, double* b, int* ka, int* kb);
+/* direction v = L zhat of slice iteration `it` of chain j (Sec. 2.2); L lower
+   triangular, row stride ORC_MAXD */
+void orc_slice_direction(uint64_t seed, int j, uint32_t step, int it, const double* L, int d, double* v);
 void orc_set_threads(int n);
 int orc_get_threads(void);
 

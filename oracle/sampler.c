@@ -35,18 +35,28 @@
  *  - accepted new points fill the slots of rejected worst points in the order
  *    of W; revived worst points keep their slots.
  *
- * Pins: tests/test_oracle_sampler.py (worked examples of Algorithms 1 and 2,
- * constant likelihood gives log Z = c exactly, log X_i = -i/N, monotone dead
- * likelihoods under sorting corrections, m = 1 identical for every correction,
- * closed-form / quadrature log Z of Gaussian, mixture and Rosenbrock runs,
- * uniformity of slice output inside a spherical constraint, exact replay of
- * the history relaxation).
+ * Pins: tests/test_oracle_sampler.py and tests/test_oracle_correct.py (worked
+ * examples of Algorithms 1 and 2, constant likelihood gives log Z = c exactly,
+ * log X_i = -i/N, monotone dead likelihoods under sorting corrections, m = 1
+ * identical for every correction, closed-form log Z of Gaussian and mixture
+ * runs, uniformity of slice output inside a spherical constraint, exact replay
+ * of the history relaxation) and tests/test_oracle_pins.py (brackets stepped
+ * out against L_W[0] while shrinking uses L_W[j], seed ranks uniform above
+ * W[j], v = L_c zhat with zhat uniform on the sphere, 2-d Rosenbrock evidence
+ * against quadrature to 3 standard errors, sequential and batched).
  */
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
 #include <omp.h>
 #include "ns_oracle.h"
+
+/* bracket of the last slice iteration of a chain, as stepped out (test hooks) */
+typedef struct {
+  double x0[ORC_MAXD], v[ORC_MAXD];
+  double a, b;
+  int ka, kb;
+} last_bracket;
 
 static int g_threads = 1;
 void orc_set_threads(int n) { g_threads = n > 0 ? n : 1; }
@@ -104,6 +114,7 @@ struct orc_ctx {
   double* hist_logL;
   double* hist_u;
   int* hist_n;
+  last_bracket* brk;
   int cap_m;
 };
 
@@ -187,7 +198,7 @@ void orc_free(orc_ctx* c) {
   free(c->u); free(c->logL); free(c->label);
   free(c->dead_u); free(c->dead_logL);
   free(c->seeds); free(c->tau); free(c->new_u); free(c->new_logL); free(c->chain_evals);
-  free(c->hist_logL); free(c->hist_u); free(c->hist_n);
+  free(c->hist_logL); free(c->hist_u); free(c->hist_n); free(c->brk);
   free(c);
 }
 
@@ -217,14 +228,40 @@ static int inbox(int d, const double* y) {
   return 1;
 }
 
+/* Direction of slice iteration `it` of chain j in step `step` (Sec. 2.2): an
+ * isotropic direction zhat (Box-Muller normals, normalised), transformed with
+ * the lower-triangular Cholesky factor L (row stride ORC_MAXD) of the chain's
+ * cluster covariance: v = L zhat. */
+void orc_slice_direction(uint64_t seed, int j, uint32_t step, int it, const double* L, int d, double* v) {
+  const uint32_t c3 = ((uint32_t)ORC_STREAM_SLICE << 24) | (uint32_t)it;
+  double z[ORC_MAXD];
+  for (int p = 0; 2 * p < d; ++p) {
+    double uu[2];
+    orc_uniform2(seed, ORC_SLOT_DIR0 + (uint32_t)p, (uint32_t)j, step, c3, uu);
+    double r = sqrt(-2.0 * log(uu[0]));
+    double ang = 6.283185307179586 * uu[1];
+    z[2 * p] = r * cos(ang);
+    if (2 * p + 1 < d) z[2 * p + 1] = r * sin(ang);
+  }
+  double nrm = 0.0;
+  for (int i = 0; i < d; ++i) nrm += z[i] * z[i];
+  nrm = sqrt(nrm);
+  for (int i = 0; i < d; ++i) z[i] = z[i] / nrm;
+  for (int i = 0; i < d; ++i) {
+    double s = 0.0;
+    for (int k = 0; k <= i; ++k) s += L[i * ORC_MAXD + k] * z[k];
+    v[i] = s;
+  }
+}
+
 static void slice_chain(orc_ctx* c, int j, int seed_slot, double tau_j, double tau_e,
                         double* xout, double* lout, double* hl, double* hu, int* hn,
-                        chain_stats* st) {
+                        chain_stats* st, last_bracket* lb) {
   const int d = c->d, n_iter = c->cfg.slice_steps_per_dim * d, T = c->cfg.hist_cap;
   const double w = c->cfg.step_width;
   const uint64_t seed = c->cfg.seed;
   const uint32_t step = (uint32_t)c->step;
-  double x[ORC_MAXD], y[ORC_MAXD], z[ORC_MAXD], v[ORC_MAXD];
+  double x[ORC_MAXD], y[ORC_MAXD], v[ORC_MAXD];
   memcpy(x, c->u + (long)seed_slot * d, sizeof(double) * d);
   double lx = c->logL[seed_slot];
   const double* L = c->tree.chol + (long)c->label[seed_slot] * ORC_MAXD * ORC_MAXD;
@@ -232,24 +269,7 @@ static void slice_chain(orc_ctx* c, int j, int seed_slot, double tau_j, double t
   for (int it = 0; it < n_iter; ++it) {
     const uint32_t c3 = ((uint32_t)ORC_STREAM_SLICE << 24) | (uint32_t)it;
     const int last = (it == n_iter - 1);
-    /* isotropic direction, transformed with the cluster's Cholesky factor */
-    for (int p = 0; 2 * p < d; ++p) {
-      double uu[2];
-      orc_uniform2(seed, ORC_SLOT_DIR0 + (uint32_t)p, (uint32_t)j, step, c3, uu);
-      double r = sqrt(-2.0 * log(uu[0]));
-      double ang = 6.283185307179586 * uu[1];
-      z[2 * p] = r * cos(ang);
-      if (2 * p + 1 < d) z[2 * p + 1] = r * sin(ang);
-    }
-    double nrm = 0.0;
-    for (int i = 0; i < d; ++i) nrm += z[i] * z[i];
-    nrm = sqrt(nrm);
-    for (int i = 0; i < d; ++i) z[i] = z[i] / nrm;
-    for (int i = 0; i < d; ++i) {
-      double s = 0.0;
-      for (int k = 0; k <= i; ++k) s += L[i * ORC_MAXD + k] * z[k];
-      v[i] = s;
-    }
+    orc_slice_direction(seed, j, step, it, L, d, v);
     /* stepping out against the batch-worst threshold */
     double uu[2];
     orc_uniform2(seed, ORC_SLOT_STEPOUT, (uint32_t)j, step, c3, uu);
@@ -279,6 +299,11 @@ static void slice_chain(orc_ctx* c, int j, int seed_slot, double tau_j, double t
     }
     double a = a0 - (double)ka * w;
     double b = b0 + (double)kb * w;
+    if (last) {
+      memcpy(lb->x0, x, sizeof(double) * d);
+      memcpy(lb->v, v, sizeof(double) * d);
+      lb->a = a; lb->b = b; lb->ka = ka; lb->kb = kb;
+    }
     /* shrinking against the chain's own threshold */
     int acc = 0;
     for (int s = 0; s < c->cfg.max_shrink; ++s) {
@@ -422,7 +447,7 @@ static void ensure_batch(orc_ctx* c, int m) {
   if (m <= c->cap_m) return;
   const int d = c->d, T = c->cfg.hist_cap;
   free(c->seeds); free(c->tau); free(c->new_u); free(c->new_logL); free(c->chain_evals);
-  free(c->hist_logL); free(c->hist_u); free(c->hist_n);
+  free(c->hist_logL); free(c->hist_u); free(c->hist_n); free(c->brk);
   c->seeds = (int*)malloc(sizeof(int) * m);
   c->tau = (double*)malloc(sizeof(double) * m);
   c->new_u = (double*)malloc(sizeof(double) * m * d);
@@ -431,6 +456,7 @@ static void ensure_batch(orc_ctx* c, int m) {
   c->hist_logL = (double*)malloc(sizeof(double) * (long)T * m);
   c->hist_u = (double*)malloc(sizeof(double) * (long)T * m * d);
   c->hist_n = (int*)malloc(sizeof(int) * m);
+  c->brk = (last_bracket*)calloc(m, sizeof(last_bracket));
   c->cap_m = m;
 }
 
@@ -466,7 +492,7 @@ int orc_step(orc_ctx* c, int m) {
     double* hl = hist_tmp + (long)j * T;
     for (int t = 0; t < T; ++t) hl[t] = -INFINITY;
     slice_chain(c, j, c->seeds[j], c->tau[j], tau_e, c->new_u + (long)j * d, &c->new_logL[j],
-                hl, c->hist_u + (long)j * T * d, &c->hist_n[j], &st[j]);
+                hl, c->hist_u + (long)j * T * d, &c->hist_n[j], &st[j], &c->brk[j]);
   }
   for (int j = 0; j < m; ++j) {
     for (int t = 0; t < T; ++t) c->hist_logL[(long)t * m + j] = hist_tmp[(long)j * T + t];
@@ -599,4 +625,17 @@ void orc_get_last_batch(const orc_ctx* c, int* seeds, double* tau, double* new_u
   if (hist_logL) memcpy(hist_logL, c->hist_logL, sizeof(double) * (long)T * m);
   if (hist_u) memcpy(hist_u, c->hist_u, sizeof(double) * (long)T * m * d);
   if (hist_n) memcpy(hist_n, c->hist_n, sizeof(int) * m);
+}
+
+void orc_get_last_brackets(const orc_ctx* c, double* x0, double* v, double* a, double* b, int* ka, int* kb) {
+  const int m = c->last_m, d = c->d;
+  for (int j = 0; j < m; ++j) {
+    const last_bracket* lb = &c->brk[j];
+    if (x0) memcpy(x0 + (long)j * d, lb->x0, sizeof(double) * d);
+    if (v) memcpy(v + (long)j * d, lb->v, sizeof(double) * d);
+    if (a) a[j] = lb->a;
+    if (b) b[j] = lb->b;
+    if (ka) ka[j] = lb->ka;
+    if (kb) kb[j] = lb->kb;
+  }
 }

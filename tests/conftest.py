@@ -1,6 +1,10 @@
 import os
 import sys
 
+# the oracle's OpenMP threads sleep instead of spinning while they wait, so
+# tests stay fast on a host that is busy with other work
+os.environ.setdefault("OMP_WAIT_POLICY", "passive")
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
