@@ -1,26 +1,30 @@
 """Benchmark of the batched nested sampler on one MI355X.
 
-A "step" here is one complete nested-sampling run of the benchmark workload
-(init -> batched updates until the stopping rule -> final evidence), which
-passes through every stage of the hot path: selection, clustering, slice
-sampling with the vectorised likelihood, batch correction and evidence.
+Default workload (the largest of the five): the 27-d emulator likelihood, a
+random-weight 27-512-512-512-1024 tanh network with a diagonal chi^2 against
+seeded data (stand-in for the cosmological emulator of Sec. 5), prior
+[0,1]^27, N_live = 4000, batch m = 400, FP32 sampler state, cluster tree depth
+1, 5 d slice iterations, network layers on bfloat16 MFMA with the activations
+split in three bfloat16 terms and FP32 accumulation, chi^2 in FP64.
 
-Default workload: 10-d Rosenbrock chain, prior [-5,5]^10, N_live = 500,
-batch m = 50, FP64 likelihood, FP32 sampler state, cluster tree depth 2,
-5 d slice iterations, stop at remaining-evidence fraction 1e-3.
+A "step" is one ns_step_batch(m): select the m worst, m slice-sampling chains
+with the batched network likelihood, cluster tree, batch correction, live and
+dead update, evidence.  One complete run (seed 0) is made: `warmup` steps,
+then exactly `steps` timed steps (HIP-event timing of the dense layers on the
+context's stream), then the rest of the run untimed.  value = live-point
+updates per second over the timed steps (inputs and live set resident on the
+device).  The run's log Z is checked against the stored FP64 reference of this
+likelihood (importance-sampling integral computed by the oracle) within 2
+combined sigma, sigma = sqrt(H/N); the line says whether the gate passed.
+The same run with the learned pre-screen is reported beside it.
 
-value = live-point updates per second over the timed runs (dead rows / wall
-time of ns_run, inputs and live set already on the device); evaluations per
-second are reported beside it.  Every run's log Z is checked against the
-oracle's mean on the same workload (|dlogZ| < 2 combined sigma) and against
-the transfer-matrix quadrature value.
+cpu_baseline: the FP64 oracle (plain C, OpenMP over chains) on the same
+likelihood and live-set size: one batched step from the prior live set, on
+all host threads (up to 16) and on one thread.
 
-Other modes (one JSON line each): --workload 4 / 5 (27-d emulator runs, with
---prec f32|bf16x3 and --no-screen), --lik-sweep (the batched emulator
-likelihood at 200 ... 25,600 rows per call), --select-sweep (worst-1000
-selection at N = 2^16 ... 2^24), --cluster-sweep (one cluster-tree node at
-N = 2^16 ... 2^24) and --train-sweep (a dense network's training step at
-batch 1,024 ... 65,536).
+Other modes (one JSON line each): --workload 2 (10-d Rosenbrock, N = 500,
+m = 50; complete runs), --workload 4 (27-d emulator, N = 2000, m = 200),
+--no-screen-run, --lik-sweep, --select-sweep, --cluster-sweep, --train-sweep.
 """
 import argparse
 import json
@@ -31,81 +35,69 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
-ROSEN_QUADRATURE_LOGZ = -43.10836   # transfer-matrix quadrature of the 10-d chain on [-5,5]^10
 FP64_PEAK = 78.6e12                 # MI355X FP64 vector FLOP/s
-
-
-EMU_FLOPS = 2 * (27 * 512 + 512 * 512 * 2 + 512 * 1024)   # one emulator evaluation
-# MFMA work actually issued per row by the split-bfloat16 path: nine products of
-# 32 (padded) inputs in the first layer, three activation terms afterwards
+FP32_PEAK = 157.3e12                # MI355X FP32 vector FLOP/s
+BF16_PEAK = 2.5e15                  # MI355X dense BF16 MFMA FLOP/s
+EMU_FLOPS = 2 * (27 * 512 + 512 * 512 * 2 + 512 * 1024)   # one emulator evaluation: 2,124,800
+# MFMA work issued per row by the split-bfloat16 path: nine products of 32
+# (padded) inputs in the first layer, three activation terms afterwards
 EMU_MFMA_ISSUED = 2 * (9 * 32 * 512 + 3 * (512 * 512 * 2 + 512 * 1024))
-BF16_PEAK = 2.5e15                                          # MI355X dense BF16 MFMA FLOP/s
-
-# HBM bytes per launch of the fused slice kernel on this workload, from two
-# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled
-# by what the counter reads for a 256 MiB device copy (FETCH_SIZE reads half the
-# bytes moved: x2.0; WRITE_SIZE: x1.0).  Valid only for the kernel sources they
-# were taken with: reported as null once those sources change.
-SLICE_TRAFFIC = {
-    "sources": ["paper_2608_28514_amd/csrc/k_slice.hip", "paper_2608_28514_amd/csrc/ns_device.hpp",
-                "paper_2608_28514_amd/csrc/ns_internal.hpp"],
-    "sha256": "f25b04853910a423c7b68b7fcf73d8aed303ab83ed738ecb825572fcbc8c59cb",
-    "fetch_kib": 325.30, "fetch_scale": 2.0, "write_kib": 18.31, "write_scale": 1.0,
-}
+METRIC = "live-point updates/s at |dlogZ|<2sigma vs oracle, 1 GPU"
 
 
-def slice_traffic_bytes():
-    import hashlib
-    here = os.path.dirname(os.path.abspath(__file__))
-    h = hashlib.sha256()
-    for f in SLICE_TRAFFIC["sources"]:
-        with open(os.path.join(here, f), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest() != SLICE_TRAFFIC["sha256"]:
-        return None
-    t = SLICE_TRAFFIC
-    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
-FP32_PEAK = 157.3e12                                        # MI355X FP32 vector FLOP/s
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def rosen_flops_per_eval(d):
-    # theta = lo + span*u (2d) + 9 terms of 8 flops + proposal x + t v (2d)
-    return 2 * d + 8 * (d - 1) + 2 * d
+def host_threads():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--m", type=int, default=None)
-    ap.add_argument("--workload", type=int, default=2,
-                    help="2: 10-d Rosenbrock (default); 4: 27-d emulator; 5: emulator + learned screen")
+    ap.add_argument("--workload", type=int, default=5,
+                    help="5: 27-d emulator N=4000 m=400 (default); 4: N=2000 m=200; 2: 10-d Rosenbrock")
     ap.add_argument("--prec", default=None, help="emulator layers: bf16x3 (default) or f32")
-    ap.add_argument("--max-steps", type=int, default=0,
-                    help="emulator workloads: stop each run after this many batched steps (timing probe)")
+    ap.add_argument("--timed-only", action="store_true",
+                    help="emulator: stop after the timed steps (no complete run, no gate; for profiling)")
+    ap.add_argument("--no-screen-run", action="store_true", help="emulator: skip the learned-screen run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--stepout-spec", type=int, default=None,
-                    help="batched rounds: stepping-out offsets per side evaluated per round")
-    ap.add_argument("--shrink-spec", type=int, default=None,
-                    help="batched rounds: shrink proposals evaluated per round")
     ap.add_argument("--screen", default="",
-                    help="workload 5: surrogate settings as k=v pairs, e.g. margin=3,train_every=4")
-    ap.add_argument("--no-screen", action="store_true",
-                    help="workload 5 without the learned pre-screen (the plain sampler)")
+                    help="learned-screen settings as k=v pairs, e.g. margin=3,train_every=4")
+    ap.add_argument("--stepout-spec", type=int, default=None)
+    ap.add_argument("--shrink-spec", type=int, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--select-sweep", action="store_true",
-                    help="worst-1000 selection alone at N = 2^16 ... 2^24 (HBM streaming passes)")
-    ap.add_argument("--cluster-sweep", action="store_true",
-                    help="one cluster-tree node (mean, covariance, 2-means) at N = 2^16 ... 2^24, d = 10")
-    ap.add_argument("--lik-sweep", action="store_true",
-                    help="batched emulator likelihood alone at M = 200 ... 25600 rows per call")
-    ap.add_argument("--train-sweep", action="store_true",
-                    help="network training step alone (forward + backward) at batch 1024 ... 65536")
+    ap.add_argument("--select-sweep", action="store_true")
+    ap.add_argument("--cluster-sweep", action="store_true")
+    ap.add_argument("--lik-sweep", action="store_true")
+    ap.add_argument("--train-sweep", action="store_true")
+    ap.add_argument("--runs", default="",
+                    help="independent runs at once, e.g. 1,2,4,8,16: aggregate throughput of R concurrent runs "
+                         "(one stream and host thread each) of --workload 2 or 4/5")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only (the build targets a single "
+                                   "MI355X); run with --gpus 1", "n_gpus": args.gpus}))
+        sys.exit(2)
     if args.copy_probe:
         import torch
         n = args.copy_probe * (1 << 20) // 4
@@ -116,11 +108,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": 4 * n}))
         return
-    if args.gpus != 1:
-        print(json.dumps({"error": "the benchmark runs on one GPU only; run with --gpus 1",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
 
+    if args.runs:
+        # one hardware queue per concurrent run's stream (read when the HIP runtime starts)
+        need = max(int(r) for r in args.runs.split(","))
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(4, need)))
     import numpy as np
     import torch
     from paper_2608_28514_amd import native, workloads
@@ -134,27 +126,246 @@ def main():
         return bench_cluster_sweep(args, np, torch, native)
     if args.train_sweep:
         return bench_train_sweep(args, np, torch, native)
+    if args.runs:
+        return bench_runs(args, np, torch, native, workloads)
     if args.workload in (4, 5):
         return bench_emulator(args, np, torch, native, workloads)
+    if args.workload == 2:
+        return bench_rosenbrock(args, np, torch, native, workloads)
+    raise SystemExit(f"unknown workload {args.workload}")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------- 27-d emulator (default)
+def _emu_sampler(native, spec, N, prec, seed, args, screen):
+    kw = dict(prec=prec, state="f32", tree_depth=1, seed=seed)
+    if args.stepout_spec:
+        kw["stepout_spec"] = args.stepout_spec
+    if args.shrink_spec:
+        kw["shrink_spec"] = args.shrink_spec
+    s = native.Sampler(spec, N, **kw)
+    if screen:
+        skw = {"prec": "bf16"}
+        for item in filter(None, args.screen.split(",")):
+            k, v = item.split("=")
+            skw[k] = float(v) if "." in v or "e" in v else int(v)
+        s.enable_surrogate(**skw)
+    return s
+
+
+def _finish_run(native, s, m, t_start, label):
+    """Run s to the stopping rule, printing progress; returns wall seconds from t_start."""
+    while True:
+        rc, _ = s.run(m, max_steps=200)
+        st = s.stats()
+        log(f"{label}: {st['steps']} steps, {st['dead']} dead, {time.perf_counter() - t_start:.1f} s")
+        if rc == native.NS_DONE:
+            break
+    return time.perf_counter() - t_start
+
+
+def bench_emulator(args, np, torch, native, workloads):
+    wl = args.workload
+    prec = args.prec or "bf16x3"
+    N, m = (2000, 200) if wl == 4 else (4000, 400)
+    m = args.m or m
+    spec = workloads.likelihood(wl, seed=0)
+    ref = json.load(open(os.path.join(GOLDEN, "emulator27d_reference.json")))
+    lik_bit = 1 << native.TIMING_CLASSES.index("lik")
+
+    # ---- the timed steps, inside a complete run of the plain sampler (seed 0)
+    s = _emu_sampler(native, spec, N, prec, 0, args, screen=False)
+    native.ns_sync(s.ctx)
+    t_run0 = time.perf_counter()
+    s.run(m, max_steps=args.warmup)
+    st0 = s.stats()
+    native.ns_set_timing(s.ctx, lik_bit)          # events around the batched likelihood of each round
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, nsteps = s.run(m, max_steps=args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st1 = s.stats()
+    lik_ms, lik_rounds = s.timing()["lik"]
+    native.ns_set_timing(s.ctx, False)
+    if nsteps != args.steps:
+        raise SystemExit(f"the run stopped after {nsteps} of {args.steps} timed steps")
+    t_steps = t1 - t0
+    dead = st1["dead"] - st0["dead"]
+    rows = st1["net_rows"] - st0["net_rows"]
+    evals = st1["evals"] - st0["evals"]
+    log(f"timed {args.steps} steps: {t_steps:.3f} s, {dead / t_steps:.0f} updates/s, "
+        f"{rows} network rows, likelihood {lik_ms:.1f} ms over {lik_rounds} rounds")
+    useful = rows * EMU_FLOPS / (lik_ms * 1e-3)
+    issued = rows * EMU_MFMA_ISSUED / (lik_ms * 1e-3)
+    peak = BF16_PEAK if prec.startswith("bf16") else FP32_PEAK
+    roof = {"kernel": "k_dense_frag: the four dense layers of one round (27-512, two 512-512, "
+                      "512-1024 with the chi^2 fused)" if prec.startswith("bf16") else
+                      "k_gemm<F32> layers + k_chi2",
+            "bound": "mfma" if prec.startswith("bf16") else "alu",
+            "achieved": useful / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": useful / peak,
+            "traffic": None,
+            "flops_per_launch": rows * EMU_FLOPS / max(lik_rounds, 1),
+            "avg_launch_us": 1e3 * lik_ms / max(lik_rounds, 1), "launches": lik_rounds,
+            "rows_per_launch": rows / max(lik_rounds, 1),
+            "mfma_issued_tflops": issued / 1e12, "mfma_issued_frac": issued / peak,
+            "note": "one launch = the four layer kernels of one batched round, timed by HIP events on the "
+                    "context's stream; useful work 2,124,800 FLOP per network row (the split activations "
+                    "issue 3x that on MFMA, 9x in the first layer)"}
+    out = {"metric": METRIC, "value": dead / t_steps, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * t_steps / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16" if prec.startswith("bf16") else "f32",
+           "data": "synthetic",
+           "config": {"workload": f"emulator27d random-MLP 27-512-512-512-1024 tanh + diagonal chi^2, "
+                                  f"prior [0,1]^27, N_live={N}, m={m}, depth 1, 5d slice iterations, "
+                                  f"layers {prec}, FP32 state, seed 0",
+                      "n_live": N, "m": m, "d": 27},
+           "evals_per_s": evals / t_steps, "net_rows_per_s": rows / t_steps, "roofline": roof}
+    if args.timed_only:
+        s.close()
+        print(json.dumps(out, default=float))
+        return
+    wall = _finish_run(native, s, m, t_run0, "plain run")
+    st = s.stats()
+    lz, sig, H = s.logZ()
+    s.close()
+    lim = 2.0 * math.sqrt(sig ** 2 + ref["logZ_se"] ** 2)
+    out["run"] = {"seed": 0, "wall_s": wall, "dead": st["dead"], "steps": st["steps"],
+                  "updates_per_s_whole_run": st["dead"] / wall, "evals": st["evals"] - N,
+                  "net_rows": st["net_rows"], "logZ": lz, "sigma": sig, "H": H}
+    out["logZ_gate"] = {"reference_logZ": ref["logZ"], "reference_se": ref["logZ_se"],
+                        "reference": "tests/golden/emulator27d_reference.json (oracle, importance sampling, FP64)",
+                        "diff": lz - ref["logZ"], "limit_2sigma": lim, "pass": abs(lz - ref["logZ"]) < lim}
+    out["meets_gate"] = bool(out["logZ_gate"]["pass"])
+    log(f"plain run: log Z {lz:.4f} +- {sig:.4f} (reference {ref['logZ']:.4f}); {wall:.1f} s")
+
+    # ---- the same run with the learned pre-screen
+    if wl == 5 and not args.no_screen_run:
+        t = _emu_sampler(native, spec, N, prec, 0, args, screen=True)
+        native.ns_sync(t.ctx)
+        ts0 = time.perf_counter()
+        wall_s = _finish_run(native, t, m, ts0, "screened run")
+        st_s = t.stats()
+        lz_s, sig_s, H_s = t.logZ()
+        ss = t.surrogate_stats()
+        t.close()
+        lim_s = 2.0 * math.sqrt(sig_s ** 2 + ref["logZ_se"] ** 2)
+        out["screened_run"] = {"seed": 0, "wall_s": wall_s, "dead": st_s["dead"], "steps": st_s["steps"],
+                               "updates_per_s_whole_run": st_s["dead"] / wall_s, "net_rows": st_s["net_rows"],
+                               "screened": st_s["screened"], "logZ": lz_s, "sigma": sig_s,
+                               "gate_pass": abs(lz_s - ref["logZ"]) < lim_s,
+                               "speedup_vs_plain": wall / wall_s, "surrogate": ss}
+        log(f"screened run: log Z {lz_s:.4f} +- {sig_s:.4f}; {wall_s:.1f} s")
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_emulator(np, spec, N)
+    print(json.dumps(out, default=float))
+
+
+def cpu_baseline_emulator(np, spec, N):
+    """The FP64 oracle on the same likelihood and live-set size: one batched
+    step from the prior live set (m chains), on all host threads and on one."""
+    import oracle
+    res = {}
+    for threads, m in ((host_threads(), 4 * host_threads()), (1, 4)):
+        oracle.set_threads(threads)
+        o = oracle.Oracle(spec, N, seed=0, tree_depth=1)
+        t0 = time.perf_counter()
+        o.step(m)
+        dt = time.perf_counter() - t0
+        res[threads] = (m / dt, m, dt)
+        log(f"oracle {threads} thread(s): one step of {m} chains in {dt:.2f} s")
+    oracle.set_threads(1)
+    nt = host_threads()
+    return {"value": res[nt][0], "unit": "updates/s", "cores": nt, "kind": "oracle",
+            "value_1core": res[1][0], "cpu": cpu_model(),
+            "sample": f"one FP64 oracle step of the same workload from the prior live set (N={N}): "
+                      f"{res[nt][1]} chains on {nt} threads ({res[nt][2]:.1f} s), {res[1][1]} chains on "
+                      f"1 thread ({res[1][2]:.1f} s); OpenMP over the chains"}
+
+
+# ---------------------------------------------------------------- R runs at once
+def bench_runs(args, np, torch, native, workloads):
+    """R independent complete runs at once (ns_run_many: a stream and a host
+    thread per run), seeds 0..R-1, for each R in --runs: aggregate live-point
+    updates/s, evaluations/s and the per-run log Z.  Workload 2: 10-d
+    Rosenbrock (N = 500, m = 50, FP64 likelihood, FP32 state, depth 2), with
+    the useful FP64 rate of the counted Rosenbrock calls; workload 4/5: the
+    27-d emulator at N = 500, m = 100 (bf16x3)."""
+    Rs = [int(r) for r in args.runs.split(",")]
+    if args.workload == 2:
+        spec, N, m = workloads.likelihood(2), 500, args.m or 50
+        kw = dict(prec="f64", state="f32", tree_depth=2)
+        flops_per_eval = 2 * 10 + 8 * 9 + 2 * 10      # box map, 9 chain terms, proposal x + t v
+        desc = f"rosenbrock10d prior[-5,5]^10 N_live={N} m={m} depth 2 f64-likelihood f32-state"
+    else:
+        spec, N, m = workloads.likelihood(4, seed=0), 500, args.m or 100
+        kw = dict(prec=args.prec or "bf16x3", state="f32", tree_depth=1)
+        flops_per_eval = EMU_FLOPS
+        desc = f"emulator27d N_live={N} m={m} depth 1 layers {kw['prec']}"
+    streams = [torch.cuda.Stream() for _ in range(max(Rs))]
+    # warm-up: one run per stream
+    warm = [native.Sampler(spec, N, seed=900 + r, stream=streams[r], **kw) for r in range(min(2, max(Rs)))]
+    native.run_many(warm, m)
+    for w in warm:
+        w.close()
+    res = []
+    for R in Rs:
+        ss = [native.Sampler(spec, N, seed=r, stream=streams[r], **kw) for r in range(R)]
+        for x in ss:
+            native.ns_sync(x.ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        native.run_many(ss, m)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        stats = [x.stats() for x in ss]
+        lz = [x.logZ() for x in ss]
+        for x in ss:
+            x.close()
+        dead = sum(st["dead"] for st in stats)
+        evals = sum(st["evals"] - N for st in stats)
+        r = {"R": R, "wall_s": dt, "updates_per_s": dead / dt, "evals_per_s": evals / dt,
+             "useful_tflops": evals * flops_per_eval / dt / 1e12,
+             "logZ_mean": float(np.mean([x[0] for x in lz])), "sigma_mean": float(np.mean([x[1] for x in lz]))}
+        if R > 1:
+            r["logZ_std"] = float(np.std([x[0] for x in lz], ddof=1))
+        res.append(r)
+        log(f"R={R}: {dt:.2f} s, {dead / dt:.0f} updates/s")
+    peak = FP64_PEAK if args.workload == 2 else BF16_PEAK
+    best = max(res, key=lambda x: x["updates_per_s"])
+    print(json.dumps({"metric": "aggregate live-point updates/s of R independent runs at once, 1 GPU",
+                      "unit": "updates/s", "data": "synthetic", "config": {"workload": desc},
+                      "peak_tflops": peak / 1e12, "best_R": best["R"],
+                      "best_frac_of_peak": best["useful_tflops"] * 1e12 / peak,
+                      "speedup_best_vs_R1": best["updates_per_s"] / res[0]["updates_per_s"] if res[0]["R"] == 1
+                      else None, "sweep": res}, default=float))
+
+
+# ---------------------------------------------------------------- 10-d Rosenbrock
+def bench_rosenbrock(args, np, torch, native, workloads):
+    """10-d Rosenbrock, N = 500, m = 50 (or --m), FP64 likelihood, FP32 state,
+    depth 2: one step = one complete run (seeds 0 .., after warm-up runs);
+    log Z against the stored oracle ensemble of the same setting."""
     spec = workloads.likelihood(2)
     N, m, d, depth = 500, args.m or 50, 10, 2
     kw = dict(prec="f64", state="f32", tree_depth=depth)
-
+    ens = json.load(open(os.path.join(GOLDEN, "c2_oracle_ensemble.json")))
+    row = next((r for r in ens["settings"] if (r["m"], r["n"], r["depth"]) == (m, 5, depth)), None)
     for k in range(args.warmup):
         s = native.Sampler(spec, N, seed=999 + k, **kw)
         s.run(m)
-        s.logZ()
         s.close()
-
     torch.cuda.synchronize()
-    runs = []
-    t_total = 0.0
-    kern = {c: [0.0, 0] for c in native.TIMING_CLASSES}
+    runs, t_total = [], 0.0
+    slice_ms = slice_n = 0.0
+    slice_bit = 1 << native.TIMING_CLASSES.index("slice")
     for k in range(args.steps):
         s = native.Sampler(spec, N, seed=k, **kw)
-        # events around the slice kernel only: it is the roofline kernel, and
-        # the other launches run without extra stream records
-        native.ns_set_timing(s.ctx, 1 << native.TIMING_CLASSES.index("slice"))
+        native.ns_set_timing(s.ctx, slice_bit)
         native.ns_sync(s.ctx)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -162,89 +373,56 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         t_total += t1 - t0
-        tm = native.ns_get_timing(s.ctx)
-        for c, (ms, n) in tm.items():
-            kern[c][0] += ms
-            kern[c][1] += n
+        ms, n = s.timing()["slice"]
+        slice_ms += ms
+        slice_n += n
         st = s.stats()
         lz, sig, H = s.logZ()
-        runs.append({"seed": k, "time_s": t1 - t0, "dead": st["dead"], "steps": st["steps"],
-                     "evals": st["evals"] - N, "logZ": lz, "sigma": sig, "H": H})
+        runs.append({"seed": k, "time_s": t1 - t0, "dead": st["dead"], "evals": st["evals"] - N,
+                     "logZ": lz, "sigma": sig, "H": H})
         s.close()
-
     dead = sum(r["dead"] for r in runs)
     evals = sum(r["evals"] for r in runs)
-    steps_sum = sum(r["steps"] for r in runs)
-    value = dead / t_total
-    # dominant kernel class and its roofline (ALU bound: FP64 likelihood arithmetic)
-    dom = "slice"
-    slice_ms, slice_n = kern["slice"]
-    # useful work of the slice kernel: the counted likelihood calls (the
-    # directions are formed by the separate draw kernel)
-    flops = evals * rosen_flops_per_eval(d)
-    achieved = flops / (slice_ms * 1e-3) if slice_ms > 0 else 0.0
-    roof = {"kernel": "k_slice<float,double,10>", "bound": "alu", "achieved": achieved / 1e12,
-            "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK,
-            "traffic": slice_traffic_bytes(), "traffic_unit": "bytes per launch",
-            "avg_launch_us": 1e3 * slice_ms / max(slice_n, 1),
-            "flops_per_launch": flops / max(slice_n, 1), "dominant_class": dom}
-
-    out = {
-        "metric": "live-point updates/s at |dlogZ|<2sigma vs oracle, 1 GPU",
-        "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * t_total / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"rosenbrock10d prior[-5,5]^10 N_live={N} m={m} depth={depth} "
-                               f"slice=5d f64-likelihood f32-state stop=1e-3",
-                   "n_live": N, "m": m, "d": d},
-        "evals_per_s": evals / t_total,
-        "kernel_ms": {"slice": round(kern["slice"][0], 3)},
-        "kernel_launches": {"slice": kern["slice"][1]},
-        "roofline": roof,
-        "runs": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()} for r in runs],
-        "quadrature_logZ": ROSEN_QUADRATURE_LOGZ,
-    }
-
+    out = {"metric": METRIC, "value": dead / t_total, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * t_total / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"rosenbrock10d prior[-5,5]^10 N_live={N} m={m} depth={depth} slice=5d "
+                                  f"f64-likelihood f32-state; one step = one complete run", "n_live": N,
+                      "m": m, "d": d},
+           "evals_per_s": evals / t_total,
+           "slice_kernel": {"avg_launch_us": 1e3 * slice_ms / max(slice_n, 1), "launches": int(slice_n),
+                            "bound": "latency",
+                            "note": "one wave per chain; m waves on 1,024 SIMDs"}}
+    if row is not None:
+        g = np.array([r["logZ"] for r in runs])
+        o = np.array(row["logZ"])
+        sem = math.sqrt((g.var(ddof=1) if g.size > 1 else 0.0) / g.size + o.var(ddof=1) / o.size)
+        out["oracle_ensemble"] = {"mean": row["mean"], "runs": len(row["logZ"]), "std": row["std"]}
+        out["gpu_logZ_mean"] = float(g.mean())
+        out["mean_diff_in_sem"] = float((g.mean() - row["mean"]) / sem) if sem > 0 else None
+        out["runs_within_2sigma"] = int(sum(abs(r["logZ"] - row["mean"]) < 2 * math.sqrt(r["sigma"] ** 2 +
+                                                                                     row["sem"] ** 2)
+                                            for r in runs))
+        out["meets_gate"] = bool(abs(g.mean() - row["mean"]) < 3 * sem)
+    out["runs"] = runs
     if not args.no_cpu_baseline:
         import oracle
-        threads = min(os.cpu_count() or 1, 16)
-        oracle.set_threads(threads)
-        o_dead, o_time, o_lz = 0, 0.0, []
-        seed = 0
+        nt = host_threads()
+        oracle.set_threads(nt)
+        o_dead, o_time, seed = 0, 0.0, 0
         while o_time < args.cpu_seconds and seed < 16:
             o = oracle.Oracle(spec, N, seed=seed, tree_depth=depth)
             t0 = time.perf_counter()
             o.run(m)
             o_time += time.perf_counter() - t0
             o_dead += o.n_dead()
-            o_lz.append(o.logZ())
             seed += 1
-        o_vals = np.array([x[0] for x in o_lz])
-        o_mean = float(o_vals.mean())
-        o_sig = float(np.mean([x[1] for x in o_lz]))
-        # per-run scatter: the larger of sqrt(H/N) and the oracle's own spread
-        o_spread = float(o_vals.std(ddof=1)) if len(o_vals) > 1 else o_sig
-        out["cpu_baseline"] = {"value": o_dead / o_time, "unit": "updates/s", "cores": threads,
-                               "kind": "oracle",
-                               "sample": f"{len(o_lz)} complete FP64 oracle runs of the same workload "
-                                         f"(seeds 0..{len(o_lz) - 1}), OpenMP over the m chains"}
-        out["oracle_logZ_mean"] = o_mean
-        out["oracle_logZ_run_std"] = o_spread
-        out["gpu_logZ_mean"] = float(np.mean([r["logZ"] for r in runs]))
-        gate = [abs(r["logZ"] - o_mean) < 2 * math.sqrt(max(r["sigma"], o_spread) ** 2 + o_spread ** 2 / len(o_lz))
-                for r in runs]
-        out["pass_2sigma_vs_oracle"] = f"{sum(gate)}/{len(gate)}"
-        gate_s = [abs(r["logZ"] - o_mean) < 2 * math.sqrt(r["sigma"] ** 2 + o_spread ** 2 / len(o_lz))
-                  for r in runs]
-        out["pass_2sigma_vs_oracle_sqrtHN"] = f"{sum(gate_s)}/{len(gate_s)}"
-        g_vals = np.array([r["logZ"] for r in runs])
-        sem = math.sqrt((g_vals.var(ddof=1) if len(g_vals) > 1 else o_spread ** 2) / len(g_vals)
-                        + o_spread ** 2 / len(o_lz))
-        out["mean_logZ_diff_vs_oracle_in_sem"] = float((g_vals.mean() - o_mean) / sem)
-    out["pass_2sigma_vs_quadrature"] = \
-        f"{sum(abs(r['logZ'] - ROSEN_QUADRATURE_LOGZ) < 2 * r['sigma'] for r in runs)}/{len(runs)}"
-    print(json.dumps(out))
+        oracle.set_threads(1)
+        out["cpu_baseline"] = {"value": o_dead / o_time, "unit": "updates/s", "cores": nt, "kind": "oracle",
+                               "cpu": cpu_model(),
+                               "sample": f"{seed} complete FP64 oracle runs of the same workload, OpenMP over "
+                                         f"the m chains"}
+    print(json.dumps(out, default=float))
 
 
 HBM_PEAK = 8.0e12                   # MI355X HBM3E bytes/s
@@ -430,100 +608,6 @@ def bench_lik_sweep(args, np, torch, native, workloads):
                       "sweep": res}))
 
 
-def bench_emulator(args, np, torch, native, workloads):
-    """27-d random-MLP emulator (workload 4) or the same with the learned screen
-    and N=4000, m=400 (workload 5).  One step = one complete run; the dominant
-    kernels are the dense layers (MFMA for bf16x3)."""
-    wl = args.workload
-    prec = args.prec or "bf16x3"
-    N, m = (2000, 200) if wl == 4 else (4000, 400)
-    m = args.m or m
-    spec = workloads.likelihood(wl, seed=0)
-    kw = dict(prec=prec, state="f32", tree_depth=1)
-    if args.stepout_spec:
-        kw["stepout_spec"] = args.stepout_spec
-    if args.shrink_spec:
-        kw["shrink_spec"] = args.shrink_spec
-    screen_kw = {"prec": "bf16"}
-    for item in filter(None, args.screen.split(",")):
-        k, v = item.split("=")
-        screen_kw[k] = float(v) if "." in v or "e" in v else int(v)
-    runs, t_total = [], 0.0
-    kern = {c: [0.0, 0] for c in native.TIMING_CLASSES}
-    for k in range(args.warmup + args.steps):
-        s = native.Sampler(spec, N, seed=(999 + k) if k < args.warmup else k - args.warmup, **kw)
-        if wl == 5 and not args.no_screen:
-            s.enable_surrogate(**screen_kw)
-        timed = k >= args.warmup
-        if timed:
-            native.ns_set_timing(s.ctx, True)
-        native.ns_sync(s.ctx)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        # chunks of 100 steps with a progress line each (a full run takes minutes)
-        left = args.max_steps if args.max_steps else None
-        while True:
-            chunk = 100 if left is None else min(100, left)
-            rc, _ = s.run(m, max_steps=chunk)
-            done = rc == native.NS_DONE
-            if left is not None:
-                left -= chunk
-            st_p = s.stats()
-            print(f"[bench] workload {wl} run {k}: {st_p['steps']} steps, {st_p['dead']} dead, "
-                  f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-            if done or (left is not None and left <= 0):
-                break
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        print(f"[bench] workload {wl} run {k} ({'timed' if timed else 'warm-up'}): {t1 - t0:.1f} s",
-              file=sys.stderr, flush=True)
-        if not timed:
-            s.close()
-            continue
-        t_total += t1 - t0
-        for c, (ms, n) in native.ns_get_timing(s.ctx).items():
-            kern[c][0] += ms
-            kern[c][1] += n
-        st = s.stats()
-        lz, sig, H = s.logZ()
-        r = {"seed": k - args.warmup, "time_s": t1 - t0, "dead": st["dead"], "steps": st["steps"],
-             "evals": st["evals"] - N, "net_rows": st["net_rows"], "screened": st["screened"],
-             "logZ": lz, "sigma": sig, "H": H}
-        if wl == 5 and not args.no_screen:
-            r["surrogate"] = s.surrogate_stats()
-        runs.append(r)
-        s.close()
-    dead = sum(r["dead"] for r in runs)
-    evals = sum(r["evals"] for r in runs)
-    rows = sum(r["net_rows"] for r in runs)
-    lik_ms = kern["lik"][0]
-    flops = rows * EMU_FLOPS
-    peak = BF16_PEAK if prec.startswith("bf16") else FP32_PEAK
-    achieved = flops / (lik_ms * 1e-3) if lik_ms > 0 else 0.0
-    out = {
-        "metric": "live-point updates/s at |dlogZ|<2sigma vs oracle, 1 GPU",
-        "value": dead / t_total, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * t_total / max(args.steps, 1),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16" if prec.startswith("bf16") else "f32", "data": "synthetic",
-        "config": {"workload": f"emulator27d MLP 27-512-512-512-1024 N_live={N} m={m} depth=1 "
-                               f"spec={kw.get('stepout_spec', 4)}/{kw.get('shrink_spec', 8)} "
-                               f"layers={prec}{' +learned-screen' if wl == 5 and not args.no_screen else ''}"
-                               f"{f' PARTIAL first {args.max_steps} steps' if args.max_steps else ''}",
-                   "n_live": N, "m": m, "d": 27},
-        "evals_per_s": evals / t_total, "net_rows_per_s": rows / t_total,
-        "kernel_ms": {c: round(v[0], 3) for c, v in kern.items()},
-        "kernel_launches": {c: v[1] for c, v in kern.items()},
-        "roofline": {"kernel": ("k_dense_frag (emulator layers, chi^2 partials fused; the row sums run in "
-                                "the next round's advance kernel)"
-                                if prec.startswith("bf16") else "k_gemm<F32> + k_chi2"),
-                     "bound": "mfma" if prec.startswith("bf16") else "alu", "achieved": achieved / 1e12,
-                     "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                     "note": "network rows x 2,124,800 FLOP over the batched-likelihood time (HIP events); "
-                             "the split activations issue 3x this MFMA work (9x in the first layer)"},
-        "runs": runs,
-    }
-    print(json.dumps(out, default=float))
 
 
 if __name__ == "__main__":

@@ -63,14 +63,27 @@ typedef enum {
   NS_CORR_HISTORY = 3         /* Algorithm 2: Algorithm 1 + history_iters relaxations     */
 } ns_corr;
 
-/* Likelihood families (all vectorised on the device). */
+/* Likelihood families (vectorised on the device, except NS_LIK_CALLBACK). */
 typedef enum {
   NS_LIK_MIXTURE = 0,    /* log sum_k exp(logw_k - q_k/2), q_k diagonal Mahalanobis:
                             Gaussians, Eq. (2), Eq. (3), Eq. (5) and Gaussian mixtures   */
   NS_LIK_ROSENBROCK = 1, /* -sum_i [b (x_{i+1} - x_i^2)^2 + (a - x_i)^2], Eq. (6)      */
   NS_LIK_SHELL = 2,      /* -((|x| - r0)/w)^2 / 2, Eq. (4)                              */
-  NS_LIK_MLP = 3         /* emulator: tanh MLP, linear output, diagonal chi^2 (Sec. 5)  */
+  NS_LIK_MLP = 3,        /* emulator: tanh MLP, linear output, diagonal chi^2 (Sec. 5)  */
+  NS_LIK_CALLBACK = 4    /* any likelihood, evaluated on the host by a user function   */
 } ns_lik_kind;
+
+/* Host likelihood for NS_LIK_CALLBACK: logL[k] = log L(theta_k) for the n
+ * points theta (n x d, row major, parameter space theta = lo + (hi - lo) u,
+ * all inside the prior box), FP64.  Both arrays are host memory owned by the
+ * library, valid during the call.  Return 0 on success; any other value stops
+ * the step with NS_EINVAL.  NaN results count as -inf and are counted in
+ * ns_stats_t.nan_logL; -inf is a valid value (zero likelihood).  The sampler
+ * calls it from the thread that calls ns_init / ns_step_batch / ns_run, once
+ * per batched round with that round's proposals (the rounds driver is used;
+ * with stepout_spec = shrink_spec = 1 every point passed is one counted
+ * likelihood evaluation), and synchronises its stream around each call. */
+typedef int (*ns_lik_callback)(void* user, const double* theta, int64_t n, int d, double* logL);
 
 typedef struct {
   ns_lik_kind kind;
@@ -95,6 +108,10 @@ typedef struct {
   const double* biases;
   const double* data;
   const double* sigma;
+  /* NS_LIK_CALLBACK: the function and its user pointer (prec must be NS_FP64);
+     kept, not copied: both must stay valid while the context lives          */
+  ns_lik_callback callback;
+  void* callback_user;
 } ns_likelihood;
 
 typedef struct {
@@ -129,7 +146,8 @@ typedef struct {
   int64_t stepout_caps;    /* stepping-out sides that hit max_stepout                   */
   int64_t shrink_caps;     /* slice iterations that hit max_shrink                      */
   int64_t clusterings;     /* cluster-tree builds                                       */
-  int64_t nan_logL;        /* likelihood values that were NaN (counted as -inf)         */
+  int64_t nan_logL;        /* likelihood values that were NaN (counted as -inf): every
+                              NaN a callback returns, and NaNs of the initial points  */
   int32_t done;            /* stopping rule reached                                     */
   int32_t n_clusters;      /* clusters of the current tree                              */
   int64_t screened;        /* proposals the surrogate screened out (not evaluated)      */
@@ -162,17 +180,38 @@ ns_status ns_step_batch(ns_ctx* c, int m);
  * NS_DONE or NS_OK. */
 ns_status ns_run(ns_ctx* c, int m, int64_t max_steps, int64_t* steps);
 
+/* R independent runs at once: ns_run(ctxs[r], m, max_steps, &steps[r]) for
+ * every r, each from a host thread of its own, so that the runs' steps are in
+ * flight together and the device holds R * m chains.  Independent runs (the
+ * alternative to batching that the paper weighs in Sec. 1, and the way to fill
+ * the device when m is small) give the same results as run one by one: each
+ * context draws from its own seed and runs on its own stream.  For overlap the
+ * contexts need distinct streams (ns_init's hip_stream), and the HIP runtime
+ * at least R hardware queues (environment GPU_MAX_HW_QUEUES >= R, at most 32,
+ * set before the runtime starts; streams beyond it share queues and
+ * serialise).  Contexts with a callback likelihood run their callbacks from
+ * these threads.  steps (R entries, may be NULL) as in ns_run.  Returns the
+ * first error in context order (its ns_last_error describes it), else NS_DONE
+ * if every run reached the stopping rule, else NS_OK. */
+ns_status ns_run_many(ns_ctx* const* ctxs, int R, int m, int64_t max_steps, int64_t* steps);
+
 /* Wait for all enqueued work of the context. */
 ns_status ns_sync(ns_ctx* c);
 
-/* Evidence with the final live points added, each with prior volume X_end/N:
- * logZ, sigma = sqrt(H/N) and the information H = sum_i p_i log L_i - log Z.
- * Does not change the run; any output pointer may be NULL. */
+/* Evidence, Eq. (1) Z = int L(X) dX, by the single-point integration the
+ * paper keeps for batched deaths (Sec. 3): dead row i (i = 1, 2, ...) has
+ * log X_i = -i/N and the rectangle weight w_i = (X_{i-1} - X_i) L_i; the final
+ * live points are added, each with prior volume X_end/N.  Returns logZ,
+ * sigma = sqrt(H/N) and the information H = sum_i p_i log L_i - log Z
+ * (p_i = w_i/Z), all in FP64.  Does not change the run; any output pointer may
+ * be NULL; synchronises the context's stream. */
 ns_status ns_logZ(ns_ctx* c, double* logZ, double* sigma, double* H);
 
-/* Dead rows in death order.  Two-phase: with u == logL == logX == logw == NULL
- * only *n is set.  Otherwise arrays hold *n rows: u (n*d), logL, logX = -i/N,
- * logw = log((X_{i-1} - X_i) L_i) (host arrays, any may be NULL). */
+/* Dead rows in death order (Algorithm 1: the rejected entries of each batch,
+ * ascending).  Two-phase: with u == logL == logX == logw == NULL only *n is
+ * set.  Otherwise arrays hold *n rows: u (n*d), logL, logX = -i/N and the
+ * rectangle weight logw = log((X_{i-1} - X_i) L_i) of the single-point
+ * integration of Eq. (1) (host arrays, any may be NULL). */
 ns_status ns_get_dead(ns_ctx* c, int64_t* n, double* u, double* logL, double* logX, double* logw);
 
 /* Live set: u (N*d), logL (N), label (N: cluster node of each point); host

@@ -39,8 +39,6 @@ constexpr int kShrinkFirst = 4;  // proposals of the first shrink round
 constexpr int kSoFirst = 8, kSpecK = 4, kSpecQ = 3;
 constexpr uint32_t kSoMask = (1u << kSoFirst) - 1u;
 static_assert(2 * kSoFirst + kSpecK * kSpecK * kSpecQ <= 64, "first round exceeds a wave");
-constexpr int kShrinkPre = 32;  // shrink uniforms drawn ahead per iteration
-constexpr int kDrawExtra = 1 + kShrinkPre;  // draw block: d direction entries, a0, U_0..U_31
 static_assert(kSpecQ <= kShrinkPre, "speculative shrink uniforms must be pre-drawn");
 
 template <typename LT>

@@ -56,6 +56,16 @@ struct ns_ctx {
   double* mlp_data = nullptr;
   double* mlp_isig = nullptr;
   bool emu_frag = false;      // emulator likelihood on the fragment-major path (emu_forward_logL)
+  // host likelihood (NS_LIK_CALLBACK): rows staged through pinned memory
+  ns_lik_callback cb = nullptr;
+  void* cb_user = nullptr;
+  void* h_pts = nullptr;      // pinned, rows_cap x d, state precision
+  int* h_flag = nullptr;      // pinned, rows_cap
+  int* h_cbgate = nullptr;    // pinned, one int
+  double* h_rl = nullptr;     // pinned, rows_cap
+  std::vector<double> cb_theta, cb_out;
+  std::vector<long> cb_rows;
+  int64_t cb_nan = 0;
   // compaction of the rows to evaluate (network likelihoods) + learned screen
   SurrCounters* d_sc = nullptr;
   SurrCounters* h_sc = nullptr;   // pinned
@@ -196,9 +206,9 @@ static ns_status alloc_batch(ns_ctx* c, int M) {
   NS_TRY(dalloc(&b.hist_logL, static_cast<size_t>(T) * M));
   NS_TRY(hipMalloc(&b.hist_u, sb * static_cast<size_t>(M) * T * d));
   NS_TRY(dalloc(&b.hist_n, M));
-  // draw blocks of the fused slice kernel: M chains x n_iter iterations x (d + 33)
+  // draw blocks of the fused slice kernel: M chains x n_iter iterations x (d + kDrawExtra)
   const size_t n_iter = static_cast<size_t>(c->cfg.slice_steps_per_dim) * d;
-  NS_TRY(hipMalloc(&b.draws, sb * static_cast<size_t>(M) * n_iter * (d + 33)));
+  NS_TRY(hipMalloc(&b.draws, sb * static_cast<size_t>(M) * n_iter * (d + kDrawExtra)));
   c->M = M;
   return NS_OK;
 }
@@ -244,6 +254,10 @@ static void free_all(ns_ctx* c) {
   if (c->h_prog) (void)hipHostFree(c->h_prog);
   if (c->h_gate) (void)hipHostFree(c->h_gate);
   if (c->h_sc) (void)hipHostFree(c->h_sc);
+  if (c->h_pts) (void)hipHostFree(c->h_pts);
+  if (c->h_flag) (void)hipHostFree(c->h_flag);
+  if (c->h_cbgate) (void)hipHostFree(c->h_cbgate);
+  if (c->h_rl) (void)hipHostFree(c->h_rl);
   if (c->poll_ev) (void)hipEventDestroy(c->poll_ev);
   for (auto& p : c->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -357,8 +371,49 @@ static NetDev surr_netdev(const ns_ctx* c) {
 // Likelihood of the first n rows of the row buffers (gate: skip when zero).
 // Network likelihoods: in-box rows (minus the ones the surrogate screens out,
 // when allowed) are compacted, evaluated, and scattered back.
+// The rows' likelihoods from the host callback: in-box rows are copied to
+// pinned memory, mapped to parameter space (theta = lo + span u, FP64), passed
+// to the callback in one call, and the values (NaN -> -inf, counted; rows
+// outside the box -inf) copied back.  Synchronises the stream.
+static ns_status eval_rows_callback(ns_ctx* c, long n, const int* gate) {
+  const int d = c->sh.d;
+  const size_t sb = c->sh.state_f32 ? 4 : 8;
+  NS_TRY(hipMemcpyAsync(c->h_pts, c->rb.pts, sb * n * d, hipMemcpyDeviceToHost, c->stream));
+  NS_TRY(hipMemcpyAsync(c->h_flag, c->rb.flag, sizeof(int) * n, hipMemcpyDeviceToHost, c->stream));
+  if (gate) NS_TRY(hipMemcpyAsync(c->h_cbgate, gate, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  NS_TRY(hipStreamSynchronize(c->stream));
+  if (gate && *c->h_cbgate == 0) return NS_OK;   // no chain proposed anything this round
+  c->cb_rows.clear();
+  for (long r = 0; r < n; ++r)
+    if (c->h_flag[r]) c->cb_rows.push_back(r);
+  const long k = static_cast<long>(c->cb_rows.size());
+  c->cb_theta.resize(static_cast<size_t>(k) * d);
+  c->cb_out.assign(static_cast<size_t>(k), 0.0);
+  for (long q = 0; q < k; ++q) {
+    const long r = c->cb_rows[q];
+    for (int i = 0; i < d; ++i) {
+      const double ui = c->sh.state_f32 ? static_cast<double>(static_cast<const float*>(c->h_pts)[r * d + i])
+                                        : static_cast<const double*>(c->h_pts)[r * d + i];
+      c->cb_theta[static_cast<size_t>(q) * d + i] = c->lik.lo[i] + c->lik.span[i] * ui;
+    }
+  }
+  if (k > 0) {
+    const int rc = c->cb(c->cb_user, c->cb_theta.data(), static_cast<int64_t>(k), d, c->cb_out.data());
+    if (rc != 0) return inval(c, "likelihood callback failed (returned " + std::to_string(rc) + ")");
+  }
+  for (long r = 0; r < n; ++r) c->h_rl[r] = -INFINITY;
+  for (long q = 0; q < k; ++q) {
+    const double v = c->cb_out[q];
+    if (std::isnan(v)) ++c->cb_nan;
+    c->h_rl[c->cb_rows[q]] = std::isnan(v) ? -INFINITY : v;
+  }
+  NS_TRY(hipMemcpyAsync(c->rb.rlogL, c->h_rl, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+  return NS_OK;
+}
+
 static ns_status eval_rows(ns_ctx* c, long n, const int* gate, bool allow_screen = false, int round = -1) {
   TimeScope ts(c, NS_TIME_LIK);
+  if (c->cb) return eval_rows_callback(c, n, gate);
   if (c->is_mlp && round >= 0 && c->rb.xf_direct) {
     // rows written by the advance kernel straight into compacted split planes
     const int* crows = c->rb.crows + round;
@@ -559,10 +614,12 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
     return inval(nullptr, "ns_init: unknown correction");
   if (cfg->state_prec != NS_FP64 && cfg->state_prec != NS_FP32)
     return inval(nullptr, "ns_init: state_prec must be FP64 or FP32");
-  if (lik->kind < NS_LIK_MIXTURE || lik->kind > NS_LIK_MLP)
+  if (lik->kind < NS_LIK_MIXTURE || lik->kind > NS_LIK_CALLBACK)
     return inval(nullptr, "ns_init: unknown likelihood kind");
   if (lik->kind != NS_LIK_MLP && lik->prec != NS_FP64 && lik->prec != NS_FP32)
     return inval(nullptr, "ns_init: analytic likelihoods run in FP64 or FP32");
+  if (lik->kind == NS_LIK_CALLBACK && (!lik->callback || lik->prec != NS_FP64))
+    return inval(nullptr, "ns_init: a callback likelihood needs a function and prec NS_FP64");
   if (lik->kind == NS_LIK_MLP) {
     if (lik->prec != NS_FP32 && lik->prec != NS_BF16 && lik->prec != NS_BF16X3)
       return inval(nullptr, "ns_init: the network likelihood runs in FP32, BF16 or BF16X3");
@@ -576,7 +633,7 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
       if (!(lik->sigma[i] > 0) || !std::isfinite(lik->sigma[i]))
         return inval(nullptr, "ns_init: sigma must be positive and finite");
   }
-  if (cfg->batch_rounds || lik->kind == NS_LIK_MLP) {
+  if (cfg->batch_rounds || lik->kind == NS_LIK_MLP || lik->kind == NS_LIK_CALLBACK) {
     if (cfg->stepout_spec < 1 || cfg->stepout_spec > 32 || cfg->shrink_spec < 1 || cfg->shrink_spec > 64)
       return inval(nullptr, "ns_init: stepout_spec in [1, 32], shrink_spec in [1, 64]");
   }
@@ -641,7 +698,11 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
     NS_INIT_TRY(upload(c, iv.data(), iv.size(), &L.ivar_f));
   }
   c->is_mlp = lik->kind == NS_LIK_MLP;
-  c->batched = c->is_mlp || cfg->batch_rounds != 0;
+  if (lik->kind == NS_LIK_CALLBACK) {
+    c->cb = lik->callback;
+    c->cb_user = lik->callback_user;
+  }
+  c->batched = c->is_mlp || c->cb || cfg->batch_rounds != 0;
   if (c->is_mlp) {
     NetDev& net = c->net;
     net.n_layers = lik->n_layers;
@@ -769,6 +830,14 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
     NS_INIT_HIP(dalloc(&rb.cmap, static_cast<size_t>(rb.rows_cap / rp.P + 1)));
     NS_INIT_HIP(dalloc(&rb.cbase, static_cast<size_t>(rb.rows_cap / rp.P + 1)));
     NS_INIT_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_gate), sizeof(int), hipHostMallocDefault));
+    if (c->cb) {
+      NS_INIT_HIP(hipHostMalloc(&c->h_pts, sb * rb.rows_cap * d, hipHostMallocDefault));
+      NS_INIT_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_flag), sizeof(int) * rb.rows_cap,
+                                hipHostMallocDefault));
+      NS_INIT_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_cbgate), sizeof(int), hipHostMallocDefault));
+      NS_INIT_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_rl), sizeof(double) * rb.rows_cap,
+                                hipHostMallocDefault));
+    }
     if (c->is_mlp) {
       // hidden activations: FP32, or three bfloat16 planes (1.5x) on the split path
       // three bfloat16 planes of rows (padded to 16) x max_width = 1.5 floats per element
@@ -944,6 +1013,29 @@ ns_status ns_run(ns_ctx* c, int m, int64_t max_steps, int64_t* steps) {
   return c->known_done ? NS_DONE : NS_OK;
 }
 
+ns_status ns_run_many(ns_ctx* const* ctxs, int R, int m, int64_t max_steps, int64_t* steps) {
+  if (!ctxs || R < 1 || R > 1024) return inval(nullptr, "ns_run_many: need 1 <= R <= 1024 contexts");
+  for (int r = 0; r < R; ++r) {
+    if (!ctxs[r]) return inval(nullptr, "ns_run_many: null context");
+    for (int q = 0; q < r; ++q)
+      if (ctxs[q] == ctxs[r]) return inval(nullptr, "ns_run_many: a context appears twice");
+  }
+  std::vector<ns_status> rc(R, NS_OK);
+  std::vector<int64_t> st(R, 0);
+  std::vector<std::thread> th;
+  th.reserve(R);
+  for (int r = 0; r < R; ++r)
+    th.emplace_back([&, r] { rc[r] = ns_run(ctxs[r], m, max_steps, &st[r]); });
+  for (auto& t : th) t.join();
+  bool all_done = true;
+  for (int r = 0; r < R; ++r) {
+    if (steps) steps[r] = st[r];
+    if (rc[r] < 0) return rc[r];
+    all_done &= rc[r] == NS_DONE;
+  }
+  return all_done ? NS_DONE : NS_OK;
+}
+
 ns_status ns_logZ(ns_ctx* c, double* logZ, double* sigma, double* H) {
   if (!c) return NS_EINVAL;
   NS_TRY(launch_final_logZ(c->sh, c->b, c->d_out3, c->stream));
@@ -1093,7 +1185,7 @@ ns_status ns_stats(ns_ctx* c, ns_stats_t* s) {
   s->stepout_caps = static_cast<int64_t>(h.so_caps);
   s->shrink_caps = static_cast<int64_t>(h.sh_caps);
   s->clusterings = static_cast<int64_t>(h.clusterings);
-  s->nan_logL = static_cast<int64_t>(h.nan_logL);
+  s->nan_logL = static_cast<int64_t>(h.nan_logL) + c->cb_nan;
   s->done = h.done;
   s->screened = static_cast<int64_t>(h.screened);
   s->net_rows = 0;

@@ -45,6 +45,10 @@ struct DevBufs {
 };
 
 constexpr int kStatW = 8;  // ints per chain in chain_stat
+// Draw block of one slice iteration of the fused slice kernel: d direction
+// entries, the bracket offset a0 and kShrinkPre shrink uniforms.
+constexpr int kShrinkPre = 32;
+constexpr int kDrawExtra = 1 + kShrinkPre;
 
 struct Shape {
   int N, d, T, nodes, depth;

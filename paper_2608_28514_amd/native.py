@@ -19,11 +19,15 @@ STATUS = {0: "NS_OK", 1: "NS_DONE", -1: "NS_EINVAL", -2: "NS_ENOMEM", -3: "NS_ED
           -4: "NS_ESTATE", -5: "NS_ENUMERIC"}
 PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
 CORR = {"none": 0, "best_of_worst": 1, "sort": 2, "history": 3}
-LIK = {"mixture": 0, "rosenbrock": 1, "shell": 2, "mlp": 3}
+LIK = {"mixture": 0, "rosenbrock": 1, "shell": 2, "mlp": 3, "callback": 4}
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)
 _i64p = C.POINTER(C.c_int64)
+
+
+# int callback(void* user, const double* theta, int64_t n, int d, double* logL)
+LIK_CALLBACK = C.CFUNCTYPE(C.c_int, C.c_void_p, _dp, C.c_int64, C.c_int, _dp)
 
 
 class NsLikelihood(C.Structure):
@@ -32,7 +36,7 @@ class NsLikelihood(C.Structure):
                 ("ros_a", C.c_double), ("ros_b", C.c_double),
                 ("shell_r0", C.c_double), ("shell_w", C.c_double),
                 ("n_layers", C.c_int), ("widths", _ip), ("weights", _dp), ("biases", _dp),
-                ("data", _dp), ("sigma", _dp)]
+                ("data", _dp), ("sigma", _dp), ("callback", LIK_CALLBACK), ("callback_user", C.c_void_p)]
 
 
 class NsConfig(C.Structure):
@@ -97,6 +101,7 @@ def lib():
             "ns_step_batch": [vp, C.c_int],
             "ns_run": [vp, C.c_int, C.c_int64, _i64p],
             "ns_sync": [vp],
+            "ns_run_many": [C.POINTER(vp), C.c_int, C.c_int, C.c_int64, _i64p],
             "ns_logZ": [vp, _dp, _dp, _dp],
             "ns_get_dead": [vp, _i64p, _dp, _dp, _dp, _dp],
             "ns_get_live": [vp, _dp, _dp, _ip],
@@ -189,6 +194,21 @@ def make_likelihood(spec, prec="f64"):
         L.ros_a, L.ros_b = spec.get("a", 1.0), spec.get("b", 100.0)
     elif spec["kind"] == "shell":
         L.shell_r0, L.shell_w = spec.get("r0", 5.0), spec.get("w", 1.0)
+    elif spec["kind"] == "callback":
+        fn = spec["fn"]
+
+        def _call(user, theta, n, d, out):
+            # marshalling only: numpy views of the library's host arrays
+            try:
+                t = np.ctypeslib.as_array(theta, shape=(int(n), int(d)))
+                np.ctypeslib.as_array(out, shape=(int(n),))[:] = np.asarray(fn(t), dtype=np.float64)
+                return 0
+            except Exception:      # reported to the library as a failed call
+                return 1
+
+        cb = LIK_CALLBACK(_call)
+        keep.append(cb)
+        L.callback = cb
     elif spec["kind"] == "mlp":
         widths = np.ascontiguousarray(np.asarray(spec["widths"], dtype=np.int32))
         W = _f64(np.concatenate([np.asarray(w, dtype=np.float64).ravel() for w in spec["weights"]]))
@@ -201,8 +221,12 @@ def make_likelihood(spec, prec="f64"):
     return L, keep
 
 
-def ns_init(spec, n_live, cfg, prec="f64", stream=None):
-    L, keep = make_likelihood(spec, prec)
+def ns_init(spec, n_live, cfg, prec="f64", stream=None, keep=None):
+    """keep (list, optional): receives the objects a callback likelihood needs
+    for the life of the context."""
+    L, kp = make_likelihood(spec, prec)
+    if keep is not None:
+        keep.extend(kp)
     lo, hi = _f64(spec["lo"]), _f64(spec["hi"])
     ctx = C.c_void_p()
     rc = lib().ns_init(C.byref(ctx), _d(lo), _d(hi), int(spec["d"]), int(n_live), C.byref(cfg),
@@ -219,6 +243,27 @@ def ns_run(ctx, m, max_steps=2 ** 62):
     n = C.c_int64()
     rc = _check(lib().ns_run(ctx, int(m), int(max_steps), C.byref(n)), ctx, "ns_run")
     return rc, n.value
+
+
+def ns_run_many(ctxs, m, max_steps=2 ** 62):
+    """Run the contexts ctxs (a list of ns_ctx handles) to their stopping rule
+    at once; returns (status, steps per context)."""
+    R = len(ctxs)
+    arr = (C.c_void_p * R)(*[c.value if isinstance(c, C.c_void_p) else c for c in ctxs])
+    st = np.zeros(R, dtype=np.int64)
+    rc = lib().ns_run_many(arr, R, int(m), int(max_steps), st.ctypes.data_as(_i64p))
+    if rc < 0:
+        for c in ctxs:
+            msg = lib().ns_last_error(c).decode(errors="replace")
+            if msg:
+                raise NsError(f"ns_run_many: {STATUS.get(rc, rc)}: {msg}")
+        raise NsError(f"ns_run_many: {STATUS.get(rc, rc)}: {lib().ns_last_error(None).decode(errors='replace')}")
+    return rc, st
+
+
+def run_many(samplers, m, max_steps=2 ** 62):
+    """ns_run_many over Sampler objects."""
+    return ns_run_many([s.ctx for s in samplers], m, max_steps)
 
 
 def ns_sync(ctx):
@@ -451,7 +496,8 @@ class Sampler:
             setattr(c, k, v)
         self.cfg = c
         self.T = c.hist_cap
-        self.ctx = ns_init(spec, n_live, c, prec=prec, stream=stream)
+        self._keep = [stream]
+        self.ctx = ns_init(spec, n_live, c, prec=prec, stream=stream, keep=self._keep)
 
     def step(self, m):
         return ns_step_batch(self.ctx, m)

@@ -70,9 +70,11 @@ def test_c2_fp32_tree_after_a_run_equals_oracle_tree():
     reclusters first builds the tree of the live set read just before it."""
     spec = W.likelihood(2)
     s = _c2_sampler(1)
-    s.run(50, max_steps=250)          # past log X = -25, where the valley splits into clusters
+    s.run(50, max_steps=150)          # past log X = -15; the valley splits into clusters later on
     compared = splits = 0
-    for _ in range(6):
+    for _ in range(300):
+        if splits >= 2:
+            break
         lv = s.live()
         n_cl = s.stats()["clusterings"]
         s.step(50)
@@ -97,7 +99,7 @@ def test_c2_fp32_tree_after_a_run_equals_oracle_tree():
         compared += 1
         splits += int(t["accepted"].sum() > 1)
     print(f"C2 trees compared: {compared}, with more than one cluster: {splits}")
-    assert compared >= 2 and splits >= 1
+    assert splits >= 2
     assert spec["d"] == 10
 
 
