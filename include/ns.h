@@ -136,6 +136,13 @@ typedef struct {
                               kernel per step                                           */
   int stepout_spec;        /* batched rounds: stepping-out offsets per side per round; 4 */
   int shrink_spec;         /* batched rounds: shrink proposals per round; 8             */
+  int fused_chains;        /* network likelihoods: 1 (default) runs a step's chains in
+                              one persistent launch whose workgroups evaluate their own
+                              rows through the network (FP32 state, split-bfloat16
+                              layers, stepout_spec <= 4, shrink_spec <= 8, hidden
+                              widths 256 or 512; otherwise, and with the learned
+                              screen, the batched-rounds driver); 0: always the
+                              batched-rounds driver (the same results)              */
 } ns_config;
 
 typedef struct {

@@ -9,7 +9,8 @@ import sys
 from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["k_select.hip", "k_select_large.hip", "k_slice.hip", "k_slice_rounds.hip", "k_gemm.hip", "k_surrogate.hip",
+SOURCES = ["k_select.hip", "k_select_large.hip", "k_slice.hip", "k_slice_rounds.hip", "k_emu_chains.hip",
+           "k_gemm.hip", "k_surrogate.hip",
            "k_cluster.hip", "k_cluster_large.hip", "k_correct.hip", "ns_api.hip"]
 LIB = os.path.join(HERE, "libns.so")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-ffp-contract=off",

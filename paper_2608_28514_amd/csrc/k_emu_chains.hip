@@ -1,0 +1,606 @@
+// k_emu_chains.hip -- slice sampling (Sec. 2.2, thresholds of Sec. 3.1) with
+// a dense-network likelihood (the emulator of Sec. 5) in one persistent launch
+// per step.
+//
+// A workgroup owns kEC chains and takes them through all their slice
+// iterations.  Each round every chain proposes kEP points -- stepping-out
+// offsets or a run of shrink proposals, exactly as the batched-rounds driver
+// (k_slice_rounds.hip) does -- and the workgroup evaluates its kEC * kEP rows
+// through the whole network itself: the activations stay in LDS as three
+// bfloat16 planes (hi, mid, lo) in the fragment-major layout, the weights are
+// read from L2, the chi^2 is fused into the output layer.  Chains are
+// independent within a step, so no workgroup ever waits for another: a step's
+// rounds need no launches and no device-wide synchronisation.
+//
+// Every 16 x 16 output tile is accumulated from the same operand fragments in
+// the same order as the layer kernels of k_gemm.hip (K steps ascending; term
+// pairs by decreasing pa + pb, then pa), with the same bias, tanh, split and
+// chi^2 butterfly, and a row's chi^2 partials are summed in column-block
+// order; the chain decisions, draws, counts and history are the rounds
+// driver's.  A run is therefore identical to one on the rounds driver.
+#include "ns_internal.hpp"
+#include "ns_gemm.hpp"
+#include "ns_rounds.hpp"
+
+namespace ns {
+
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+
+// Two chains of eight rows fill one 16-row MFMA block: a batch of m chains
+// runs on m/2 workgroups (one per CU up to 512 chains), each evaluating 16
+// rows a round.
+constexpr int kEC = 2;                 // chains per workgroup (waves 0 .. kEC-1 run them)
+constexpr int kEW = 8;                 // waves per workgroup (all evaluate the network)
+constexpr int kEP = 8;                 // rows per chain and round
+constexpr int kER = kEC * kEP;         // rows per round
+constexpr int kERB = kER / 16;         // row blocks
+constexpr int kEMaxW = 64 * kEW;       // widest hidden layer held in LDS (512)
+constexpr int kEMaxOutB = 64;          // output column blocks of 32 (width <= 2048)
+static_assert(kER % 16 == 0 && kEC <= kEW, "whole row blocks, a wave per chain");
+
+// the network, as the layer kernels see it
+struct EmuNet {
+  int n_layers;
+  int act;               // hidden activation
+  int widths[9];
+  const __bf16* Wf[8];   // fragment-major W^T; layer 0: three planes of widths[1] x 32
+  const float* b[8];
+  const double* data;
+  const double* isig;
+};
+
+struct EmuArgs {
+  RoundsParams p;
+  EmuNet net;
+  const float* u;
+  const double* logL;
+  const int* label;
+  const float* chol;
+  const int* seeds;
+  const double* tau;
+  const double* LW;
+  float* new_u;
+  double* new_logL;
+  int* chain_stat;
+  double* hist_logL;
+  float* hist_u;
+  int* hist_n;
+  const RunState* st;
+  unsigned long long* net_rows;
+};
+
+// LDS ordering inside one wave (chain logic): every lane's earlier LDS writes
+// are visible to the wave's later LDS reads.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ float emu_act(int act, float z) {
+  if (act == kActTanh) return tanhf(z);
+  if (act == kActSilu) return z / (1.0f + expf(-z));
+  return z;
+}
+
+struct EmuShared {
+  __attribute__((aligned(16))) __bf16 act[3 * kER * kEMaxW];   // activations, 3 planes of kER x width
+  __attribute__((aligned(16))) __bf16 xin[3 * kER * 32];       // network input, 3 planes of kER x 32
+  double part[kER * kEMaxOutB];                                // chi^2 partials, [row][column block]
+  double rl[kER];                                              // row log-likelihoods of the last round
+  int rflag[kER];                                              // row inside the box
+  ChainState<float> S[kEC];
+  float pts[kEC][kEP][kMaxD];                                  // the rows' points (state precision)
+  float zs[kEC][kMaxD];
+  float Us[kEC][64];
+  float toff[kEC][64];
+  int has[kEC][64];
+  int done[kEC];
+  unsigned long long rows;
+};
+
+// ---------------------------------------------------------------- chain logic
+// One round of chain j on wave w (64 lanes): consume the likelihoods of the
+// rows it proposed in the previous round, then propose the next kEP rows.
+__device__ __forceinline__ void emu_chain_round(const EmuArgs& A, EmuShared& sh, int w, int j, int round, uint32_t step) {
+  const RoundsParams& p = A.p;
+  const int lane = threadIdx.x & 63;
+  const int d = p.d, m = p.m, TH = p.T;
+  ChainState<float>& S = sh.S[w];
+  const double tau_j = A.tau[j], tau_e = A.LW[0];
+  const float w_ = static_cast<float>(p.w);
+  const int myrow = w * kEP + min(lane, kEP - 1);
+  const int fl = round > 0 ? sh.rflag[myrow] : 0;
+  const double rl = round > 0 ? sh.rl[myrow] : -INFINITY;
+
+  if (round == 0) {
+    if (lane == 0) {
+      const int s = A.seeds[j];
+      S.it = 0; S.phase = kPhaseDir; S.ka = -1; S.kb = -1; S.base = 0; S.s0 = 0; S.hn = 0;
+      S.n_evals = 0; S.n_oob = 0; S.n_so = 0; S.n_sh = 0; S.n_scr = 0; S.label = A.label[s];
+      S.lx = A.logL[s];
+      S.seed_slot = s;
+    }
+    wave_sync();
+    if (lane < d) S.x[lane] = A.u[static_cast<long>(S.seed_slot) * d + lane];
+    wave_sync();
+  }
+
+  // ---------------------------------------------------------------- consume
+  if (round > 0 && S.phase == kPhaseStepout) {
+    const int E = p.so_spec;
+    const bool left = lane < E;
+    const int k = S.base + (left ? lane : lane - E);
+    const bool active = lane < 2 * E && (left ? S.ka < 0 : S.kb < 0) && k < p.max_stepout;
+    const bool inb = active && fl != 0;
+    const bool pass = inb && rl > tau_e;
+    const uint64_t mp = __ballot(pass);
+    const uint64_t mo = __ballot(active && !inb);
+    int kside[2] = {S.ka, S.kb};
+    int ne = 0, no = 0, nso = 0;
+    const uint32_t emask = (E >= 32) ? 0xffffffffu : ((1u << E) - 1u);
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      int& kk = kside[side];
+      if (kk >= 0) continue;
+      const uint32_t bits = static_cast<uint32_t>(mp >> (E * side)) & emask;
+      const uint32_t obits = static_cast<uint32_t>(mo >> (E * side)) & emask;
+      const int kf = (bits == emask) ? E : __builtin_ctz(~bits);
+      if (S.base + kf >= p.max_stepout) {        // k == E_max is never evaluated
+        ne += p.max_stepout - S.base;
+        nso += 1;
+        kk = p.max_stepout;
+      } else if (kf < E) {
+        const uint32_t o = (obits >> kf) & 1u;
+        ne += kf + (o ? 0 : 1);
+        no += o;
+        kk = S.base + kf;
+      } else {
+        ne += E;
+      }
+    }
+    const int ka = kside[0], kb = kside[1];
+    wave_sync();
+    if (lane == 0) {
+      S.ka = ka; S.kb = kb;
+      S.n_evals += ne; S.n_oob += no; S.n_so += nso;
+      if (ka >= 0 && kb >= 0) {
+        S.a = S.a0 - static_cast<float>(ka) * w_;
+        S.b = S.b0 + static_cast<float>(kb) * w_;
+        S.phase = kPhaseShrink;
+        S.s0 = 0;
+      } else {
+        S.base += E;
+      }
+    }
+    wave_sync();
+  } else if (round > 0 && S.phase == kPhaseShrink) {
+    const int Sn = min(p.sh_spec, p.max_shrink - S.s0);
+    const bool mine = lane < Sn;
+    const bool inb = mine && fl != 0;
+    const double l = inb ? rl : -INFINITY;
+    const bool pass = mine && l > tau_j;
+    const uint64_t mp = __ballot(pass);
+    const uint64_t mi = __ballot(inb);
+    const int upto = mp ? __builtin_ctzll(mp) : Sn - 1;
+    const uint64_t taken = (upto >= 63) ? ~0ull : ((2ull << upto) - 1ull);
+    const bool last = (S.it == p.n_iter - 1);
+    if (last) {
+      // the proposals up to the accepted one (at most TH - 1 slots)
+      const int nh = min(upto + 1, TH - 1 - S.s0);
+      if (lane < nh) A.hist_logL[static_cast<long>(S.s0 + lane) * m + j] = l;
+      float* hu = A.hist_u + (static_cast<long>(j) * TH + S.s0) * d;
+      for (int e = lane; e < nh * d; e += 64) {
+        const int q = e / d;
+        hu[e] = sh.pts[w][q][e - q * d];
+      }
+    }
+    if (mp) {
+      // the accepted point, recomputed from the chain's line exactly as it was
+      // proposed (same draws, same bracket recurrence, same expression)
+      const uint32_t c3 = (kStreamSlice << 24) | static_cast<uint32_t>(S.it);
+      if (lane <= upto) {
+        const Draw2 du = uniform2(p.seed, kSlotShrink0 + S.s0 + lane, static_cast<uint32_t>(j), step, c3);
+        sh.Us[w][lane] = static_cast<float>(du.a);
+      }
+      wave_sync();
+      float aa = S.a, bb = S.b, t = 0.f;
+      for (int q = 0; q <= upto; ++q) {
+        t = aa + sh.Us[w][q] * (bb - aa);
+        if (t < 0.f) aa = t; else bb = t;
+      }
+      if (lane < d) S.x[lane] = S.x[lane] + t * S.v[lane];
+      if (lane == upto) S.lx = l;
+    }
+    wave_sync();
+    if (lane == 0) {
+      S.n_evals += __popcll(mi & taken);
+      S.n_oob += (upto + 1) - __popcll(mi & taken);
+      if (last) S.hn = min(S.s0 + upto + 1, TH - 1);
+      bool next_iter = false;
+      if (mp) {
+        next_iter = true;
+      } else {
+        S.a = S.br_a;
+        S.b = S.br_b;
+        S.s0 += Sn;
+        if (S.s0 >= p.max_shrink) { S.n_sh += 1; next_iter = true; }
+      }
+      if (next_iter) {
+        S.it += 1;
+        S.phase = (S.it >= p.n_iter) ? kPhaseDone : kPhaseDir;
+      }
+    }
+    wave_sync();
+    if (S.phase == kPhaseDone) {
+      if (lane < d) {
+        A.new_u[static_cast<long>(j) * d + lane] = S.x[lane];
+        A.hist_u[(static_cast<long>(j) * TH + (TH - 1)) * d + lane] = S.x[lane];
+      }
+      if (lane == 0) {
+        A.new_logL[j] = S.lx;
+        A.hist_logL[static_cast<long>(TH - 1) * m + j] = S.lx;
+        A.hist_n[j] = S.hn;
+        A.chain_stat[kStatW * j + 0] = S.n_evals;
+        A.chain_stat[kStatW * j + 1] = S.n_oob;
+        A.chain_stat[kStatW * j + 2] = S.n_so;
+        A.chain_stat[kStatW * j + 3] = S.n_sh;
+        A.chain_stat[kStatW * j + 4] = 0;
+      }
+    }
+  }
+  wave_sync();
+
+  // ---------------------------------------------------------------- propose
+  if (S.phase == kPhaseDir) {
+    const uint32_t c3 = (kStreamSlice << 24) | static_cast<uint32_t>(S.it);
+    if (2 * lane < d) {
+      const Draw2 dr = uniform2(p.seed, kSlotDir0 + lane, static_cast<uint32_t>(j), step, c3);
+      const float r = DirMath<float>::r_of(static_cast<float>(dr.a));
+      const float ang = static_cast<float>(6.283185307179586) * static_cast<float>(dr.b);
+      float sn, csn;
+      DirMath<float>::sc(ang, &sn, &csn);
+      sh.zs[w][2 * lane] = r * csn;
+      if (2 * lane + 1 < d) sh.zs[w][2 * lane + 1] = r * sn;
+    }
+    wave_sync();
+    float nrm = 0.f;
+    for (int i = 0; i < d; ++i) nrm += sh.zs[w][i] * sh.zs[w][i];
+    nrm = DirMath<float>::sq(nrm);
+    if (lane < d) {
+      // row `lane` of the cluster's Cholesky factor (L2-resident), its loads
+      // issued together
+      const float* Lr = A.chol + static_cast<long>(S.label) * kMaxD * kMaxD + lane * kMaxD;
+      float Lrow[kMaxD];
+#pragma unroll
+      for (int k = 0; k < kMaxD; ++k) Lrow[k] = k <= lane ? Lr[k] : 0.f;
+      float acc = 0.f;
+#pragma unroll
+      for (int k = 0; k < kMaxD; ++k)
+        if (k <= lane) acc += Lrow[k] * (sh.zs[w][k] / nrm);
+      S.v[lane] = acc;
+    }
+    if (lane == 0) {
+      const Draw2 d0 = uniform2(p.seed, kSlotStepout, static_cast<uint32_t>(j), step, c3);
+      S.a0 = -w_ * static_cast<float>(d0.a);
+      S.b0 = S.a0 + w_;
+      S.ka = -1; S.kb = -1; S.base = 0;
+      S.phase = kPhaseStepout;
+    }
+    wave_sync();
+  }
+  bool has = false, inb = false;
+  float toff = 0.f;   // proposal = x + toff v
+  if (S.phase == kPhaseStepout) {
+    const int E = p.so_spec;
+    const bool left = lane < E;
+    const int k = S.base + (left ? lane : lane - E);
+    has = lane < 2 * E && (left ? S.ka < 0 : S.kb < 0) && k < p.max_stepout;
+    if (has) {
+      toff = left ? S.a0 - static_cast<float>(k) * w_ : S.b0 + static_cast<float>(k) * w_;
+      inb = line_in_box(S.x, S.v, toff, d);
+    }
+  } else if (S.phase == kPhaseShrink) {
+    const uint32_t c3 = (kStreamSlice << 24) | static_cast<uint32_t>(S.it);
+    const int Sn = min(p.sh_spec, p.max_shrink - S.s0);
+    if (lane < Sn) {
+      const Draw2 du = uniform2(p.seed, kSlotShrink0 + S.s0 + lane, static_cast<uint32_t>(j), step, c3);
+      sh.Us[w][lane] = static_cast<float>(du.a);
+    }
+    wave_sync();
+    if (lane < Sn) {
+      float aa = S.a, bb = S.b, t = 0.f;
+      for (int q = 0; q <= lane; ++q) {
+        t = aa + sh.Us[w][q] * (bb - aa);
+        if (t < 0.f) aa = t; else bb = t;
+      }
+      toff = t;
+      has = true;
+      inb = line_in_box(S.x, S.v, t, d);
+      if (lane == Sn - 1) { S.br_a = aa; S.br_b = bb; }
+    }
+  }
+  if (lane < kEP) {
+    sh.rflag[w * kEP + lane] = inb ? 1 : 0;
+    sh.toff[w][lane] = toff;
+    sh.has[w][lane] = has ? 1 : 0;
+  }
+  // network rows counted as the rounds driver counts them: kEP per chain with
+  // a row inside the box
+  const uint64_t any = __ballot(lane < kEP && inb);
+  if (lane == 0 && any) atomicAdd(&sh.rows, static_cast<unsigned long long>(kEP));
+  wave_sync();
+  // the rows' points and their network input (theta in three bfloat16 terms)
+  for (int e = lane; e < kEP * d; e += 64) {
+    const int q = e / d, i = e - q * d;
+    if (!sh.has[w][q]) continue;
+    const float yi = S.x[i] + sh.toff[w][q] * S.v[i];
+    sh.pts[w][q][i] = yi;
+    const float xv = p.lo_f[i] + p.span_f[i] * yi;
+    const long fi = frag_index(w * kEP + q, i, 32);
+    const __bf16 h = static_cast<__bf16>(xv);
+    const float r1 = xv - static_cast<float>(h);
+    const __bf16 mm = static_cast<__bf16>(r1);
+    sh.xin[fi] = h;
+    sh.xin[kER * 32 + fi] = mm;
+    sh.xin[2 * kER * 32 + fi] = static_cast<__bf16>(r1 - static_cast<float>(mm));
+  }
+  if (lane == 0) sh.done[w] = S.phase == kPhaseDone ? 1 : 0;
+  wave_sync();
+}
+
+// ---------------------------------------------------------------- network
+// One pass of a wave over NCB column blocks (cb0 .. cb0 + NCB - 1, two 16-wide
+// tiles each) of both row blocks, K in steps of 32.  A: LDS planes (stride
+// apl), fragment-major with S = K/32 steps; Wf: global, fragment-major W^T
+// (tile ct at (ct S + s) 512), WS weight planes of stride wpl.
+template <int NCB, int WS>
+__device__ __forceinline__ void emu_pass(const __bf16* Al, int apl, int S, const __bf16* __restrict__ Wf, long wpl,
+                                         int cb0, f32x4 (&acc)[kERB][NCB][2]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int r = 0; r < kERB; ++r)
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) acc[r][c][0] = acc[r][c][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const __bf16* bp = Wf + static_cast<long>(2 * cb0) * S * 512 + lane * 8;
+  const long tstep = static_cast<long>(S) * 512;   // next column tile
+  // weight fragments of three K steps in registers: two steps of loads in
+  // flight while one is multiplied
+  bf16x8 b0[NCB][2][WS], b1[NCB][2][WS], b2[NCB][2][WS];
+  auto loadb = [&](int s, bf16x8 (&b)[NCB][2][WS]) {
+#pragma unroll
+    for (int c = 0; c < NCB; ++c)
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int q = 0; q < WS; ++q)
+          b[c][t][q] = *reinterpret_cast<const bf16x8*>(bp + (2 * c + t) * tstep + q * wpl + static_cast<long>(s) * 512);
+  };
+  auto step = [&](int s, const bf16x8 (&b)[NCB][2][WS]) {
+    bf16x8 a[kERB][3];
+#pragma unroll
+    for (int r = 0; r < kERB; ++r)
+#pragma unroll
+      for (int pa = 0; pa < 3; ++pa)
+        a[r][pa] = *reinterpret_cast<const bf16x8*>(Al + pa * apl + (r * S + s) * 512 + lane * 8);
+    // term pairs (activation pa, weight pb) by decreasing pa + pb, then pa
+#pragma unroll
+    for (int sum = 2 + WS - 1; sum >= 0; --sum)
+#pragma unroll
+      for (int pa = 2; pa >= 0; --pa) {
+        const int pb = sum - pa;
+        if (pb < 0 || pb >= WS) continue;
+#pragma unroll
+        for (int r = 0; r < kERB; ++r)
+#pragma unroll
+          for (int c = 0; c < NCB; ++c) {
+            acc[r][c][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r][pa], b[c][0][pb], acc[r][c][0], 0, 0, 0);
+            acc[r][c][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r][pa], b[c][1][pb], acc[r][c][1], 0, 0, 0);
+          }
+      }
+  };
+  loadb(0, b0);
+  if (S > 1) loadb(1, b1);
+  for (int s = 0; s < S; s += 3) {
+    if (s + 2 < S) loadb(s + 2, b2);
+    step(s, b0);
+    if (s + 1 >= S) break;
+    if (s + 3 < S) loadb(s + 3, b0);
+    step(s + 1, b1);
+    if (s + 2 >= S) break;
+    if (s + 4 < S) loadb(s + 4, b1);
+    step(s + 2, b2);
+  }
+}
+
+// act(z + bias) of a pass's tiles into the activation planes (width N).
+template <int NCB>
+__device__ __forceinline__ void emu_store_hidden(EmuShared& sh, int N, int cb0, const float* __restrict__ bias,
+                                                 int act, const f32x4 (&acc)[kERB][NCB][2]) {
+  const int lane = threadIdx.x & 63;
+  const int apl = kER * N;
+#pragma unroll
+  for (int c = 0; c < NCB; ++c)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int n = (cb0 + c) * 32 + t * 16 + (lane & 15);
+      const float bz = bias ? bias[n] : 0.f;
+#pragma unroll
+      for (int r = 0; r < kERB; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = r * 16 + 4 * (lane >> 4) + i;
+          const float x = emu_act(act, acc[r][c][t][i] + bz);
+          const __bf16 h = static_cast<__bf16>(x);
+          const float r1 = x - static_cast<float>(h);
+          const __bf16 md = static_cast<__bf16>(r1);
+          const long fi = frag_index(row, n, N);
+          sh.act[fi] = h;
+          sh.act[apl + fi] = md;
+          sh.act[2 * apl + fi] = static_cast<__bf16>(r1 - static_cast<float>(md));
+        }
+    }
+}
+
+// chi^2 partials of a pass's column blocks: every row's sum over the block's
+// 32 columns of ((y + bias - data) isig)^2, FP64, with the layer kernels'
+// butterfly.
+template <int NCB>
+__device__ __forceinline__ void emu_store_chi2(EmuShared& sh, int nb, int cb0, const float* __restrict__ bias,
+                                               const double* __restrict__ data, const double* __restrict__ isig,
+                                               const f32x4 (&acc)[kERB][NCB][2]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int c = 0; c < NCB; ++c) {
+    const int n0 = (cb0 + c) * 32 + (lane & 15);
+    const float bz0 = bias ? bias[n0] : 0.f, bz1 = bias ? bias[n0 + 16] : 0.f;
+    const double d0 = data[n0], d1 = data[n0 + 16], s0 = isig[n0], s1 = isig[n0 + 16];
+#pragma unroll
+    for (int r = 0; r < kERB; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double e0 = (static_cast<double>(acc[r][c][0][i] + bz0) - d0) * s0;
+        const double e1 = (static_cast<double>(acc[r][c][1][i] + bz1) - d1) * s1;
+        double t = e0 * e0 + e1 * e1;
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) t += __shfl_xor(t, o);
+        const int row = r * 16 + 4 * (lane >> 4) + i;
+        if ((lane & 15) == 0) sh.part[row * kEMaxOutB + cb0 + c] = t;
+      }
+  }
+}
+
+// One layer over all kER rows: the column blocks are dealt to the kEW waves,
+// NCB per pass.  First layer: input from xin (K = 32, weights in three
+// planes); hidden layers: input from and output to the activation planes
+// (in place, after every wave has read its input); output layer: chi^2.
+template <int NCB>
+__device__ __forceinline__ void emu_layer(EmuShared& sh, const EmuNet& net, int l) {
+  const int wave = threadIdx.x >> 6;
+  const int L = net.n_layers;
+  const int N = net.widths[l + 1];
+  const int nb = N >> 5;
+  f32x4 acc[kERB][NCB][2];
+  if (l == 0) {
+    for (int cb0 = wave * NCB; cb0 < nb; cb0 += kEW * NCB) {
+      emu_pass<NCB, 3>(sh.xin, kER * 32, 1, net.Wf[0], static_cast<long>(N) * 32, cb0, acc);
+      if (L == 1) emu_store_chi2<NCB>(sh, nb, cb0, net.b[0], net.data, net.isig, acc);
+      else emu_store_hidden<NCB>(sh, N, cb0, net.b[0], net.act, acc);
+    }
+    __syncthreads();
+    return;
+  }
+  const int K = net.widths[l];
+  const int S = K >> 5;
+  if (l == L - 1) {
+    for (int cb0 = wave * NCB; cb0 < nb; cb0 += kEW * NCB) {
+      emu_pass<NCB, 1>(sh.act, kER * K, S, net.Wf[l], 0L, cb0, acc);
+      emu_store_chi2<NCB>(sh, nb, cb0, net.b[l], net.data, net.isig, acc);
+    }
+    __syncthreads();
+    return;
+  }
+  // hidden layer, in place: every wave's column blocks in one pass (N <= kEW * NCB * 32)
+  const int cb0 = wave * NCB;
+  const bool mine = cb0 < nb;
+  if (mine) emu_pass<NCB, 1>(sh.act, kER * K, S, net.Wf[l], 0L, cb0, acc);
+  __syncthreads();
+  if (mine) emu_store_hidden<NCB>(sh, N, cb0, net.b[l], net.act, acc);
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(64 * kEW)
+k_emu_chains(EmuArgs A) {
+  __shared__ EmuShared sh;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const RunState* st = A.st;
+  if (st->done) return;
+  const uint32_t step = static_cast<uint32_t>(st->step);
+  const int j0 = blockIdx.x * kEC;
+  const int nchain = min(kEC, A.p.m - j0);
+  // inputs beyond the first d columns stay zero; rows of absent chains never
+  // reach an output
+  for (int q = threadIdx.x; q < 3 * kER * 32; q += 64 * kEW) sh.xin[q] = static_cast<__bf16>(0.f);
+  if (threadIdx.x < kER) { sh.rflag[threadIdx.x] = 0; sh.rl[threadIdx.x] = -INFINITY; }
+  if (threadIdx.x < kEC) sh.done[threadIdx.x] = threadIdx.x < nchain ? 0 : 1;
+  if (threadIdx.x == 0) sh.rows = 0ull;
+  __syncthreads();
+  const int L = A.net.n_layers;
+  const int nbo = A.net.widths[L] >> 5;
+  for (int round = 0;; ++round) {
+    if (wave < nchain && !sh.done[wave]) emu_chain_round(A, sh, wave, j0 + wave, round, step);
+    __syncthreads();
+    int alive = 0;
+#pragma unroll
+    for (int c = 0; c < kEC; ++c) alive += sh.done[c] ? 0 : 1;
+    if (alive == 0) break;
+    // the kER rows through the network (hidden layers 256 or 512 wide: one
+    // or two column blocks per wave; output layer two per pass)
+    emu_layer<1>(sh, A.net, 0);
+    for (int l = 1; l < L; ++l) {
+      if (l == L - 1) emu_layer<2>(sh, A.net, l);
+      else if (A.net.widths[l + 1] == 32 * kEW) emu_layer<1>(sh, A.net, l);
+      else emu_layer<2>(sh, A.net, l);
+    }
+    // row log-likelihoods: the partials summed in column-block order
+    if (threadIdx.x < kER) {
+      const int r = threadIdx.x;
+      double t = 0.0;
+      for (int q = 0; q < nbo; ++q) t += sh.part[r * kEMaxOutB + q];
+      const double v = -0.5 * t;
+      sh.rl[r] = (sh.rflag[r] == 0 || isnan(v)) ? -INFINITY : v;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && A.net_rows && sh.rows) atomicAdd(A.net_rows, sh.rows);
+  (void)lane;
+}
+
+bool emu_chains_eligible(const NetDev& net, const RoundsParams& p, int state_f32) {
+  if (!state_f32 || p.P != kEP || 2 * p.so_spec > kEP || p.sh_spec > kEP || p.d > kMaxD) return false;
+  const int L = net.n_layers;
+  if (L < 2 || L > 8 || net.widths[0] > 32) return false;
+  for (int l = 1; l < L; ++l)   // hidden widths: one pass of one or two column blocks per wave
+    if (net.widths[l] != 32 * kEW && net.widths[l] != 64 * kEW) return false;
+  if (net.widths[L] % (32 * kEW * 2) != 0 || net.widths[L] > 32 * kEMaxOutB) return false;
+  for (int l = 0; l < L; ++l)
+    if (!net.Wf[l]) return false;
+  return true;
+}
+
+hipError_t launch_emu_chains(const RoundsParams& p, const NetDev& net, const double* data, const double* isig,
+                             const Shape& sh, const DevBufs& b, unsigned long long* net_rows, hipStream_t s) {
+  EmuArgs A{};
+  A.p = p;
+  A.net.n_layers = net.n_layers;
+  A.net.act = net.act;
+  for (int l = 0; l <= net.n_layers; ++l) A.net.widths[l] = net.widths[l];
+  for (int l = 0; l < net.n_layers; ++l) {
+    A.net.Wf[l] = net.Wf[l];
+    A.net.b[l] = net.b[l];
+  }
+  A.net.data = data;
+  A.net.isig = isig;
+  A.u = static_cast<const float*>(b.u);
+  A.logL = b.logL;
+  A.label = b.label;
+  A.chol = b.chol_f;
+  A.seeds = b.seeds;
+  A.tau = b.tau;
+  A.LW = b.LW;
+  A.new_u = static_cast<float*>(b.new_u);
+  A.new_logL = b.new_logL;
+  A.chain_stat = b.chain_stat;
+  A.hist_logL = b.hist_logL;
+  A.hist_u = static_cast<float*>(b.hist_u);
+  A.hist_n = b.hist_n;
+  A.st = b.st;
+  A.net_rows = net_rows;
+  (void)sh;
+  const int grid = (p.m + kEC - 1) / kEC;
+  hipLaunchKernelGGL(k_emu_chains, dim3(grid), dim3(64 * kEW), 0, s, A);
+  return hipGetLastError();
+}
+
+}  // namespace ns

@@ -56,6 +56,7 @@ struct ns_ctx {
   double* mlp_data = nullptr;
   double* mlp_isig = nullptr;
   bool emu_frag = false;      // emulator likelihood on the fragment-major path (emu_forward_logL)
+  bool emu_chains = false;    // a step's chains in one persistent launch (k_emu_chains)
   // host likelihood (NS_LIK_CALLBACK): rows staged through pinned memory
   ns_lik_callback cb = nullptr;
   void* cb_user = nullptr;
@@ -592,6 +593,7 @@ ns_status ns_config_default(ns_config* cfg) {
   cfg->batch_rounds = 0;
   cfg->stepout_spec = 4;
   cfg->shrink_spec = 8;
+  cfg->fused_chains = 1;
   return NS_OK;
 }
 
@@ -866,6 +868,8 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
       NS_INIT_HIP(hipMemsetAsync(rb.rthr, 0, sizeof(double) * rb.rows_cap, c->stream));
       NS_INIT_HIP(hipMemsetAsync(c->s_norm, 0, sizeof(float) * kNormLen, c->stream));
     }
+    c->emu_chains = c->is_mlp && c->emu_frag && cfg->fused_chains != 0 &&
+                    emu_chains_eligible(c->net, rp, sh.state_f32);
     NS_INIT_HIP(launch_init_rows(n_live, d, cfg->seed, rp, sh.state_f32, b.u, rb.pts, rb.xin, rb.flag,
                                  c->stream));
     NS_INIT_TRY(eval_rows(c, n_live, nullptr));
@@ -947,7 +951,12 @@ ns_status ns_step_batch(ns_ctx* c, int m) {
   p.max_shrink = c->cfg.max_shrink;
   p.corr = corr;
   p.seed = c->cfg.seed;
-  if (c->batched) {
+  if (c->batched && c->emu_chains && !c->surr) {
+    RoundsParams rp = c->rp;
+    rp.m = m;
+    TimeScope ts(c, NS_TIME_SLICE);
+    NS_TRY(launch_emu_chains(rp, c->net, c->mlp_data, c->mlp_isig, c->sh, c->b, &c->d_sc->emu_rows, c->stream));
+  } else if (c->batched) {
     ns_status r = run_rounds(c, m);
     if (r != NS_OK) return r;
   } else {

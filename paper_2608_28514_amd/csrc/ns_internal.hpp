@@ -25,7 +25,7 @@ struct DevBufs {
   double* hist_logL;    // T x M (row t, column chain)
   void* hist_u;         // M x T x d
   int* hist_n;          // M
-  void* draws;          // M x n_iter x (d + 33): per-iteration draw blocks of the slice kernel
+  void* draws;          // M x n_iter x (d + kDrawExtra): per-iteration draw blocks of the slice kernel
   // cluster tree
   int* nodeof;          // N: deepest tree node of each point
   int* count;           // nodes

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include "ns_internal.hpp"
+#include "ns_gemm.hpp"
 
 namespace ns {
 
@@ -66,6 +67,13 @@ hipError_t launch_rows_from_points(long n, int d, const double* u, const RoundsP
                                    int state_f32, void* pts, float* xin, int* flag, hipStream_t s);
 hipError_t launch_init_rows(int N, int d, uint64_t seed, const RoundsParams& p, int state_f32, void* u,
                             void* pts, float* xin, int* flag, hipStream_t s);
+// A step's chains with a network likelihood in one persistent launch
+// (k_emu_chains.hip): same results as the rounds driver.  Eligible for FP32
+// state, split-bfloat16 fragment-major layers, P = 8 rows per chain and round,
+// hidden widths 256 or 512, output width a multiple of 512 up to 2048.
+bool emu_chains_eligible(const NetDev& net, const RoundsParams& p, int state_f32);
+hipError_t launch_emu_chains(const RoundsParams& p, const NetDev& net, const double* data, const double* isig,
+                             const Shape& sh, const DevBufs& b, unsigned long long* net_rows, hipStream_t s);
 // analytic likelihood on rows (the batched driver with an analytic family)
 hipError_t launch_rows_loglike(const Shape& sh, const LikDev& lik, long n, const void* pts,
                                const int* flag, double* out, const int* gate, hipStream_t s);

@@ -46,7 +46,8 @@ class NsConfig(C.Structure):
                 ("recluster_every", C.c_int), ("kmeans_iters", C.c_int), ("correction", C.c_int),
                 ("history_iters", C.c_int), ("hist_cap", C.c_int), ("state_prec", C.c_int),
                 ("stop_frac", C.c_double), ("eig_floor", C.c_double), ("seed", C.c_uint64),
-                ("batch_rounds", C.c_int), ("stepout_spec", C.c_int), ("shrink_spec", C.c_int)]
+                ("batch_rounds", C.c_int), ("stepout_spec", C.c_int), ("shrink_spec", C.c_int),
+                ("fused_chains", C.c_int)]
 
 
 class NsStats(C.Structure):

@@ -6,10 +6,10 @@ Eq. (1) with the oracle's FP64 likelihood, +-0.0024).
   layers) moves the evidence by little: the reference's importance samples
   re-weighted with the GPU likelihood give log Z within 0.05 of the FP64
   value.
-* Complete GPU runs of the full-width network (N = 500, m = 100; both layer
+* Complete GPU runs of workload 4 (N = 2000, m = 200; both layer
   precisions) give log Z within 2 sigma of the reference, sigma =
-  sqrt(sigma_run^2 + se_ref^2), sigma_run = sqrt(H/N).  The benchmark runs the
-  N = 4000, m = 400 workload to the same gate.
+  sqrt(sigma_run^2 + se_ref^2), sigma_run = sqrt(H/N).  The benchmark runs
+  workload 5 (N = 4000, m = 400) to the same gate.
 """
 import json
 import math
@@ -77,8 +77,8 @@ def test_gpu_likelihood_arithmetic_moves_the_evidence_little(prec):
 @pytest.mark.parametrize("prec", ["bf16x3", "f32"])
 def test_full_width_run_within_2_sigma_of_reference(prec):
     spec = W.likelihood(4, seed=0)
-    s = native.Sampler(spec, 500, prec=prec, state="f32", tree_depth=1, seed=1)
-    s.run(100)
+    s = native.Sampler(spec, 2000, prec=prec, state="f32", tree_depth=1, seed=1)
+    s.run(200)
     lz, sig, H = s.logZ()
     st = s.stats()
     s.close()
