@@ -91,6 +91,14 @@ def main():
     ap.add_argument("--runs", default="",
                     help="independent runs at once, e.g. 1,2,4,8,16: aggregate throughput of R concurrent runs "
                          "(one stream and host thread each) of --workload 2 or 4/5")
+    ap.add_argument("--corr-sweep", action="store_true",
+                    help="Sec. 3.2 study: batch corrections vs m/N on the 2-d Gaussian of Eq. (5)")
+    ap.add_argument("--cluster-study", action="store_true",
+                    help="Sec. 2.3 study: Tests 1-3 with and without clustering, and the Test 2 depth sweep")
+    ap.add_argument("--suite", action="store_true",
+                    help="Sec. 4 workloads: Gaussians d = 2..32, 2-d Rosenbrock and the 49-mode array vs N_live")
+    ap.add_argument("--seeds", type=int, default=0, help="study modes: runs per setting (0: the paper's count)")
+    ap.add_argument("--concurrent", type=int, default=16, help="study modes: runs at once (ns_run_many)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -109,9 +117,9 @@ def main():
         print(json.dumps({"copy_probe_bytes": 4 * n}))
         return
 
-    if args.runs:
+    if args.runs or args.corr_sweep or args.cluster_study or args.suite:
         # one hardware queue per concurrent run's stream (read when the HIP runtime starts)
-        need = max(int(r) for r in args.runs.split(","))
+        need = max(int(r) for r in args.runs.split(",")) if args.runs else args.concurrent
         os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(4, need)))
     import numpy as np
     import torch
@@ -128,6 +136,12 @@ def main():
         return bench_train_sweep(args, np, torch, native)
     if args.runs:
         return bench_runs(args, np, torch, native, workloads)
+    if args.corr_sweep:
+        return study_corrections(args, np, torch, native, workloads)
+    if args.cluster_study:
+        return study_clustering(args, np, torch, native, workloads)
+    if args.suite:
+        return study_suite(args, np, torch, native, workloads)
     if args.workload in (4, 5):
         return bench_emulator(args, np, torch, native, workloads)
     if args.workload == 2:
@@ -353,6 +367,207 @@ def bench_runs(args, np, torch, native, workloads):
                       "best_frac_of_peak": best["useful_tflops"] * 1e12 / peak,
                       "speedup_best_vs_R1": best["updates_per_s"] / res[0]["updates_per_s"] if res[0]["R"] == 1
                       else None, "sweep": res}, default=float))
+
+
+# ---------------------------------------------------------------- paper studies
+def _ensemble(native, torch, spec, N, m, seeds, streams, **kw):
+    """Complete runs of spec for the given seeds, len(streams) at a time
+    (ns_run_many, one stream and host thread per run).  Returns the per-run
+    results and the summed wall time of the batches."""
+    out, wall = [], 0.0
+    R = len(streams)
+    for i in range(0, len(seeds), R):
+        batch = seeds[i:i + R]
+        ss = [native.Sampler(spec, N, seed=int(sd), stream=streams[k], **kw) for k, sd in enumerate(batch)]
+        for x in ss:
+            native.ns_sync(x.ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        native.run_many(ss, m)
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        for sd, x in zip(batch, ss):
+            st = x.stats()
+            lz, sig, H = x.logZ()
+            out.append({"seed": int(sd), "logZ": lz, "sigma": sig, "H": H, "dead": st["dead"],
+                        "evals": st["evals"] - N, "steps": st["steps"]})
+            x.close()
+    return out, wall
+
+
+def _summ(np, runs, truth, wall=None):
+    z = np.array([r["logZ"] for r in runs])
+    d = {"runs": len(runs), "mean_err": float(z.mean() - truth), "std": float(z.std(ddof=1)) if z.size > 1 else 0.0,
+         "sem": float(z.std(ddof=1) / math.sqrt(z.size)) if z.size > 1 else 0.0,
+         "sigma_mean": float(np.mean([r["sigma"] for r in runs])),
+         "evals_mean": float(np.mean([r["evals"] for r in runs])), "dead_mean": float(np.mean([r["dead"] for r in runs]))}
+    if wall is not None:
+        d["wall_s"] = wall
+        d["updates_per_s"] = sum(r["dead"] for r in runs) / wall
+    return d
+
+
+def _oracle_runs(spec, N, m, seeds, **kw):
+    import oracle
+    oracle.set_threads(host_threads())
+    res = []
+    for sd in seeds:
+        o = oracle.Oracle(spec, N, seed=int(sd), **kw)
+        o.run(m)
+        lz, sig, H = o.logZ()
+        res.append({"seed": int(sd), "logZ": lz, "sigma": sig, "H": H, "dead": o.n_dead(),
+                    "evals": o.counters()["evals"] - N})
+    oracle.set_threads(1)
+    return res
+
+
+def study_corrections(args, np, torch, native, workloads):
+    """Sec. 3.2: log Z of the 2-d Gaussian of Eq. (5) on [-7,7]^2 (closed form
+    d/2 log 2 pi - d log 14, up to the box truncation), N = 1000, against the
+    batch fraction m/N in {0.001 ... 0.5} for (i) no correction, best-of-worst
+    thresholds, (ii) batch sorting, (iii)-(v) history correction with K = 1,
+    2, 10 iterations; 50 runs each (m = 1 is sequential nested sampling: one
+    set of runs stands for every variant).  FP64.  Oracle runs of the same
+    seeds check a subset."""
+    from scipy.special import erf
+    spec = workloads.paper_problem("eq5_gauss2d")
+    truth = 2.0 * math.log(0.5 * (erf(7 / math.sqrt(2)) - erf(-7 / math.sqrt(2))) * math.sqrt(2 * math.pi) / 14)
+    N = 1000
+    S = args.seeds or 50
+    seeds = list(range(S))
+    streams = [torch.cuda.Stream() for _ in range(args.concurrent)]
+    variants = [("none", 1), ("best_of_worst", 1), ("sort", 1), ("history", 1), ("history", 2), ("history", 10)]
+    ms = [1, 2, 5, 10, 20, 50, 100, 200, 500]
+    table = []
+    for m in ms:
+        for corr, K in (variants if m > 1 else [("history", 1)]):
+            runs, wall = _ensemble(native, torch, spec, N, m, seeds, streams, correction=corr, history_iters=K)
+            row = {"m": m, "m_over_N": m / N, "correction": corr if m > 1 else "all (m = 1)", "K": K}
+            row.update(_summ(np, runs, truth, wall))
+            table.append(row)
+            log(f"m={m:4d} {row['correction']:>14s} K={K:2d}: err {row['mean_err']:+.4f} +- {row['sem']:.4f} "
+                f"(std {row['std']:.3f}, sigma {row['sigma_mean']:.3f}), {wall:.1f} s")
+    checks = []
+    if not args.no_cpu_baseline:
+        for corr, m in (("history", 100), ("none", 100), ("sort", 500)):
+            o = _oracle_runs(spec, N, m, seeds[:16], correction=corr)
+            g = next(r for r in table if r["m"] == m and r["correction"] == corr and r["K"] == 1)
+            oz = _summ(np, o, truth)
+            checks.append({"m": m, "correction": corr, "oracle_mean_err": oz["mean_err"], "oracle_sem": oz["sem"],
+                           "gpu_mean_err": g["mean_err"], "gpu_sem": g["sem"],
+                           "diff_in_sem": (g["mean_err"] - oz["mean_err"]) / math.sqrt(g["sem"] ** 2 + oz["sem"] ** 2)})
+            log(f"oracle check {corr} m={m}: oracle {oz['mean_err']:+.4f} +- {oz['sem']:.4f}, "
+                f"GPU {g['mean_err']:+.4f} +- {g['sem']:.4f}")
+    print(json.dumps({"metric": "log Z error vs batch fraction m/N per correction (Sec. 3.2)", "truth": truth,
+                      "data": "synthetic", "config": {"workload": "eq5 gauss2d prior[-7,7]^2 N_live=1000 FP64, "
+                                                                  "depth 0, 5d slice iterations"},
+                      "seeds": S, "table": table, "oracle_checks": checks}, default=float))
+
+
+def _two_gauss_truth(d):
+    import numpy as np
+    var1 = np.array([0.1 if (i % 2 == 0) else 1.0 for i in range(d)])
+    var2 = np.array([1.0 if (i % 2 == 0) else 0.1 for i in range(d)])
+    a = math.log(0.1) + 0.5 * float(np.sum(np.log(2 * math.pi * var1)))
+    b = 0.5 * float(np.sum(np.log(2 * math.pi * var2)))
+    return float(np.logaddexp(a, b)) - d * math.log(40.0)
+
+
+def _shell_truth():
+    from scipy import integrate
+    f = lambda r: r * math.exp(-0.5 * (r - 5.0) ** 2)
+    disk = 2 * math.pi * integrate.quad(f, 0.0, 10.0, epsabs=1e-13)[0]
+    # the square's four corners beyond r = 10: at radius r they span the angle
+    # 2 pi - 8 acos(10 / r)
+    corner = integrate.quad(lambda r: f(r) * (2 * math.pi - 8 * math.acos(10.0 / r)), 10.0, 10.0 * math.sqrt(2.0),
+                            epsabs=1e-15)[0]
+    return math.log((disk + corner) / 400.0)
+
+
+def study_clustering(args, np, torch, native, workloads):
+    """Sec. 2.3, Table 1: Test 1 (Eq. (2), 49 Gaussians, [-20,20]^2, depth 6),
+    Test 2 (Eq. (3), two 10-d Gaussians, [-20,20]^10, depth 1), Test 3
+    (Eq. (4), shell, [-10,10]^2, depth 4), each with and without clustering
+    (depth 0), N = 1000, sequential (m = 1), recluster every 100 deaths, 50
+    runs (Test 2: 20); and the Test 2 depth sweep over d in {2, 4, 6, 8, 10},
+    10 runs.  FP64.  Evaluations and the paper's CPU numbers are reported
+    beside the GPU's."""
+    paper = {"test1": {"on": (-1.6470, 0.0207, 1.027, 102881), "off": (-1.6492, 0.0212, 0.113, 124568)},
+             "test2": {"on": (-33.408, 0.198, 3.49, 10508225), "off": (-33.272, 0.221, 4.03, 14144037)},
+             "test3": {"on": (-1.6261, 0.0274, 0.273, 96925), "off": (-1.6322, 0.0314, 0.048, 134944)}}
+    tests = [("test1", workloads.paper_problem("test1_array49"), 6, math.log(49 * 2 * math.pi / 1600.0)),
+             ("test2", workloads.paper_problem("test2_two_gauss_10d"), 1, _two_gauss_truth(10)),
+             ("test3", workloads.paper_problem("test3_shell"), 4, _shell_truth())]
+    streams = [torch.cuda.Stream() for _ in range(args.concurrent)]
+    table = []
+    for name, spec, depth, truth in tests:
+        S = args.seeds or (20 if name == "test2" else 50)
+        for on in (True, False):
+            runs, wall = _ensemble(native, torch, spec, 1000, 1, list(range(S)), streams,
+                                   tree_depth=depth if on else 0, recluster_every=100)
+            row = {"test": name, "clustering": on, "depth": depth if on else 0, "truth": truth}
+            row.update(_summ(np, runs, truth, wall))
+            row["logZ_mean"] = truth + row["mean_err"]
+            row["paper_cpu"] = dict(zip(("logZ", "std", "wall_s", "evals"), paper[name]["on" if on else "off"]))
+            table.append(row)
+            log(f"{name} clustering={on}: log Z {row['logZ_mean']:.4f} (truth {truth:.4f}) std {row['std']:.4f}, "
+                f"evals {row['evals_mean']:.0f}, {wall:.1f} s for {S} runs")
+    sweep = []
+    for d in (2, 4, 6, 8, 10):
+        spec = workloads.paper_problem(f"test2_two_gauss_{d}d")
+        truth = _two_gauss_truth(d)
+        for depth in (0, 1, 3, 6):
+            runs, wall = _ensemble(native, torch, spec, 1000, 1, list(range(args.seeds or 10)), streams,
+                                   tree_depth=depth, recluster_every=100)
+            row = {"d": d, "depth": depth, "truth": truth}
+            row.update(_summ(np, runs, truth, wall))
+            sweep.append(row)
+            log(f"test2 d={d} depth={depth}: err {row['mean_err']:+.4f} std {row['std']:.3f} "
+                f"evals {row['evals_mean']:.0f}")
+    for row in sweep:
+        base = next(r for r in sweep if r["d"] == row["d"] and r["depth"] == 0)
+        row["evals_ratio_vs_depth0"] = row["evals_mean"] / base["evals_mean"]
+    print(json.dumps({"metric": "clustering study (Sec. 2.3, Table 1, Fig. 1)", "data": "synthetic",
+                      "config": {"workload": "Tests 1-3, N_live=1000, m=1, recluster every 100 deaths, FP64"},
+                      "table": table, "depth_sweep": sweep}, default=float))
+
+
+def study_suite(args, np, torch, native, workloads):
+    """Sec. 4 workloads (the comparison samplers themselves are not run):
+    Gaussian of Eq. (5) on [-7,7]^d for d in {2, 4, 8, 16, 32} (N = 1000, 50
+    runs; d = 32: 10), 2-d Rosenbrock of Eq. (6) on [-10,10]^2 and the
+    49-Gaussian array of Eq. (2) for N in {100, 200, 500, 1000} (100 runs);
+    sequential (m = 1), FP32 state and likelihood as the paper's Sec. 4 runs;
+    log Z against the closed form or quadrature."""
+    from scipy.special import erf
+    streams = [torch.cuda.Stream() for _ in range(args.concurrent)]
+    kw = dict(prec="f32", state="f32")
+    gauss, ros, arr = [], [], []
+    for d in (2, 4, 8, 16, 32):
+        spec = workloads.paper_problem(f"eq5_gauss{d}d")
+        truth = d * math.log(0.5 * (erf(7 / math.sqrt(2)) - erf(-7 / math.sqrt(2))) * math.sqrt(2 * math.pi) / 14)
+        S = args.seeds or (10 if d == 32 else 50)
+        runs, wall = _ensemble(native, torch, spec, 1000, 1, list(range(S)), streams, **kw)
+        row = {"d": d, "N": 1000, "truth": truth}
+        row.update(_summ(np, runs, truth, wall))
+        gauss.append(row)
+        log(f"gauss d={d}: err {row['mean_err']:+.4f} std {row['std']:.3f}, {wall:.1f} s / {S} runs")
+    x = np.linspace(-10, 10, 400001)
+    inner = math.sqrt(math.pi / 100) * 0.5 * (erf(10 * (10 - x ** 2)) - erf(10 * (-10 - x ** 2)))
+    ros_truth = math.log(np.trapezoid(np.exp(-(1 - x) ** 2) * inner, x) / 400.0)
+    arr_truth = math.log(49 * 2 * math.pi / 1600.0)
+    for N in (100, 200, 500, 1000):
+        S = args.seeds or 100
+        for name, spec, truth, depth, out in (("rosenbrock2d", workloads.paper_problem("eq6_rosenbrock2d"), ros_truth, 0, ros),
+                                              ("array49", workloads.paper_problem("test1_array49"), arr_truth, 6, arr)):
+            runs, wall = _ensemble(native, torch, spec, N, 1, list(range(S)), streams, tree_depth=depth, **kw)
+            row = {"N": N, "truth": truth, "depth": depth}
+            row.update(_summ(np, runs, truth, wall))
+            out.append(row)
+            log(f"{name} N={N}: err {row['mean_err']:+.4f} std {row['std']:.3f}, {wall:.1f} s / {S} runs")
+    print(json.dumps({"metric": "Sec. 4 workloads: log Z error and throughput", "data": "synthetic",
+                      "config": {"workload": "sequential m=1, FP32 state and likelihood, 5d slice iterations"},
+                      "gaussian": gauss, "rosenbrock2d": ros, "array49": arr}, default=float))
 
 
 # ---------------------------------------------------------------- 10-d Rosenbrock

@@ -351,12 +351,16 @@ __device__ __forceinline__ void emu_chain_round(const EmuArgs& A, EmuShared& sh,
 }
 
 // ---------------------------------------------------------------- network
+constexpr int kEStages = 4;   // K steps of weight fragments in registers (three loads in flight)
+
 // One pass of a wave over NCB column blocks (cb0 .. cb0 + NCB - 1, two 16-wide
-// tiles each) of both row blocks, K in steps of 32.  A: LDS planes (stride
-// apl), fragment-major with S = K/32 steps; Wf: global, fragment-major W^T
-// (tile ct at (ct S + s) 512), WS weight planes of stride wpl.
-template <int NCB, int WS>
-__device__ __forceinline__ void emu_pass(const __bf16* Al, int apl, int S, const __bf16* __restrict__ Wf, long wpl,
+// tiles each) of the kERB row blocks, S K steps of 32.  A: LDS planes (stride
+// apl), fragment-major; Wf: global, fragment-major W^T (tile ct at
+// (ct S + s) 512), WS weight planes of stride wpl.  Weight fragments stream
+// through a ring of kEStages K steps (static register indices: the loop is
+// unrolled).
+template <int NCB, int WS, int S>
+__device__ __forceinline__ void emu_pass(const __bf16* Al, int apl, const __bf16* __restrict__ Wf, long wpl,
                                          int cb0, f32x4 (&acc)[kERB][NCB][2]) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -364,20 +368,25 @@ __device__ __forceinline__ void emu_pass(const __bf16* Al, int apl, int S, const
 #pragma unroll
     for (int c = 0; c < NCB; ++c) acc[r][c][0] = acc[r][c][1] = f32x4{0.f, 0.f, 0.f, 0.f};
   const __bf16* bp = Wf + static_cast<long>(2 * cb0) * S * 512 + lane * 8;
-  const long tstep = static_cast<long>(S) * 512;   // next column tile
-  // weight fragments of three K steps in registers: two steps of loads in
-  // flight while one is multiplied
-  bf16x8 b0[NCB][2][WS], b1[NCB][2][WS], b2[NCB][2][WS];
-  auto loadb = [&](int s, bf16x8 (&b)[NCB][2][WS]) {
+  constexpr long tstep = static_cast<long>(S) * 512;   // next column tile
+  // four weight columns per wave (the 1024-wide output layer): one stage less
+  constexpr int DS = NCB >= 4 ? kEStages - 1 : kEStages;
+  constexpr int D = S < DS ? S : DS;
+  bf16x8 b[D][NCB][2][WS];
+  auto loadb = [&](int s, bf16x8 (&bb)[NCB][2][WS]) {
 #pragma unroll
     for (int c = 0; c < NCB; ++c)
 #pragma unroll
       for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int q = 0; q < WS; ++q)
-          b[c][t][q] = *reinterpret_cast<const bf16x8*>(bp + (2 * c + t) * tstep + q * wpl + static_cast<long>(s) * 512);
+          bb[c][t][q] = *reinterpret_cast<const bf16x8*>(bp + (2 * c + t) * tstep + q * wpl + static_cast<long>(s) * 512);
   };
-  auto step = [&](int s, const bf16x8 (&b)[NCB][2][WS]) {
+#pragma unroll
+  for (int s = 0; s < D - 1; ++s) loadb(s, b[s]);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    if (s + D - 1 < S) loadb(s + D - 1, b[(s + D - 1) % D]);
     bf16x8 a[kERB][3];
 #pragma unroll
     for (int r = 0; r < kERB; ++r)
@@ -395,22 +404,10 @@ __device__ __forceinline__ void emu_pass(const __bf16* Al, int apl, int S, const
         for (int r = 0; r < kERB; ++r)
 #pragma unroll
           for (int c = 0; c < NCB; ++c) {
-            acc[r][c][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r][pa], b[c][0][pb], acc[r][c][0], 0, 0, 0);
-            acc[r][c][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r][pa], b[c][1][pb], acc[r][c][1], 0, 0, 0);
+            acc[r][c][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r][pa], b[s % D][c][0][pb], acc[r][c][0], 0, 0, 0);
+            acc[r][c][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r][pa], b[s % D][c][1][pb], acc[r][c][1], 0, 0, 0);
           }
       }
-  };
-  loadb(0, b0);
-  if (S > 1) loadb(1, b1);
-  for (int s = 0; s < S; s += 3) {
-    if (s + 2 < S) loadb(s + 2, b2);
-    step(s, b0);
-    if (s + 1 >= S) break;
-    if (s + 3 < S) loadb(s + 3, b0);
-    step(s + 1, b1);
-    if (s + 2 >= S) break;
-    if (s + 4 < S) loadb(s + 4, b1);
-    step(s + 2, b2);
   }
 }
 
@@ -447,7 +444,7 @@ __device__ __forceinline__ void emu_store_hidden(EmuShared& sh, int N, int cb0, 
 // 32 columns of ((y + bias - data) isig)^2, FP64, with the layer kernels'
 // butterfly.
 template <int NCB>
-__device__ __forceinline__ void emu_store_chi2(EmuShared& sh, int nb, int cb0, const float* __restrict__ bias,
+__device__ __forceinline__ void emu_store_chi2(EmuShared& sh, int cb0, const float* __restrict__ bias,
                                                const double* __restrict__ data, const double* __restrict__ isig,
                                                const f32x4 (&acc)[kERB][NCB][2]) {
   const int lane = threadIdx.x & 63;
@@ -471,43 +468,43 @@ __device__ __forceinline__ void emu_store_chi2(EmuShared& sh, int nb, int cb0, c
   }
 }
 
-// One layer over all kER rows: the column blocks are dealt to the kEW waves,
-// NCB per pass.  First layer: input from xin (K = 32, weights in three
-// planes); hidden layers: input from and output to the activation planes
-// (in place, after every wave has read its input); output layer: chi^2.
-template <int NCB>
+// One layer over all kER rows, NCB = N/256 column blocks per wave in one
+// pass.  First layer (S = 1): input from xin (weights in three planes);
+// hidden layers: input from and output to the activation planes (in place,
+// after every wave has read its input); output layer: chi^2 partials.
+template <int NCB, int S, bool FIRST, bool OUT>
 __device__ __forceinline__ void emu_layer(EmuShared& sh, const EmuNet& net, int l) {
   const int wave = threadIdx.x >> 6;
-  const int L = net.n_layers;
   const int N = net.widths[l + 1];
-  const int nb = N >> 5;
-  f32x4 acc[kERB][NCB][2];
-  if (l == 0) {
-    for (int cb0 = wave * NCB; cb0 < nb; cb0 += kEW * NCB) {
-      emu_pass<NCB, 3>(sh.xin, kER * 32, 1, net.Wf[0], static_cast<long>(N) * 32, cb0, acc);
-      if (L == 1) emu_store_chi2<NCB>(sh, nb, cb0, net.b[0], net.data, net.isig, acc);
-      else emu_store_hidden<NCB>(sh, N, cb0, net.b[0], net.act, acc);
-    }
-    __syncthreads();
-    return;
-  }
-  const int K = net.widths[l];
-  const int S = K >> 5;
-  if (l == L - 1) {
-    for (int cb0 = wave * NCB; cb0 < nb; cb0 += kEW * NCB) {
-      emu_pass<NCB, 1>(sh.act, kER * K, S, net.Wf[l], 0L, cb0, acc);
-      emu_store_chi2<NCB>(sh, nb, cb0, net.b[l], net.data, net.isig, acc);
-    }
-    __syncthreads();
-    return;
-  }
-  // hidden layer, in place: every wave's column blocks in one pass (N <= kEW * NCB * 32)
   const int cb0 = wave * NCB;
-  const bool mine = cb0 < nb;
-  if (mine) emu_pass<NCB, 1>(sh.act, kER * K, S, net.Wf[l], 0L, cb0, acc);
+  f32x4 acc[kERB][NCB][2];
+  if (FIRST) emu_pass<NCB, 3, 1>(sh.xin, kER * 32, net.Wf[0], static_cast<long>(N) * 32, cb0, acc);
+  else emu_pass<NCB, 1, S>(sh.act, kER * S * 32, net.Wf[l], 0L, cb0, acc);
+  if (OUT) {
+    emu_store_chi2<NCB>(sh, cb0, net.b[l], net.data, net.isig, acc);
+  } else {
+    if (!FIRST) __syncthreads();     // every wave has read the layer's input
+    emu_store_hidden<NCB>(sh, N, cb0, net.b[l], net.act, acc);
+  }
   __syncthreads();
-  if (mine) emu_store_hidden<NCB>(sh, N, cb0, net.b[l], net.act, acc);
-  __syncthreads();
+}
+
+// dispatch on the layer's width (N = 256 NCB) and input depth (K = 32 S)
+template <bool FIRST, bool OUT>
+__device__ __forceinline__ void emu_layer_any(EmuShared& sh, const EmuNet& net, int l) {
+  const int N = net.widths[l + 1], K = FIRST ? 32 : net.widths[l];
+  if (FIRST) {
+    if (N == 256) emu_layer<1, 1, true, OUT>(sh, net, l);
+    else emu_layer<2, 1, true, OUT>(sh, net, l);
+  } else if (K == 256) {
+    if (N == 256) emu_layer<1, 8, false, OUT>(sh, net, l);
+    else if (N == 512) emu_layer<2, 8, false, OUT>(sh, net, l);
+    else emu_layer<4, 8, false, OUT>(sh, net, l);
+  } else {
+    if (N == 256) emu_layer<1, 16, false, OUT>(sh, net, l);
+    else if (N == 512) emu_layer<2, 16, false, OUT>(sh, net, l);
+    else emu_layer<4, 16, false, OUT>(sh, net, l);
+  }
 }
 
 __global__ void __launch_bounds__(64 * kEW)
@@ -535,13 +532,11 @@ k_emu_chains(EmuArgs A) {
 #pragma unroll
     for (int c = 0; c < kEC; ++c) alive += sh.done[c] ? 0 : 1;
     if (alive == 0) break;
-    // the kER rows through the network (hidden layers 256 or 512 wide: one
-    // or two column blocks per wave; output layer two per pass)
-    emu_layer<1>(sh, A.net, 0);
+    // the kER rows through the network
+    emu_layer_any<true, false>(sh, A.net, 0);
     for (int l = 1; l < L; ++l) {
-      if (l == L - 1) emu_layer<2>(sh, A.net, l);
-      else if (A.net.widths[l + 1] == 32 * kEW) emu_layer<1>(sh, A.net, l);
-      else emu_layer<2>(sh, A.net, l);
+      if (l == L - 1) emu_layer_any<false, true>(sh, A.net, l);
+      else emu_layer_any<false, false>(sh, A.net, l);
     }
     // row log-likelihoods: the partials summed in column-block order
     if (threadIdx.x < kER) {
@@ -561,9 +556,11 @@ bool emu_chains_eligible(const NetDev& net, const RoundsParams& p, int state_f32
   if (!state_f32 || p.P != kEP || 2 * p.so_spec > kEP || p.sh_spec > kEP || p.d > kMaxD) return false;
   const int L = net.n_layers;
   if (L < 2 || L > 8 || net.widths[0] > 32) return false;
-  for (int l = 1; l < L; ++l)   // hidden widths: one pass of one or two column blocks per wave
-    if (net.widths[l] != 32 * kEW && net.widths[l] != 64 * kEW) return false;
-  if (net.widths[L] % (32 * kEW * 2) != 0 || net.widths[L] > 32 * kEMaxOutB) return false;
+  // every layer one pass of N/256 column blocks per wave; hidden widths 256 or
+  // 512 (held in LDS), output width 256, 512 or 1024
+  for (int l = 1; l < L; ++l)
+    if (net.widths[l] != 256 && net.widths[l] != 512) return false;
+  if (net.widths[L] != 256 && net.widths[L] != 512 && net.widths[L] != 1024) return false;
   for (int l = 0; l < L; ++l)
     if (!net.Wf[l]) return false;
   return true;
