@@ -13,6 +13,7 @@
 // the cluster on its path.  All reductions use fixed trees, so repeated runs
 // give identical trees.
 #include "ns_internal.hpp"
+#include "ns_cluster_large.hpp"
 
 namespace ns {
 
@@ -609,9 +610,54 @@ k_cluster_prune(int nodes, int depth, int N, double log_keep, int nmin, const in
   }
 }
 
+// Points of one LDS chunk of the per-node kernel (odd stride).
+static int node_chunk_points(int d, int state_f32) {
+  int cs = kPtsBytes / (state_f32 ? 4 : 8) / d;
+  return cs - ((cs & 1) ^ 1);
+}
+
+bool cluster_root_split(const Shape& sh) {
+  return sh.state_f32 && sh.depth >= 1 && sh.N >= 2 && sh.N > node_chunk_points(sh.d, 1);
+}
+
+// The root node from the multi-workgroup split: its point count, mean and
+// covariance in the tree's layout, and each point's child (the same
+// quantities the per-node kernel writes for the root).
+__global__ void __launch_bounds__(256)
+k_cluster_root_take(int N, int d, const double* __restrict__ stats, const unsigned char* __restrict__ side,
+                    int* __restrict__ nodeof, int* __restrict__ count, double* __restrict__ centre,
+                    double* __restrict__ cov, const RunState* __restrict__ st) {
+  if (st->done) return;
+  const long k = static_cast<long>(blockIdx.x) * 256 + threadIdx.x;
+  if (k < N) nodeof[k] = 1 + side[k];
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) count[0] = N;
+    if (threadIdx.x < d) centre[threadIdx.x] = stats[threadIdx.x];
+    for (int q = threadIdx.x; q < d * d; q += 256) {
+      const int i = q / d, j = q - i * d;
+      cov[i * kMaxD + j] = stats[32 + q];
+    }
+  }
+}
+
 hipError_t launch_cluster(const Shape& sh, const DevBufs& b, double p, int nmin, int iters,
                           double eps, hipStream_t s) {
-  for (int level = 0; level <= sh.depth; ++level) {
+  int level0 = 0;
+  if (cluster_root_split(sh)) {
+    // a root beyond one workgroup's LDS: its passes spread over the device
+    // instead of reloading the points chunk by chunk in one workgroup
+    if (!b.root_work || !b.root_stats || !b.root_side) return hipErrorInvalidValue;
+    hipError_t e = launch_cluster_split(static_cast<const float*>(b.u), sh.N, sh.d, iters, b.root_stats,
+                                        b.root_stats + 32, b.root_stats + 32 + 32 * 32, b.root_side,
+                                        b.root_work, nullptr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cluster_root_take, dim3((sh.N + 255) / 256), dim3(256), 0, s, sh.N, sh.d,
+                       b.root_stats, b.root_side, b.nodeof, b.count, b.centre, b.cov, b.st);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    level0 = 1;
+  }
+  for (int level = level0; level <= sh.depth; ++level) {
     const dim3 grid(1u << level), block(kCT);
 #define NS_LEVEL_K(T, DM, XD)                                                                  \
   hipLaunchKernelGGL((k_cluster_level<T, DM, XD>), grid, block, 0, s, level, sh.depth, sh.N, sh.d, \

@@ -21,6 +21,7 @@
 // changes or after `iters` updates; an empty side keeps its centre.  Passes
 // after the stop exit at once.
 #include <algorithm>
+#include <atomic>
 #include "ns_device.hpp"
 #include "ns_cluster_large.hpp"
 
@@ -670,18 +671,20 @@ __global__ void k_cl_finish(int* __restrict__ passes, CLWork* __restrict__ w) {
 // runtime cannot tell.
 template <int DM>
 static int lloyd_resident() {
-  static int cache[16] = {0};
+  static std::atomic<int> cache[16];   // zero-initialised (static storage)
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return 0;
-  if (cache[dev] == 0) {
+  int v = cache[dev].load(std::memory_order_relaxed);
+  if (v == 0) {
     int cus = 0, nb = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_cl_lloyd<DM>), 256, 0) !=
             hipSuccess)
       return 0;
-    cache[dev] = cus * nb;
+    v = cus * nb;
+    cache[dev].store(v, std::memory_order_relaxed);
   }
-  return cache[dev];
+  return v;
 }
 
 hipError_t launch_cluster_split(const float* u, long N, int d, int iters, double* mean, double* cov,

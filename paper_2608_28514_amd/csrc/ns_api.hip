@@ -243,7 +243,7 @@ static void free_all(ns_ctx* c) {
                   b.new_u, b.new_logL,
                   b.chain_stat, b.hist_logL, b.hist_u, b.hist_n, b.draws, b.nodeof, b.count,
                   b.accepted, b.split_ok, b.logV, b.logV_eff, b.centre, b.cov, b.chol, b.chol_f,
-                  b.dead_u, b.dead_logL, b.st, c->d_out3, c->rb.cs, c->rb.pts, c->rb.xin,
+                  b.root_work, b.root_stats, b.root_side, b.dead_u, b.dead_logL, b.st, c->d_out3, c->rb.cs, c->rb.pts, c->rb.xin,
                   c->rb.flag, c->rb.rlogL, c->rb.gate, c->rb.crows, c->rb.cmap, c->rb.cbase, c->rb.H0, c->rb.H1, c->rb.Y, c->rb.rthr,
                   c->rb.sflag, c->d_sc, c->d_count, c->d_chunk, c->d_idx, c->d_aud, c->d_xc, c->d_xf, c->d_clogL,
                   c->d_yhat, c->sP, c->sG, c->sM, c->sV, c->s_norm, c->s_loss, c->s_Xb, c->s_yb,
@@ -772,6 +772,11 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
   NS_INIT_HIP(dalloc(&b.cov, static_cast<size_t>(sh.nodes) * kMaxD * kMaxD));
   NS_INIT_HIP(dalloc(&b.chol, static_cast<size_t>(sh.nodes) * kMaxD * kMaxD));
   NS_INIT_HIP(dalloc(&b.chol_f, static_cast<size_t>(sh.nodes) * kMaxD * kMaxD));
+  if (cluster_root_split(sh)) {
+    NS_INIT_HIP(hipMalloc(&b.root_work, cluster_split_work_bytes()));
+    NS_INIT_HIP(dalloc(&b.root_stats, kRootStats));
+    NS_INIT_HIP(dalloc(&b.root_side, N));
+  }
   NS_INIT_HIP(dalloc(&b.st, 1));
   NS_INIT_HIP(dalloc(&c->d_out3, 3));
   NS_INIT_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_st), sizeof(RunState), hipHostMallocDefault));
