@@ -36,7 +36,9 @@ constexpr int kEP = 8;                 // rows per chain and round
 constexpr int kER = kEC * kEP;         // rows per round
 constexpr int kERB = kER / 16;         // row blocks
 constexpr int kEMaxW = 64 * kEW;       // widest hidden layer held in LDS (512)
-constexpr int kEMaxOutB = 64;          // output column blocks of 32 (width <= 2048)
+constexpr int kEMaxOutB = 32;          // output column blocks of 32 (width <= 1024)
+constexpr int kEMaxOut = 32 * kEMaxOutB;
+constexpr int kEMaxBias = 7 * kEMaxW + kEMaxOut;   // every layer's bias (at most 8 layers)
 static_assert(kER % 16 == 0 && kEC <= kEW, "whole row blocks, a wave per chain");
 
 // the network, as the layer kernels see it
@@ -88,14 +90,18 @@ struct EmuShared {
   __attribute__((aligned(16))) __bf16 act[3 * kER * kEMaxW];   // activations, 3 planes of kER x width
   __attribute__((aligned(16))) __bf16 xin[3 * kER * 32];       // network input, 3 planes of kER x 32
   double part[kER * kEMaxOutB];                                // chi^2 partials, [row][column block]
+  float bias[kEMaxBias];                                       // the layers' biases, layer after layer
+  double dat[kEMaxOut];                                        // the data vector
+  double isg[kEMaxOut];                                        // 1 / sigma
   double rl[kER];                                              // row log-likelihoods of the last round
   int rflag[kER];                                              // row inside the box
   ChainState<float> S[kEC];
   float pts[kEC][kEP][kMaxD];                                  // the rows' points (state precision)
+  float Lc[kEC][kMaxD * (kMaxD + 1)];                          // each chain's Cholesky factor, row stride kMaxD + 1
+  double tauj[kEC];                                            // each chain's shrink threshold L_W[j]
+  double taue;                                                 // the batch-worst L_W[0]
   float zs[kEC][kMaxD];
   float Us[kEC][64];
-  float toff[kEC][64];
-  int has[kEC][64];
   int done[kEC];
   unsigned long long rows;
 };
@@ -108,7 +114,7 @@ __device__ __forceinline__ void emu_chain_round(const EmuArgs& A, EmuShared& sh,
   const int lane = threadIdx.x & 63;
   const int d = p.d, m = p.m, TH = p.T;
   ChainState<float>& S = sh.S[w];
-  const double tau_j = A.tau[j], tau_e = A.LW[0];
+  const double tau_j = sh.tauj[w], tau_e = sh.taue;
   const float w_ = static_cast<float>(p.w);
   const int myrow = w * kEP + min(lane, kEP - 1);
   const int fl = round > 0 ? sh.rflag[myrow] : 0;
@@ -124,6 +130,13 @@ __device__ __forceinline__ void emu_chain_round(const EmuArgs& A, EmuShared& sh,
     }
     wave_sync();
     if (lane < d) S.x[lane] = A.u[static_cast<long>(S.seed_slot) * d + lane];
+    // the chain's cluster factor (fixed for the step) and thresholds, once
+    const float* Lg = A.chol + static_cast<long>(S.label) * kMaxD * kMaxD;
+    for (int e = lane; e < d * kMaxD; e += 64) {
+      const int r = e / kMaxD, k = e - r * kMaxD;
+      sh.Lc[w][r * (kMaxD + 1) + k] = k <= r ? Lg[e] : 0.f;
+    }
+    if (lane == 0) sh.tauj[w] = A.tau[j];
     wave_sync();
   }
 
@@ -205,11 +218,16 @@ __device__ __forceinline__ void emu_chain_round(const EmuArgs& A, EmuShared& sh,
         sh.Us[w][lane] = static_cast<float>(du.a);
       }
       wave_sync();
+      float us[kEP];
+#pragma unroll
+      for (int q = 0; q < kEP; ++q) us[q] = sh.Us[w][q];
       float aa = S.a, bb = S.b, t = 0.f;
-      for (int q = 0; q <= upto; ++q) {
-        t = aa + sh.Us[w][q] * (bb - aa);
-        if (t < 0.f) aa = t; else bb = t;
-      }
+#pragma unroll
+      for (int q = 0; q < kEP; ++q)
+        if (q <= upto) {
+          t = aa + us[q] * (bb - aa);
+          if (t < 0.f) aa = t; else bb = t;
+        }
       if (lane < d) S.x[lane] = S.x[lane] + t * S.v[lane];
       if (lane == upto) S.lx = l;
     }
@@ -265,20 +283,25 @@ __device__ __forceinline__ void emu_chain_round(const EmuArgs& A, EmuShared& sh,
       if (2 * lane + 1 < d) sh.zs[w][2 * lane + 1] = r * sn;
     }
     wave_sync();
-    float nrm = 0.f;
-    for (int i = 0; i < d; ++i) nrm += sh.zs[w][i] * sh.zs[w][i];
-    nrm = DirMath<float>::sq(nrm);
-    if (lane < d) {
-      // row `lane` of the cluster's Cholesky factor (L2-resident), its loads
-      // issued together
-      const float* Lr = A.chol + static_cast<long>(S.label) * kMaxD * kMaxD + lane * kMaxD;
-      float Lrow[kMaxD];
+    float zr[kMaxD];
 #pragma unroll
-      for (int k = 0; k < kMaxD; ++k) Lrow[k] = k <= lane ? Lr[k] : 0.f;
+    for (int i = 0; i < kMaxD; ++i) zr[i] = i < d ? sh.zs[w][i] : 0.f;
+    float nrm = 0.f;
+#pragma unroll
+    for (int i = 0; i < kMaxD; ++i)
+      if (i < d) nrm += zr[i] * zr[i];
+    nrm = DirMath<float>::sq(nrm);
+    // z / |z|, one division per coordinate (lane i), shared through LDS
+    wave_sync();
+    if (lane < d) sh.zs[w][lane] = sh.zs[w][lane] / nrm;
+    wave_sync();
+    if (lane < d) {
+      // row `lane` of the cluster's Cholesky factor (LDS, conflict-free stride)
+      const float* Lr = sh.Lc[w] + lane * (kMaxD + 1);
       float acc = 0.f;
 #pragma unroll
       for (int k = 0; k < kMaxD; ++k)
-        if (k <= lane) acc += Lrow[k] * (sh.zs[w][k] / nrm);
+        if (k <= lane) acc += Lr[k] * sh.zs[w][k];
       S.v[lane] = acc;
     }
     if (lane == 0) {
@@ -297,10 +320,7 @@ __device__ __forceinline__ void emu_chain_round(const EmuArgs& A, EmuShared& sh,
     const bool left = lane < E;
     const int k = S.base + (left ? lane : lane - E);
     has = lane < 2 * E && (left ? S.ka < 0 : S.kb < 0) && k < p.max_stepout;
-    if (has) {
-      toff = left ? S.a0 - static_cast<float>(k) * w_ : S.b0 + static_cast<float>(k) * w_;
-      inb = line_in_box(S.x, S.v, toff, d);
-    }
+    if (has) toff = left ? S.a0 - static_cast<float>(k) * w_ : S.b0 + static_cast<float>(k) * w_;
   } else if (S.phase == kPhaseShrink) {
     const uint32_t c3 = (kStreamSlice << 24) | static_cast<uint32_t>(S.it);
     const int Sn = min(p.sh_spec, p.max_shrink - S.s0);
@@ -310,47 +330,67 @@ __device__ __forceinline__ void emu_chain_round(const EmuArgs& A, EmuShared& sh,
     }
     wave_sync();
     if (lane < Sn) {
+      float us[kEP];
+#pragma unroll
+      for (int q = 0; q < kEP; ++q) us[q] = sh.Us[w][q];
       float aa = S.a, bb = S.b, t = 0.f;
-      for (int q = 0; q <= lane; ++q) {
-        t = aa + sh.Us[w][q] * (bb - aa);
-        if (t < 0.f) aa = t; else bb = t;
-      }
+#pragma unroll
+      for (int q = 0; q < kEP; ++q)
+        if (q <= lane) {
+          t = aa + us[q] * (bb - aa);
+          if (t < 0.f) aa = t; else bb = t;
+        }
       toff = t;
       has = true;
-      inb = line_in_box(S.x, S.v, t, d);
       if (lane == Sn - 1) { S.br_a = aa; S.br_b = bb; }
     }
   }
-  if (lane < kEP) {
-    sh.rflag[w * kEP + lane] = inb ? 1 : 0;
-    sh.toff[w][lane] = toff;
-    sh.has[w][lane] = has ? 1 : 0;
+  // every proposal's point, box test and network input (theta in three
+  // bfloat16 terms), lane i taking coordinate i of all of them
+  const uint64_t hmask = __ballot(has);
+  const bool coord = lane < d;
+  const int ci = coord ? lane : 0;
+  const float xi = S.x[ci], vi = S.v[ci];
+  const float lo_i = p.lo_f[ci], span_i = p.span_f[ci];
+  uint32_t inmask = 0;
+#pragma unroll
+  for (int q = 0; q < kEP; ++q) {
+    const float tq = __shfl(toff, q);
+    if (!((hmask >> q) & 1ull)) continue;
+    const float yi = xi + tq * vi;
+    const bool out = coord && !((yi >= 0.f) & (yi <= 1.f));
+    if (__ballot(out) == 0ull) inmask |= 1u << q;
+    if (coord) {
+      sh.pts[w][q][lane] = yi;
+      const float xv = lo_i + span_i * yi;
+      const long fi = frag_index(w * kEP + q, lane, 32);
+      const __bf16 h = static_cast<__bf16>(xv);
+      const float r1 = xv - static_cast<float>(h);
+      const __bf16 mm = static_cast<__bf16>(r1);
+      sh.xin[fi] = h;
+      sh.xin[kER * 32 + fi] = mm;
+      sh.xin[2 * kER * 32 + fi] = static_cast<__bf16>(r1 - static_cast<float>(mm));
+    }
   }
+  inb = lane < kEP && ((inmask >> lane) & 1u);
+  if (lane < kEP) sh.rflag[w * kEP + lane] = inb ? 1 : 0;
   // network rows counted as the rounds driver counts them: kEP per chain with
   // a row inside the box
-  const uint64_t any = __ballot(lane < kEP && inb);
-  if (lane == 0 && any) atomicAdd(&sh.rows, static_cast<unsigned long long>(kEP));
-  wave_sync();
-  // the rows' points and their network input (theta in three bfloat16 terms)
-  for (int e = lane; e < kEP * d; e += 64) {
-    const int q = e / d, i = e - q * d;
-    if (!sh.has[w][q]) continue;
-    const float yi = S.x[i] + sh.toff[w][q] * S.v[i];
-    sh.pts[w][q][i] = yi;
-    const float xv = p.lo_f[i] + p.span_f[i] * yi;
-    const long fi = frag_index(w * kEP + q, i, 32);
-    const __bf16 h = static_cast<__bf16>(xv);
-    const float r1 = xv - static_cast<float>(h);
-    const __bf16 mm = static_cast<__bf16>(r1);
-    sh.xin[fi] = h;
-    sh.xin[kER * 32 + fi] = mm;
-    sh.xin[2 * kER * 32 + fi] = static_cast<__bf16>(r1 - static_cast<float>(mm));
-  }
+  if (lane == 0 && inmask) atomicAdd(&sh.rows, static_cast<unsigned long long>(kEP));
   if (lane == 0) sh.done[w] = S.phase == kPhaseDone ? 1 : 0;
   wave_sync();
 }
 
 // ---------------------------------------------------------------- network
+// v from the lane o places further on in the same 16-lane row (row_ror:o)
+template <int O>
+__device__ __forceinline__ double dpp_row_ror(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), 0x120 + O, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), 0x120 + O, 0xf, 0xf, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
 constexpr int kEStages = 4;   // K steps of weight fragments in registers (three loads in flight)
 
 // One pass of a wave over NCB column blocks (cb0 .. cb0 + NCB - 1, two 16-wide
@@ -413,7 +453,7 @@ __device__ __forceinline__ void emu_pass(const __bf16* Al, int apl, const __bf16
 
 // act(z + bias) of a pass's tiles into the activation planes (width N).
 template <int NCB>
-__device__ __forceinline__ void emu_store_hidden(EmuShared& sh, int N, int cb0, const float* __restrict__ bias,
+__device__ __forceinline__ void emu_store_hidden(EmuShared& sh, int N, int cb0, const float* bias,
                                                  int act, const f32x4 (&acc)[kERB][NCB][2]) {
   const int lane = threadIdx.x & 63;
   const int apl = kER * N;
@@ -422,7 +462,7 @@ __device__ __forceinline__ void emu_store_hidden(EmuShared& sh, int N, int cb0, 
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       const int n = (cb0 + c) * 32 + t * 16 + (lane & 15);
-      const float bz = bias ? bias[n] : 0.f;
+      const float bz = bias[n];
 #pragma unroll
       for (int r = 0; r < kERB; ++r)
 #pragma unroll
@@ -444,15 +484,14 @@ __device__ __forceinline__ void emu_store_hidden(EmuShared& sh, int N, int cb0, 
 // 32 columns of ((y + bias - data) isig)^2, FP64, with the layer kernels'
 // butterfly.
 template <int NCB>
-__device__ __forceinline__ void emu_store_chi2(EmuShared& sh, int cb0, const float* __restrict__ bias,
-                                               const double* __restrict__ data, const double* __restrict__ isig,
+__device__ __forceinline__ void emu_store_chi2(EmuShared& sh, int cb0, const float* bias,
                                                const f32x4 (&acc)[kERB][NCB][2]) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int c = 0; c < NCB; ++c) {
     const int n0 = (cb0 + c) * 32 + (lane & 15);
-    const float bz0 = bias ? bias[n0] : 0.f, bz1 = bias ? bias[n0 + 16] : 0.f;
-    const double d0 = data[n0], d1 = data[n0 + 16], s0 = isig[n0], s1 = isig[n0 + 16];
+    const float bz0 = bias[n0], bz1 = bias[n0 + 16];
+    const double d0 = sh.dat[n0], d1 = sh.dat[n0 + 16], s0 = sh.isg[n0], s1 = sh.isg[n0 + 16];
 #pragma unroll
     for (int r = 0; r < kERB; ++r)
 #pragma unroll
@@ -460,8 +499,14 @@ __device__ __forceinline__ void emu_store_chi2(EmuShared& sh, int cb0, const flo
         const double e0 = (static_cast<double>(acc[r][c][0][i] + bz0) - d0) * s0;
         const double e1 = (static_cast<double>(acc[r][c][1][i] + bz1) - d1) * s1;
         double t = e0 * e0 + e1 * e1;
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) t += __shfl_xor(t, o);
+        // the 16 columns of the tile summed by the butterfly of the layer
+        // kernels (partners lane ^ 8, ^ 4, ^ 2, ^ 1); after each step a
+        // row's value depends only on lane mod o, so rotating the 16-lane row
+        // by o meets a partner holding the same value as lane ^ o would
+        t += dpp_row_ror<8>(t);
+        t += dpp_row_ror<4>(t);
+        t += dpp_row_ror<2>(t);
+        t += dpp_row_ror<1>(t);
         const int row = r * 16 + 4 * (lane >> 4) + i;
         if ((lane & 15) == 0) sh.part[row * kEMaxOutB + cb0 + c] = t;
       }
@@ -473,7 +518,7 @@ __device__ __forceinline__ void emu_store_chi2(EmuShared& sh, int cb0, const flo
 // hidden layers: input from and output to the activation planes (in place,
 // after every wave has read its input); output layer: chi^2 partials.
 template <int NCB, int S, bool FIRST, bool OUT>
-__device__ __forceinline__ void emu_layer(EmuShared& sh, const EmuNet& net, int l) {
+__device__ __forceinline__ void emu_layer(EmuShared& sh, const EmuNet& net, int l, int boff) {
   const int wave = threadIdx.x >> 6;
   const int N = net.widths[l + 1];
   const int cb0 = wave * NCB;
@@ -481,29 +526,29 @@ __device__ __forceinline__ void emu_layer(EmuShared& sh, const EmuNet& net, int 
   if (FIRST) emu_pass<NCB, 3, 1>(sh.xin, kER * 32, net.Wf[0], static_cast<long>(N) * 32, cb0, acc);
   else emu_pass<NCB, 1, S>(sh.act, kER * S * 32, net.Wf[l], 0L, cb0, acc);
   if (OUT) {
-    emu_store_chi2<NCB>(sh, cb0, net.b[l], net.data, net.isig, acc);
+    emu_store_chi2<NCB>(sh, cb0, sh.bias + boff, acc);
   } else {
     if (!FIRST) __syncthreads();     // every wave has read the layer's input
-    emu_store_hidden<NCB>(sh, N, cb0, net.b[l], net.act, acc);
+    emu_store_hidden<NCB>(sh, N, cb0, sh.bias + boff, net.act, acc);
   }
   __syncthreads();
 }
 
 // dispatch on the layer's width (N = 256 NCB) and input depth (K = 32 S)
 template <bool FIRST, bool OUT>
-__device__ __forceinline__ void emu_layer_any(EmuShared& sh, const EmuNet& net, int l) {
+__device__ __forceinline__ void emu_layer_any(EmuShared& sh, const EmuNet& net, int l, int boff) {
   const int N = net.widths[l + 1], K = FIRST ? 32 : net.widths[l];
   if (FIRST) {
-    if (N == 256) emu_layer<1, 1, true, OUT>(sh, net, l);
-    else emu_layer<2, 1, true, OUT>(sh, net, l);
+    if (N == 256) emu_layer<1, 1, true, OUT>(sh, net, l, boff);
+    else emu_layer<2, 1, true, OUT>(sh, net, l, boff);
   } else if (K == 256) {
-    if (N == 256) emu_layer<1, 8, false, OUT>(sh, net, l);
-    else if (N == 512) emu_layer<2, 8, false, OUT>(sh, net, l);
-    else emu_layer<4, 8, false, OUT>(sh, net, l);
+    if (N == 256) emu_layer<1, 8, false, OUT>(sh, net, l, boff);
+    else if (N == 512) emu_layer<2, 8, false, OUT>(sh, net, l, boff);
+    else emu_layer<4, 8, false, OUT>(sh, net, l, boff);
   } else {
-    if (N == 256) emu_layer<1, 16, false, OUT>(sh, net, l);
-    else if (N == 512) emu_layer<2, 16, false, OUT>(sh, net, l);
-    else emu_layer<4, 16, false, OUT>(sh, net, l);
+    if (N == 256) emu_layer<1, 16, false, OUT>(sh, net, l, boff);
+    else if (N == 512) emu_layer<2, 16, false, OUT>(sh, net, l, boff);
+    else emu_layer<4, 16, false, OUT>(sh, net, l, boff);
   }
 }
 
@@ -521,6 +566,22 @@ k_emu_chains(EmuArgs A) {
   for (int q = threadIdx.x; q < 3 * kER * 32; q += 64 * kEW) sh.xin[q] = static_cast<__bf16>(0.f);
   if (threadIdx.x < kER) { sh.rflag[threadIdx.x] = 0; sh.rl[threadIdx.x] = -INFINITY; }
   if (threadIdx.x < kEC) sh.done[threadIdx.x] = threadIdx.x < nchain ? 0 : 1;
+  if (threadIdx.x == 0) sh.taue = A.LW[0];
+  // biases, data and 1/sigma to LDS once (the layers' epilogues read them)
+  {
+    int off = 0;
+    for (int l = 0; l < A.net.n_layers; ++l) {
+      const int n = A.net.widths[l + 1];
+      const float* bg = A.net.b[l];
+      for (int q = threadIdx.x; q < n; q += 64 * kEW) sh.bias[off + q] = bg ? bg[q] : 0.f;
+      off += n;
+    }
+    const int no = A.net.widths[A.net.n_layers];
+    for (int q = threadIdx.x; q < no; q += 64 * kEW) {
+      sh.dat[q] = A.net.data[q];
+      sh.isg[q] = A.net.isig[q];
+    }
+  }
   if (threadIdx.x == 0) sh.rows = 0ull;
   __syncthreads();
   const int L = A.net.n_layers;
@@ -533,10 +594,12 @@ k_emu_chains(EmuArgs A) {
     for (int c = 0; c < kEC; ++c) alive += sh.done[c] ? 0 : 1;
     if (alive == 0) break;
     // the kER rows through the network
-    emu_layer_any<true, false>(sh, A.net, 0);
+    emu_layer_any<true, false>(sh, A.net, 0, 0);
+    int boff = A.net.widths[1];
     for (int l = 1; l < L; ++l) {
-      if (l == L - 1) emu_layer_any<false, true>(sh, A.net, l);
-      else emu_layer_any<false, false>(sh, A.net, l);
+      if (l == L - 1) emu_layer_any<false, true>(sh, A.net, l, boff);
+      else emu_layer_any<false, false>(sh, A.net, l, boff);
+      boff += A.net.widths[l + 1];
     }
     // row log-likelihoods: the partials summed in column-block order
     if (threadIdx.x < kER) {
@@ -561,6 +624,7 @@ bool emu_chains_eligible(const NetDev& net, const RoundsParams& p, int state_f32
   for (int l = 1; l < L; ++l)
     if (net.widths[l] != 256 && net.widths[l] != 512) return false;
   if (net.widths[L] != 256 && net.widths[L] != 512 && net.widths[L] != 1024) return false;
+  static_assert(kEMaxOut >= 1024 && kEMaxBias >= 7 * 512 + 1024, "LDS room for every eligible network");
   for (int l = 0; l < L; ++l)
     if (!net.Wf[l]) return false;
   return true;
