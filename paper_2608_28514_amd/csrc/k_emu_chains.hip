@@ -80,9 +80,10 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ float emu_act(int act, float z) {
-  if (act == kActTanh) return tanhf(z);
-  if (act == kActSilu) return z / (1.0f + expf(-z));
+template <int ACT>
+__device__ __forceinline__ float emu_act(float z) {
+  if (ACT == kActTanh) return tanhf(z);
+  if (ACT == kActSilu) return z / (1.0f + expf(-z));
   return z;
 }
 
@@ -99,6 +100,11 @@ struct EmuShared {
   float pts[kEC][kEP][kMaxD];                                  // the rows' points (state precision)
   float Lc[kEC][kMaxD * (kMaxD + 1)];                          // each chain's Cholesky factor, row stride kMaxD + 1
   double tauj[kEC];                                            // each chain's shrink threshold L_W[j]
+  float dv[kEC][2][kMaxD];                                     // directions of coming iterations (by parity)
+  float da0[kEC][2];                                           // their stepping-out offsets
+  int dit[kEC][2];                                             // the iteration each buffer holds (-1: none)
+  float zs2[kEC][kMaxD];                                       // scratch of the waves that compute them
+  int itsnap[kEC];                                             // each chain's iteration at the round's start
   double taue;                                                 // the batch-worst L_W[0]
   float zs[kEC][kMaxD];
   float Us[kEC][64];
@@ -107,6 +113,51 @@ struct EmuShared {
 };
 
 // ---------------------------------------------------------------- chain logic
+// Direction v = L_c z / |z| (z from the iteration's Box-Muller draws, L_c the
+// chain's cluster factor in LDS) and stepping-out offset a0 of slice
+// iteration `it` of chain j, by one wave; zsc: kMaxD floats of scratch.
+__device__ __forceinline__ void emu_direction(const RoundsParams& p, const float* Lc, int j, int it, uint32_t step,
+                                              float* zsc, float* v, float* a0) {
+  const int lane = threadIdx.x & 63, d = p.d;
+  const uint32_t c3 = (kStreamSlice << 24) | static_cast<uint32_t>(it);
+  if (2 * lane < d) {
+    const Draw2 dr = uniform2(p.seed, kSlotDir0 + lane, static_cast<uint32_t>(j), step, c3);
+    const float r = DirMath<float>::r_of(static_cast<float>(dr.a));
+    const float ang = static_cast<float>(6.283185307179586) * static_cast<float>(dr.b);
+    float sn, csn;
+    DirMath<float>::sc(ang, &sn, &csn);
+    zsc[2 * lane] = r * csn;
+    if (2 * lane + 1 < d) zsc[2 * lane + 1] = r * sn;
+  }
+  wave_sync();
+  float zr[kMaxD];
+#pragma unroll
+  for (int i = 0; i < kMaxD; ++i) zr[i] = i < d ? zsc[i] : 0.f;
+  float nrm = 0.f;
+#pragma unroll
+  for (int i = 0; i < kMaxD; ++i)
+    if (i < d) nrm += zr[i] * zr[i];
+  nrm = DirMath<float>::sq(nrm);
+  // z / |z|, one division per coordinate (lane i), shared through LDS
+  wave_sync();
+  if (lane < d) zsc[lane] = zsc[lane] / nrm;
+  wave_sync();
+  if (lane < d) {
+    // row `lane` of the factor (conflict-free stride kMaxD + 1)
+    const float* Lr = Lc + lane * (kMaxD + 1);
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 0; k < kMaxD; ++k)
+      if (k <= lane) acc += Lr[k] * zsc[k];
+    v[lane] = acc;
+  }
+  if (lane == 0) {
+    const Draw2 d0 = uniform2(p.seed, kSlotStepout, static_cast<uint32_t>(j), step, c3);
+    *a0 = -static_cast<float>(p.w) * static_cast<float>(d0.a);
+  }
+  wave_sync();
+}
+
 // One round of chain j on wave w (64 lanes): consume the likelihoods of the
 // rows it proposed in the previous round, then propose the next kEP rows.
 __device__ __forceinline__ void emu_chain_round(const EmuArgs& A, EmuShared& sh, int w, int j, int round, uint32_t step) {
@@ -130,13 +181,6 @@ __device__ __forceinline__ void emu_chain_round(const EmuArgs& A, EmuShared& sh,
     }
     wave_sync();
     if (lane < d) S.x[lane] = A.u[static_cast<long>(S.seed_slot) * d + lane];
-    // the chain's cluster factor (fixed for the step) and thresholds, once
-    const float* Lg = A.chol + static_cast<long>(S.label) * kMaxD * kMaxD;
-    for (int e = lane; e < d * kMaxD; e += 64) {
-      const int r = e / kMaxD, k = e - r * kMaxD;
-      sh.Lc[w][r * (kMaxD + 1) + k] = k <= r ? Lg[e] : 0.f;
-    }
-    if (lane == 0) sh.tauj[w] = A.tau[j];
     wave_sync();
   }
 
@@ -272,41 +316,16 @@ __device__ __forceinline__ void emu_chain_round(const EmuArgs& A, EmuShared& sh,
 
   // ---------------------------------------------------------------- propose
   if (S.phase == kPhaseDir) {
-    const uint32_t c3 = (kStreamSlice << 24) | static_cast<uint32_t>(S.it);
-    if (2 * lane < d) {
-      const Draw2 dr = uniform2(p.seed, kSlotDir0 + lane, static_cast<uint32_t>(j), step, c3);
-      const float r = DirMath<float>::r_of(static_cast<float>(dr.a));
-      const float ang = static_cast<float>(6.283185307179586) * static_cast<float>(dr.b);
-      float sn, csn;
-      DirMath<float>::sc(ang, &sn, &csn);
-      sh.zs[w][2 * lane] = r * csn;
-      if (2 * lane + 1 < d) sh.zs[w][2 * lane + 1] = r * sn;
+    // computed ahead by the chain's helper wave, else here
+    const int b = S.it & 1;
+    if (sh.dit[w][b] == S.it) {
+      if (lane < d) S.v[lane] = sh.dv[w][b][lane];
+      if (lane == 0) S.a0 = sh.da0[w][b];
+    } else {
+      emu_direction(p, sh.Lc[w], j, S.it, step, sh.zs[w], S.v, &S.a0);
     }
     wave_sync();
-    float zr[kMaxD];
-#pragma unroll
-    for (int i = 0; i < kMaxD; ++i) zr[i] = i < d ? sh.zs[w][i] : 0.f;
-    float nrm = 0.f;
-#pragma unroll
-    for (int i = 0; i < kMaxD; ++i)
-      if (i < d) nrm += zr[i] * zr[i];
-    nrm = DirMath<float>::sq(nrm);
-    // z / |z|, one division per coordinate (lane i), shared through LDS
-    wave_sync();
-    if (lane < d) sh.zs[w][lane] = sh.zs[w][lane] / nrm;
-    wave_sync();
-    if (lane < d) {
-      // row `lane` of the cluster's Cholesky factor (LDS, conflict-free stride)
-      const float* Lr = sh.Lc[w] + lane * (kMaxD + 1);
-      float acc = 0.f;
-#pragma unroll
-      for (int k = 0; k < kMaxD; ++k)
-        if (k <= lane) acc += Lr[k] * sh.zs[w][k];
-      S.v[lane] = acc;
-    }
     if (lane == 0) {
-      const Draw2 d0 = uniform2(p.seed, kSlotStepout, static_cast<uint32_t>(j), step, c3);
-      S.a0 = -w_ * static_cast<float>(d0.a);
       S.b0 = S.a0 + w_;
       S.ka = -1; S.kb = -1; S.base = 0;
       S.phase = kPhaseStepout;
@@ -452,9 +471,9 @@ __device__ __forceinline__ void emu_pass(const __bf16* Al, int apl, const __bf16
 }
 
 // act(z + bias) of a pass's tiles into the activation planes (width N).
-template <int NCB>
+template <int NCB, int ACT>
 __device__ __forceinline__ void emu_store_hidden(EmuShared& sh, int N, int cb0, const float* bias,
-                                                 int act, const f32x4 (&acc)[kERB][NCB][2]) {
+                                                 const f32x4 (&acc)[kERB][NCB][2]) {
   const int lane = threadIdx.x & 63;
   const int apl = kER * N;
 #pragma unroll
@@ -468,7 +487,7 @@ __device__ __forceinline__ void emu_store_hidden(EmuShared& sh, int N, int cb0, 
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int row = r * 16 + 4 * (lane >> 4) + i;
-          const float x = emu_act(act, acc[r][c][t][i] + bz);
+          const float x = emu_act<ACT>(acc[r][c][t][i] + bz);
           const __bf16 h = static_cast<__bf16>(x);
           const float r1 = x - static_cast<float>(h);
           const __bf16 md = static_cast<__bf16>(r1);
@@ -529,7 +548,10 @@ __device__ __forceinline__ void emu_layer(EmuShared& sh, const EmuNet& net, int 
     emu_store_chi2<NCB>(sh, cb0, sh.bias + boff, acc);
   } else {
     if (!FIRST) __syncthreads();     // every wave has read the layer's input
-    emu_store_hidden<NCB>(sh, N, cb0, sh.bias + boff, net.act, acc);
+    // the activation chosen once per layer: no branch per element
+    if (net.act == kActTanh) emu_store_hidden<NCB, kActTanh>(sh, N, cb0, sh.bias + boff, acc);
+    else if (net.act == kActSilu) emu_store_hidden<NCB, kActSilu>(sh, N, cb0, sh.bias + boff, acc);
+    else emu_store_hidden<NCB, kActNone>(sh, N, cb0, sh.bias + boff, acc);
   }
   __syncthreads();
 }
@@ -567,6 +589,16 @@ k_emu_chains(EmuArgs A) {
   if (threadIdx.x < kER) { sh.rflag[threadIdx.x] = 0; sh.rl[threadIdx.x] = -INFINITY; }
   if (threadIdx.x < kEC) sh.done[threadIdx.x] = threadIdx.x < nchain ? 0 : 1;
   if (threadIdx.x == 0) sh.taue = A.LW[0];
+  if (threadIdx.x < 2 * kEC) sh.dit[threadIdx.x >> 1][threadIdx.x & 1] = -1;
+  if (wave < nchain) {
+    // the chain's cluster factor (fixed for the step) and its threshold
+    const float* Lg = A.chol + static_cast<long>(A.label[A.seeds[j0 + wave]]) * kMaxD * kMaxD;
+    for (int e = lane; e < A.p.d * kMaxD; e += 64) {
+      const int r = e / kMaxD, k = e - r * kMaxD;
+      sh.Lc[wave][r * (kMaxD + 1) + k] = k <= r ? Lg[e] : 0.f;
+    }
+    if (lane == 0) sh.tauj[wave] = A.tau[j0 + wave];
+  }
   // biases, data and 1/sigma to LDS once (the layers' epilogues read them)
   {
     int off = 0;
@@ -587,8 +619,22 @@ k_emu_chains(EmuArgs A) {
   const int L = A.net.n_layers;
   const int nbo = A.net.widths[L] >> 5;
   for (int round = 0;; ++round) {
-    if (wave < nchain && !sh.done[wave]) emu_chain_round(A, sh, wave, j0 + wave, round, step);
+    if (wave < nchain && !sh.done[wave]) {
+      emu_chain_round(A, sh, wave, j0 + wave, round, step);
+    } else if (wave >= kEC && wave < kEC + nchain && !sh.done[wave - kEC]) {
+      // helper of chain c: the direction of iteration itsnap + 2 (iteration 1
+      // in round 0).  An iteration spans at least two rounds, so it is ready
+      // before its chain starts it, and the buffer it fills is never the one
+      // its chain reads in this round.
+      const int c = wave - kEC;
+      const int it = round == 0 ? 1 : sh.itsnap[c] + 2;
+      if (it < A.p.n_iter && sh.dit[c][it & 1] != it) {
+        emu_direction(A.p, sh.Lc[c], j0 + c, it, step, sh.zs2[c], sh.dv[c][it & 1], &sh.da0[c][it & 1]);
+        if (lane == 0) sh.dit[c][it & 1] = it;
+      }
+    }
     __syncthreads();
+    if (threadIdx.x < kEC) sh.itsnap[threadIdx.x] = sh.S[threadIdx.x].it;
     int alive = 0;
 #pragma unroll
     for (int c = 0; c < kEC; ++c) alive += sh.done[c] ? 0 : 1;
