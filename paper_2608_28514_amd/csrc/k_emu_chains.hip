@@ -88,13 +88,12 @@ __device__ __forceinline__ float emu_act(float z) {
 }
 
 struct EmuShared {
-  __attribute__((aligned(16))) __bf16 act[3 * kER * kEMaxW];   // activations, 3 planes of kER x width
+  __attribute__((aligned(16))) __bf16 act[2][3 * kER * kEMaxW];  // activations (two buffers, layers alternate), 3 planes of kER x width
   __attribute__((aligned(16))) __bf16 xin[3 * kER * 32];       // network input, 3 planes of kER x 32
   double part[kER * kEMaxOutB];                                // chi^2 partials, [row][column block]
   float bias[kEMaxBias];                                       // the layers' biases, layer after layer
   double dat[kEMaxOut];                                        // the data vector
   double isg[kEMaxOut];                                        // 1 / sigma
-  double rl[kER];                                              // row log-likelihoods of the last round
   int rflag[kER];                                              // row inside the box
   ChainState<float> S[kEC];
   float pts[kEC][kEP][kMaxD];                                  // the rows' points (state precision)
@@ -102,6 +101,9 @@ struct EmuShared {
   double tauj[kEC];                                            // each chain's shrink threshold L_W[j]
   float dv[kEC][2][kMaxD];                                     // directions of coming iterations (by parity)
   float da0[kEC][2];                                           // their stepping-out offsets
+  float dus[kEC][2][kEP];                                      // their first shrink uniforms
+  float us0[kEC][kEP];                                         // the current iteration's first shrink uniforms
+  int us0it[kEC];                                              // the iteration us0 holds (-1: none)
   int dit[kEC][2];                                             // the iteration each buffer holds (-1: none)
   float zs2[kEC][kMaxD];                                       // scratch of the waves that compute them
   int itsnap[kEC];                                             // each chain's iteration at the round's start
@@ -117,9 +119,14 @@ struct EmuShared {
 // chain's cluster factor in LDS) and stepping-out offset a0 of slice
 // iteration `it` of chain j, by one wave; zsc: kMaxD floats of scratch.
 __device__ __forceinline__ void emu_direction(const RoundsParams& p, const float* Lc, int j, int it, uint32_t step,
-                                              float* zsc, float* v, float* a0) {
+                                              float* zsc, float* v, float* a0, float* us) {
   const int lane = threadIdx.x & 63, d = p.d;
   const uint32_t c3 = (kStreamSlice << 24) | static_cast<uint32_t>(it);
+  // us (may be null): the uniforms of the iteration's first kEP shrink proposals
+  if (us && lane < kEP) {
+    const Draw2 du = uniform2(p.seed, kSlotShrink0 + lane, static_cast<uint32_t>(j), step, c3);
+    us[lane] = static_cast<float>(du.a);
+  }
   if (2 * lane < d) {
     const Draw2 dr = uniform2(p.seed, kSlotDir0 + lane, static_cast<uint32_t>(j), step, c3);
     const float r = DirMath<float>::r_of(static_cast<float>(dr.a));
@@ -169,7 +176,16 @@ __device__ __forceinline__ void emu_chain_round(const EmuArgs& A, EmuShared& sh,
   const float w_ = static_cast<float>(p.w);
   const int myrow = w * kEP + min(lane, kEP - 1);
   const int fl = round > 0 ? sh.rflag[myrow] : 0;
-  const double rl = round > 0 ? sh.rl[myrow] : -INFINITY;
+  double rl = -INFINITY;
+  if (round > 0) {
+    // the row's chi^2 partials summed in column-block order
+    const int nbo = A.net.widths[A.net.n_layers] >> 5;
+    double t = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < nbo; ++q) t += sh.part[myrow * kEMaxOutB + q];
+    const double v = -0.5 * t;
+    rl = (fl == 0 || isnan(v)) ? -INFINITY : v;
+  }
 
   if (round == 0) {
     if (lane == 0) {
@@ -255,13 +271,8 @@ __device__ __forceinline__ void emu_chain_round(const EmuArgs& A, EmuShared& sh,
     }
     if (mp) {
       // the accepted point, recomputed from the chain's line exactly as it was
-      // proposed (same draws, same bracket recurrence, same expression)
-      const uint32_t c3 = (kStreamSlice << 24) | static_cast<uint32_t>(S.it);
-      if (lane <= upto) {
-        const Draw2 du = uniform2(p.seed, kSlotShrink0 + S.s0 + lane, static_cast<uint32_t>(j), step, c3);
-        sh.Us[w][lane] = static_cast<float>(du.a);
-      }
-      wave_sync();
+      // proposed (the uniforms of those proposals are still in Us; same
+      // bracket recurrence, same expression)
       float us[kEP];
 #pragma unroll
       for (int q = 0; q < kEP; ++q) us[q] = sh.Us[w][q];
@@ -320,9 +331,11 @@ __device__ __forceinline__ void emu_chain_round(const EmuArgs& A, EmuShared& sh,
     const int b = S.it & 1;
     if (sh.dit[w][b] == S.it) {
       if (lane < d) S.v[lane] = sh.dv[w][b][lane];
-      if (lane == 0) S.a0 = sh.da0[w][b];
+      if (lane < kEP) sh.us0[w][lane] = sh.dus[w][b][lane];
+      if (lane == 0) { S.a0 = sh.da0[w][b]; sh.us0it[w] = S.it; }
     } else {
-      emu_direction(p, sh.Lc[w], j, S.it, step, sh.zs[w], S.v, &S.a0);
+      emu_direction(p, sh.Lc[w], j, S.it, step, sh.zs[w], S.v, &S.a0, nullptr);
+      if (lane == 0) sh.us0it[w] = -1;
     }
     wave_sync();
     if (lane == 0) {
@@ -343,7 +356,9 @@ __device__ __forceinline__ void emu_chain_round(const EmuArgs& A, EmuShared& sh,
   } else if (S.phase == kPhaseShrink) {
     const uint32_t c3 = (kStreamSlice << 24) | static_cast<uint32_t>(S.it);
     const int Sn = min(p.sh_spec, p.max_shrink - S.s0);
-    if (lane < Sn) {
+    if (S.s0 == 0 && sh.us0it[w] == S.it) {
+      if (lane < Sn) sh.Us[w][lane] = sh.us0[w][lane];
+    } else if (lane < Sn) {
       const Draw2 du = uniform2(p.seed, kSlotShrink0 + S.s0 + lane, static_cast<uint32_t>(j), step, c3);
       sh.Us[w][lane] = static_cast<float>(du.a);
     }
@@ -472,7 +487,7 @@ __device__ __forceinline__ void emu_pass(const __bf16* Al, int apl, const __bf16
 
 // act(z + bias) of a pass's tiles into the activation planes (width N).
 template <int NCB, int ACT>
-__device__ __forceinline__ void emu_store_hidden(EmuShared& sh, int N, int cb0, const float* bias,
+__device__ __forceinline__ void emu_store_hidden(__bf16* act, int N, int cb0, const float* bias,
                                                  const f32x4 (&acc)[kERB][NCB][2]) {
   const int lane = threadIdx.x & 63;
   const int apl = kER * N;
@@ -492,9 +507,9 @@ __device__ __forceinline__ void emu_store_hidden(EmuShared& sh, int N, int cb0, 
           const float r1 = x - static_cast<float>(h);
           const __bf16 md = static_cast<__bf16>(r1);
           const long fi = frag_index(row, n, N);
-          sh.act[fi] = h;
-          sh.act[apl + fi] = md;
-          sh.act[2 * apl + fi] = static_cast<__bf16>(r1 - static_cast<float>(md));
+          act[fi] = h;
+          act[apl + fi] = md;
+          act[2 * apl + fi] = static_cast<__bf16>(r1 - static_cast<float>(md));
         }
     }
 }
@@ -534,8 +549,9 @@ __device__ __forceinline__ void emu_store_chi2(EmuShared& sh, int cb0, const flo
 
 // One layer over all kER rows, NCB = N/256 column blocks per wave in one
 // pass.  First layer (S = 1): input from xin (weights in three planes);
-// hidden layers: input from and output to the activation planes (in place,
-// after every wave has read its input); output layer: chi^2 partials.
+// hidden layer l reads activation buffer (l + 1) & 1 and writes buffer l & 1
+// (a layer never writes the buffer other waves may still be reading);
+// output layer: chi^2 partials.
 template <int NCB, int S, bool FIRST, bool OUT>
 __device__ __forceinline__ void emu_layer(EmuShared& sh, const EmuNet& net, int l, int boff) {
   const int wave = threadIdx.x >> 6;
@@ -543,15 +559,15 @@ __device__ __forceinline__ void emu_layer(EmuShared& sh, const EmuNet& net, int 
   const int cb0 = wave * NCB;
   f32x4 acc[kERB][NCB][2];
   if (FIRST) emu_pass<NCB, 3, 1>(sh.xin, kER * 32, net.Wf[0], static_cast<long>(N) * 32, cb0, acc);
-  else emu_pass<NCB, 1, S>(sh.act, kER * S * 32, net.Wf[l], 0L, cb0, acc);
+  else emu_pass<NCB, 1, S>(sh.act[(l + 1) & 1], kER * S * 32, net.Wf[l], 0L, cb0, acc);
   if (OUT) {
     emu_store_chi2<NCB>(sh, cb0, sh.bias + boff, acc);
   } else {
-    if (!FIRST) __syncthreads();     // every wave has read the layer's input
     // the activation chosen once per layer: no branch per element
-    if (net.act == kActTanh) emu_store_hidden<NCB, kActTanh>(sh, N, cb0, sh.bias + boff, acc);
-    else if (net.act == kActSilu) emu_store_hidden<NCB, kActSilu>(sh, N, cb0, sh.bias + boff, acc);
-    else emu_store_hidden<NCB, kActNone>(sh, N, cb0, sh.bias + boff, acc);
+    __bf16* out = sh.act[l & 1];
+    if (net.act == kActTanh) emu_store_hidden<NCB, kActTanh>(out, N, cb0, sh.bias + boff, acc);
+    else if (net.act == kActSilu) emu_store_hidden<NCB, kActSilu>(out, N, cb0, sh.bias + boff, acc);
+    else emu_store_hidden<NCB, kActNone>(out, N, cb0, sh.bias + boff, acc);
   }
   __syncthreads();
 }
@@ -586,7 +602,8 @@ k_emu_chains(EmuArgs A) {
   // inputs beyond the first d columns stay zero; rows of absent chains never
   // reach an output
   for (int q = threadIdx.x; q < 3 * kER * 32; q += 64 * kEW) sh.xin[q] = static_cast<__bf16>(0.f);
-  if (threadIdx.x < kER) { sh.rflag[threadIdx.x] = 0; sh.rl[threadIdx.x] = -INFINITY; }
+  if (threadIdx.x < kER) sh.rflag[threadIdx.x] = 0;
+  if (threadIdx.x < kEC) sh.us0it[threadIdx.x] = -1;
   if (threadIdx.x < kEC) sh.done[threadIdx.x] = threadIdx.x < nchain ? 0 : 1;
   if (threadIdx.x == 0) sh.taue = A.LW[0];
   if (threadIdx.x < 2 * kEC) sh.dit[threadIdx.x >> 1][threadIdx.x & 1] = -1;
@@ -617,7 +634,6 @@ k_emu_chains(EmuArgs A) {
   if (threadIdx.x == 0) sh.rows = 0ull;
   __syncthreads();
   const int L = A.net.n_layers;
-  const int nbo = A.net.widths[L] >> 5;
   for (int round = 0;; ++round) {
     if (wave < nchain && !sh.done[wave]) {
       emu_chain_round(A, sh, wave, j0 + wave, round, step);
@@ -629,7 +645,8 @@ k_emu_chains(EmuArgs A) {
       const int c = wave - kEC;
       const int it = round == 0 ? 1 : sh.itsnap[c] + 2;
       if (it < A.p.n_iter && sh.dit[c][it & 1] != it) {
-        emu_direction(A.p, sh.Lc[c], j0 + c, it, step, sh.zs2[c], sh.dv[c][it & 1], &sh.da0[c][it & 1]);
+        emu_direction(A.p, sh.Lc[c], j0 + c, it, step, sh.zs2[c], sh.dv[c][it & 1], &sh.da0[c][it & 1],
+                      sh.dus[c][it & 1]);
         if (lane == 0) sh.dit[c][it & 1] = it;
       }
     }
@@ -647,15 +664,7 @@ k_emu_chains(EmuArgs A) {
       else emu_layer_any<false, false>(sh, A.net, l, boff);
       boff += A.net.widths[l + 1];
     }
-    // row log-likelihoods: the partials summed in column-block order
-    if (threadIdx.x < kER) {
-      const int r = threadIdx.x;
-      double t = 0.0;
-      for (int q = 0; q < nbo; ++q) t += sh.part[r * kEMaxOutB + q];
-      const double v = -0.5 * t;
-      sh.rl[r] = (sh.rflag[r] == 0 || isnan(v)) ? -INFINITY : v;
-    }
-    __syncthreads();
+    // (each chain sums its rows' chi^2 partials when it consumes them)
   }
   if (threadIdx.x == 0 && A.net_rows && sh.rows) atomicAdd(A.net_rows, sh.rows);
   (void)lane;
