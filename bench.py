@@ -45,6 +45,16 @@ EMU_FLOPS = 2 * (27 * 512 + 512 * 512 * 2 + 512 * 1024)   # one emulator evaluat
 # (padded) inputs in the first layer, three activation terms afterwards
 EMU_MFMA_ISSUED = 2 * (9 * 32 * 512 + 3 * (512 * 512 * 2 + 512 * 1024))
 METRIC = "live-point updates/s at |dlogZ|<2sigma vs oracle, 1 GPU"
+# Counters of the persistent chain kernel at N = 4000, m = 400, BF16x3 (the
+# default workload), per launch over its first 12 steps, from
+#   rocprofv3 --pmc FETCH_SIZE  / WRITE_SIZE / TCP_TCC_READ_REQ_sum TCC_HIT_sum ... -- python3 bench.py --steps 10 --warmup 2 --timed-only --no-cpu-baseline
+# FETCH_SIZE is scaled by 2.0 and WRITE_SIZE by 1.0 (the factors a plain
+# 256 MiB device copy reads for the same counters); L1-to-L2 read requests
+# are 128-byte lines.  Valid only for the kernel source they were taken on.
+EMU_CHAINS_COUNTERS = {"source_sha256": "69bbd002746444c124201ac194ef18485d526b052e88fa594315ba75b6b6e9b3",
+                       "fetch_kib": 11928.0, "write_kib": 21477.0, "tcp_tcc_read_req": 9.4331e8,
+                       "tcc_hit": 9.4597e8, "tcc_miss": 3.3579e5}
+L2_CU_PEAK = 64 * 256 * 2.4e9       # MI355X L2-to-CU fill bandwidth: 64 B per clock per CU, 256 CUs
 
 
 def cpu_model():
@@ -81,6 +91,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--screen", default="",
                     help="learned-screen settings as k=v pairs, e.g. margin=3,train_every=4")
+    ap.add_argument("--rounds-driver", action="store_true",
+                    help="emulator: the batched-rounds driver (layer kernels per round) instead of the persistent chain kernel")
     ap.add_argument("--stepout-spec", type=int, default=None)
     ap.add_argument("--shrink-spec", type=int, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -156,6 +168,8 @@ def log(msg):
 # ---------------------------------------------------------------- 27-d emulator (default)
 def _emu_sampler(native, spec, N, prec, seed, args, screen):
     kw = dict(prec=prec, state="f32", tree_depth=1, seed=seed)
+    if args.rounds_driver:
+        kw["fused_chains"] = 0
     if args.stepout_spec:
         kw["stepout_spec"] = args.stepout_spec
     if args.shrink_spec:
@@ -232,9 +246,23 @@ def bench_emulator(args, np, torch, native, workloads):
                  "k_gemm<F32> layers + k_chi2")
         note = ("one launch = the layer kernels of one batched round, timed by HIP events on the "
                 "context's stream; useful work 2,124,800 FLOP per network row")
+    traffic, l2 = None, None
+    if fused and prec == "bf16x3" and (N, m) == (4000, 400):
+        import hashlib
+        src = os.path.join(ROOT, "paper_2608_28514_amd", "csrc", "k_emu_chains.hip")
+        cnt = EMU_CHAINS_COUNTERS
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() == cnt["source_sha256"]:
+            traffic = 1024.0 * (2.0 * cnt["fetch_kib"] + cnt["write_kib"])
+            l2b = 128.0 * cnt["tcp_tcc_read_req"]
+            t_launch = k_ms * 1e-3 / max(k_launches, 1)
+            l2 = {"bytes_per_launch": l2b, "achieved_TBps": l2b / t_launch / 1e12,
+                  "peak_TBps": L2_CU_PEAK / 1e12, "frac": l2b / t_launch / L2_CU_PEAK,
+                  "l2_hit_rate": cnt["tcc_hit"] / (cnt["tcc_hit"] + cnt["tcc_miss"]),
+                  "note": "L1-to-L2 read requests x 128 B: the weights every workgroup streams each round; "
+                          "200 of the 256 CUs hold a workgroup"}
     roof = {"kernel": kname, "bound": "mfma" if prec.startswith("bf16") else "alu",
             "achieved": useful / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": useful / peak,
-            "traffic": None,
+            "traffic": traffic, "l2_to_cu": l2,
             "flops_per_launch": rows * EMU_FLOPS / max(k_launches, 1),
             "avg_launch_us": 1e3 * k_ms / max(k_launches, 1), "launches": k_launches,
             "rows_per_launch": rows / max(k_launches, 1),
