@@ -389,7 +389,7 @@ __device__ __forceinline__ void emu_chain_round(const EmuArgs& A, EmuShared& sh,
   uint32_t inmask = 0;
 #pragma unroll
   for (int q = 0; q < kEP; ++q) {
-    const float tq = __shfl(toff, q);
+    const float tq = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(toff), q));
     if (!((hmask >> q) & 1ull)) continue;
     const float yi = xi + tq * vi;
     const bool out = coord && !((yi >= 0.f) & (yi <= 1.f));
