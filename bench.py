@@ -51,9 +51,9 @@ METRIC = "live-point updates/s at |dlogZ|<2sigma vs oracle, 1 GPU"
 # FETCH_SIZE is scaled by 2.0 and WRITE_SIZE by 1.0 (the factors a plain
 # 256 MiB device copy reads for the same counters); L1-to-L2 read requests
 # are 128-byte lines.  Valid only for the kernel source they were taken on.
-EMU_CHAINS_COUNTERS = {"source_sha256": "69bbd002746444c124201ac194ef18485d526b052e88fa594315ba75b6b6e9b3",
-                       "fetch_kib": 11928.0, "write_kib": 21477.0, "tcp_tcc_read_req": 9.4331e8,
-                       "tcc_hit": 9.4597e8, "tcc_miss": 3.3579e5}
+EMU_CHAINS_COUNTERS = {"source_sha256": "cea38a13fc4b306e66a7822605483949bef1aa0d27c4ba1397c1c42d820518fa",
+                       "fetch_kib": 11115.0, "write_kib": 21077.0, "tcp_tcc_read_req": 9.4342e8,
+                       "tcc_hit": 9.4673e8, "tcc_miss": 3.188e5}
 L2_CU_PEAK = 64 * 256 * 2.4e9       # MI355X L2-to-CU fill bandwidth: 64 B per clock per CU, 256 CUs
 
 
