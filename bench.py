@@ -233,14 +233,20 @@ def bench_emulator(args, np, torch, native, workloads):
     log(f"timed {args.steps} steps: {t_steps:.3f} s, {dead / t_steps:.0f} updates/s, "
         f"{rows} network rows, dominant kernel {k_ms:.1f} ms over {k_launches} launches")
     useful = rows * EMU_FLOPS / (k_ms * 1e-3)
-    issued = rows * EMU_MFMA_ISSUED / (k_ms * 1e-3)
+    # split-bfloat16 layers issue three MFMA per product (nine in the first layer); FP32 layers one
+    issued = rows * (EMU_MFMA_ISSUED if prec == "bf16x3" else EMU_FLOPS) / (k_ms * 1e-3)
     peak = BF16_PEAK if prec.startswith("bf16") else FP32_PEAK
-    if fused:
+    if fused and prec != "f32":
         kname = ("k_emu_chains: a step's chains in one persistent launch, each workgroup evaluating its "
                  "chains' rows through the four layers (27-512, 512-512, 512-512, 512-1024 + chi^2)")
         note = ("one launch per step, timed by HIP events on the context's stream; useful work 2,124,800 "
                 "FLOP per network row (the split activations issue 3x that on MFMA, 9x in the first layer); "
                 "the chain logic runs inside the same launch")
+    elif fused:
+        kname = ("k_emu_chains<FP32>: a step's chains in one persistent launch, the four layers on the FP32 "
+                 "MFMA (16x16x4) with FP32 activations in LDS")
+        note = ("one launch per step, timed by HIP events on the context's stream; useful work 2,124,800 "
+                "FLOP per network row against the FP32 matrix peak")
     else:
         kname = ("k_dense_frag: the four dense layers of one round" if prec.startswith("bf16") else
                  "k_gemm<F32> layers + k_chi2")
@@ -260,7 +266,7 @@ def bench_emulator(args, np, torch, native, workloads):
                   "l2_hit_rate": cnt["tcc_hit"] / (cnt["tcc_hit"] + cnt["tcc_miss"]),
                   "note": "L1-to-L2 read requests x 128 B: the weights every workgroup streams each round; "
                           "200 of the 256 CUs hold a workgroup"}
-    roof = {"kernel": kname, "bound": "mfma" if prec.startswith("bf16") else "alu",
+    roof = {"kernel": kname, "bound": "mfma" if prec.startswith("bf16") or fused else "alu",
             "achieved": useful / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": useful / peak,
             "traffic": traffic, "l2_to_cu": l2,
             "flops_per_launch": rows * EMU_FLOPS / max(k_launches, 1),

@@ -18,6 +18,11 @@
 // chi^2 butterfly, and a row's chi^2 partials are summed in column-block
 // order; the chain decisions, draws, counts and history are the rounds
 // driver's.  A run is therefore identical to one on the rounds driver.
+//
+// With FP32 layers the same kernel runs the network on the FP32 MFMA
+// (16 x 16 x 4), activations in FP32 in LDS; its sums are ordered
+// differently from the FP32 layer kernels', so such runs agree with the
+// rounds driver's to FP32 rounding, not bit for bit.
 #include "ns_internal.hpp"
 #include "ns_gemm.hpp"
 #include "ns_rounds.hpp"
@@ -47,6 +52,7 @@ struct EmuNet {
   int act;               // hidden activation
   int widths[9];
   const __bf16* Wf[8];   // fragment-major W^T; layer 0: three planes of widths[1] x 32
+  const float* Wq[8];    // FP32 layers: W^T in 16 x 16 blocks (fragq_index)
   const float* b[8];
   const double* data;
   const double* isig;
@@ -71,6 +77,13 @@ struct EmuArgs {
   const RunState* st;
   unsigned long long* net_rows;
 };
+
+// FP32 MFMA operands (16 x 16 x 4): 16 x 16 blocks of 16 rows (or weight
+// columns) by 16 K; lane l holds, for the block's four K steps t, the element
+// (l & 15, 4 t + (l >> 4)), so one 16-byte load per lane fetches a block.
+__host__ __device__ inline long fragq_index(long r, int k, int K) {
+  return ((r >> 4) * (K >> 4) + (k >> 4)) * 256 + ((r & 15) + 16 * (k & 3)) * 4 + ((k >> 2) & 3);
+}
 
 // LDS ordering inside one wave (chain logic): every lane's earlier LDS writes
 // are visible to the wave's later LDS reads.
@@ -167,6 +180,7 @@ __device__ __forceinline__ void emu_direction(const RoundsParams& p, const float
 
 // One round of chain j on wave w (64 lanes): consume the likelihoods of the
 // rows it proposed in the previous round, then propose the next kEP rows.
+template <bool F32>
 __device__ __forceinline__ void emu_chain_round(const EmuArgs& A, EmuShared& sh, int w, int j, int round, uint32_t step) {
   const RoundsParams& p = A.p;
   const int lane = threadIdx.x & 63;
@@ -397,13 +411,17 @@ __device__ __forceinline__ void emu_chain_round(const EmuArgs& A, EmuShared& sh,
     if (coord) {
       sh.pts[w][q][lane] = yi;
       const float xv = lo_i + span_i * yi;
-      const long fi = frag_index(w * kEP + q, lane, 32);
-      const __bf16 h = static_cast<__bf16>(xv);
-      const float r1 = xv - static_cast<float>(h);
-      const __bf16 mm = static_cast<__bf16>(r1);
-      sh.xin[fi] = h;
-      sh.xin[kER * 32 + fi] = mm;
-      sh.xin[2 * kER * 32 + fi] = static_cast<__bf16>(r1 - static_cast<float>(mm));
+      if constexpr (F32) {
+        reinterpret_cast<float*>(sh.xin)[fragq_index(w * kEP + q, lane, 32)] = xv;
+      } else {
+        const long fi = frag_index(w * kEP + q, lane, 32);
+        const __bf16 h = static_cast<__bf16>(xv);
+        const float r1 = xv - static_cast<float>(h);
+        const __bf16 mm = static_cast<__bf16>(r1);
+        sh.xin[fi] = h;
+        sh.xin[kER * 32 + fi] = mm;
+        sh.xin[2 * kER * 32 + fi] = static_cast<__bf16>(r1 - static_cast<float>(mm));
+      }
     }
   }
   inb = lane < kEP && ((inmask >> lane) & 1u);
@@ -572,6 +590,108 @@ __device__ __forceinline__ void emu_layer(EmuShared& sh, const EmuNet& net, int 
   __syncthreads();
 }
 
+// ---------------------------------------------------------------- FP32 network
+// One pass of a wave over NCB column blocks (two 16-wide tiles each) with FP32
+// operands, KB K blocks of 16: activations from LDS (fragq layout), weight
+// blocks from L2 through a register ring; per block, K steps in order.
+template <int NCB, int KB>
+__device__ __forceinline__ void emu_pass_f32(const float* Al, const float* __restrict__ Wq, int cb0,
+                                             f32x4 (&acc)[kERB][NCB][2]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int r = 0; r < kERB; ++r)
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) acc[r][c][0] = acc[r][c][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+  constexpr long tstep = static_cast<long>(KB) * 256;   // next 16-column tile
+  const float* bp = Wq + static_cast<long>(2 * cb0) * tstep + lane * 4;
+  constexpr int DS = NCB >= 4 ? kEStages - 1 : kEStages;
+  constexpr int D = KB < DS ? KB : DS;
+  f32x4 b[D][NCB][2];
+  auto loadb = [&](int s, f32x4 (&bb)[NCB][2]) {
+#pragma unroll
+    for (int c = 0; c < NCB; ++c)
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+        bb[c][t] = *reinterpret_cast<const f32x4*>(bp + (2 * c + t) * tstep + static_cast<long>(s) * 256);
+  };
+#pragma unroll
+  for (int s = 0; s < D - 1; ++s) loadb(s, b[s]);
+#pragma unroll
+  for (int s = 0; s < KB; ++s) {
+    if (s + D - 1 < KB) loadb(s + D - 1, b[(s + D - 1) % D]);
+    f32x4 a[kERB];
+#pragma unroll
+    for (int r = 0; r < kERB; ++r) a[r] = *reinterpret_cast<const f32x4*>(Al + (r * KB + s) * 256 + lane * 4);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < kERB; ++r)
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) {
+          acc[r][c][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][q], b[s % D][c][0][q], acc[r][c][0], 0, 0, 0);
+          acc[r][c][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][q], b[s % D][c][1][q], acc[r][c][1], 0, 0, 0);
+        }
+  }
+}
+
+// act(z + bias) of a pass's tiles into an FP32 activation buffer (width N).
+template <int NCB, int ACT>
+__device__ __forceinline__ void emu_store_hidden_f32(float* act, int N, int cb0, const float* bias,
+                                                     const f32x4 (&acc)[kERB][NCB][2]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int c = 0; c < NCB; ++c)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int n = (cb0 + c) * 32 + t * 16 + (lane & 15);
+      const float bz = bias[n];
+#pragma unroll
+      for (int r = 0; r < kERB; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = r * 16 + 4 * (lane >> 4) + i;
+          act[fragq_index(row, n, N)] = emu_act<ACT>(acc[r][c][t][i] + bz);
+        }
+    }
+}
+
+// An FP32 layer over all kER rows (the buffers as in emu_layer, in FP32).
+template <int NCB, int KB, bool FIRST, bool OUT>
+__device__ __forceinline__ void emu_layer_f32(EmuShared& sh, const EmuNet& net, int l, int boff) {
+  const int wave = threadIdx.x >> 6;
+  const int N = net.widths[l + 1];
+  const int cb0 = wave * NCB;
+  f32x4 acc[kERB][NCB][2];
+  if (FIRST) emu_pass_f32<NCB, 2>(reinterpret_cast<const float*>(sh.xin), net.Wq[0], cb0, acc);
+  else emu_pass_f32<NCB, KB>(reinterpret_cast<const float*>(sh.act[(l + 1) & 1]), net.Wq[l], cb0, acc);
+  if (OUT) {
+    emu_store_chi2<NCB>(sh, cb0, sh.bias + boff, acc);
+  } else {
+    float* out = reinterpret_cast<float*>(sh.act[l & 1]);
+    if (net.act == kActTanh) emu_store_hidden_f32<NCB, kActTanh>(out, N, cb0, sh.bias + boff, acc);
+    else if (net.act == kActSilu) emu_store_hidden_f32<NCB, kActSilu>(out, N, cb0, sh.bias + boff, acc);
+    else emu_store_hidden_f32<NCB, kActNone>(out, N, cb0, sh.bias + boff, acc);
+  }
+  __syncthreads();
+}
+
+template <bool FIRST, bool OUT>
+__device__ __forceinline__ void emu_layer_any_f32(EmuShared& sh, const EmuNet& net, int l, int boff) {
+  const int N = net.widths[l + 1], K = FIRST ? 32 : net.widths[l];
+  if (FIRST) {
+    if (N == 256) emu_layer_f32<1, 2, true, OUT>(sh, net, l, boff);
+    else emu_layer_f32<2, 2, true, OUT>(sh, net, l, boff);
+  } else if (K == 256) {
+    if (N == 256) emu_layer_f32<1, 16, false, OUT>(sh, net, l, boff);
+    else if (N == 512) emu_layer_f32<2, 16, false, OUT>(sh, net, l, boff);
+    else emu_layer_f32<4, 16, false, OUT>(sh, net, l, boff);
+  } else {
+    if (N == 256) emu_layer_f32<1, 32, false, OUT>(sh, net, l, boff);
+    else if (N == 512) emu_layer_f32<2, 32, false, OUT>(sh, net, l, boff);
+    else emu_layer_f32<4, 32, false, OUT>(sh, net, l, boff);
+  }
+}
+
 // dispatch on the layer's width (N = 256 NCB) and input depth (K = 32 S)
 template <bool FIRST, bool OUT>
 __device__ __forceinline__ void emu_layer_any(EmuShared& sh, const EmuNet& net, int l, int boff) {
@@ -590,6 +710,7 @@ __device__ __forceinline__ void emu_layer_any(EmuShared& sh, const EmuNet& net, 
   }
 }
 
+template <bool F32>
 __global__ void __launch_bounds__(64 * kEW)
 k_emu_chains(EmuArgs A) {
   __shared__ EmuShared sh;
@@ -636,7 +757,7 @@ k_emu_chains(EmuArgs A) {
   const int L = A.net.n_layers;
   for (int round = 0;; ++round) {
     if (wave < nchain && !sh.done[wave]) {
-      emu_chain_round(A, sh, wave, j0 + wave, round, step);
+      emu_chain_round<F32>(A, sh, wave, j0 + wave, round, step);
     } else if (wave >= kEC && wave < kEC + nchain && !sh.done[wave - kEC]) {
       // helper of chain c: the direction of iteration itsnap + 2 (iteration 1
       // in round 0).  An iteration spans at least two rounds, so it is ready
@@ -657,11 +778,17 @@ k_emu_chains(EmuArgs A) {
     for (int c = 0; c < kEC; ++c) alive += sh.done[c] ? 0 : 1;
     if (alive == 0) break;
     // the kER rows through the network
-    emu_layer_any<true, false>(sh, A.net, 0, 0);
+    if constexpr (F32) emu_layer_any_f32<true, false>(sh, A.net, 0, 0);
+    else emu_layer_any<true, false>(sh, A.net, 0, 0);
     int boff = A.net.widths[1];
     for (int l = 1; l < L; ++l) {
-      if (l == L - 1) emu_layer_any<false, true>(sh, A.net, l, boff);
-      else emu_layer_any<false, false>(sh, A.net, l, boff);
+      if constexpr (F32) {
+        if (l == L - 1) emu_layer_any_f32<false, true>(sh, A.net, l, boff);
+        else emu_layer_any_f32<false, false>(sh, A.net, l, boff);
+      } else {
+        if (l == L - 1) emu_layer_any<false, true>(sh, A.net, l, boff);
+        else emu_layer_any<false, false>(sh, A.net, l, boff);
+      }
       boff += A.net.widths[l + 1];
     }
     // (each chain sums its rows' chi^2 partials when it consumes them)
@@ -670,7 +797,7 @@ k_emu_chains(EmuArgs A) {
   (void)lane;
 }
 
-bool emu_chains_eligible(const NetDev& net, const RoundsParams& p, int state_f32) {
+bool emu_chains_eligible(const NetDev& net, const RoundsParams& p, int state_f32, bool f32) {
   if (!state_f32 || p.P != kEP || 2 * p.so_spec > kEP || p.sh_spec > kEP || p.d > kMaxD) return false;
   const int L = net.n_layers;
   if (L < 2 || L > 8 || net.widths[0] > 32) return false;
@@ -681,12 +808,18 @@ bool emu_chains_eligible(const NetDev& net, const RoundsParams& p, int state_f32
   if (net.widths[L] != 256 && net.widths[L] != 512 && net.widths[L] != 1024) return false;
   static_assert(kEMaxOut >= 1024 && kEMaxBias >= 7 * 512 + 1024, "LDS room for every eligible network");
   for (int l = 0; l < L; ++l)
-    if (!net.Wf[l]) return false;
+    if (f32 ? !net.Wq[l] : !net.Wf[l]) return false;
   return true;
 }
 
-hipError_t launch_emu_chains(const RoundsParams& p, const NetDev& net, const double* data, const double* isig,
-                             const Shape& sh, const DevBufs& b, unsigned long long* net_rows, hipStream_t s) {
+void fragq_layout_host(const float* wt, int N, int K, int Kp, float* out) {
+  for (int n = 0; n < N; ++n)
+    for (int k = 0; k < Kp; ++k) out[fragq_index(n, k, Kp)] = k < K ? wt[static_cast<long>(n) * K + k] : 0.f;
+}
+
+hipError_t launch_emu_chains(const RoundsParams& p, const NetDev& net, bool f32, const double* data,
+                             const double* isig, const Shape& sh, const DevBufs& b, unsigned long long* net_rows,
+                             hipStream_t s) {
   EmuArgs A{};
   A.p = p;
   A.net.n_layers = net.n_layers;
@@ -694,6 +827,7 @@ hipError_t launch_emu_chains(const RoundsParams& p, const NetDev& net, const dou
   for (int l = 0; l <= net.n_layers; ++l) A.net.widths[l] = net.widths[l];
   for (int l = 0; l < net.n_layers; ++l) {
     A.net.Wf[l] = net.Wf[l];
+    A.net.Wq[l] = net.Wq[l];
     A.net.b[l] = net.b[l];
   }
   A.net.data = data;
@@ -715,7 +849,8 @@ hipError_t launch_emu_chains(const RoundsParams& p, const NetDev& net, const dou
   A.net_rows = net_rows;
   (void)sh;
   const int grid = (p.m + kEC - 1) / kEC;
-  hipLaunchKernelGGL(k_emu_chains, dim3(grid), dim3(64 * kEW), 0, s, A);
+  if (f32) hipLaunchKernelGGL(k_emu_chains<true>, dim3(grid), dim3(64 * kEW), 0, s, A);
+  else hipLaunchKernelGGL(k_emu_chains<false>, dim3(grid), dim3(64 * kEW), 0, s, A);
   return hipGetLastError();
 }
 

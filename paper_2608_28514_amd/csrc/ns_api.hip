@@ -57,6 +57,7 @@ struct ns_ctx {
   double* mlp_isig = nullptr;
   bool emu_frag = false;      // emulator likelihood on the fragment-major path (emu_forward_logL)
   bool emu_chains = false;    // a step's chains in one persistent launch (k_emu_chains)
+  bool emu_f32 = false;       // ... with FP32 layers (the FP32 MFMA)
   // host likelihood (NS_LIK_CALLBACK): rows staged through pinned memory
   ns_lik_callback cb = nullptr;
   void* cb_user = nullptr;
@@ -730,6 +731,14 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
         NS_INIT_TRY(upload(c, wf.data(), wf.size(), &net.Wf[0]));
       }
       NS_INIT_TRY(upload(c, bb.data(), bb.size(), &net.b[l]));
+      if (lik->prec == NS_FP32 && Nn % 32 == 0 && (l > 0 || K <= 32)) {
+        // FP32 blocks for the chain kernel's FP32 MFMA (K padded to 16; the
+        // first layer's input to 32, the width of the network-input rows)
+        const int Kp = l == 0 ? 32 : (K + 15) / 16 * 16;
+        std::vector<float> wq(static_cast<size_t>(Nn) * Kp);
+        fragq_layout_host(wt.data(), Nn, K, Kp, wq.data());
+        NS_INIT_TRY(upload(c, wq.data(), wq.size(), &net.Wq[l]));
+      }
       if (lik->prec == NS_BF16X3 && l >= 1 && K % 32 == 0) {
         std::vector<__bf16> wb(wt.size());
         for (size_t q = 0; q < wt.size(); ++q) wb[q] = static_cast<__bf16>(wt[q]);
@@ -873,8 +882,9 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
       NS_INIT_HIP(hipMemsetAsync(rb.rthr, 0, sizeof(double) * rb.rows_cap, c->stream));
       NS_INIT_HIP(hipMemsetAsync(c->s_norm, 0, sizeof(float) * kNormLen, c->stream));
     }
-    c->emu_chains = c->is_mlp && c->emu_frag && cfg->fused_chains != 0 &&
-                    emu_chains_eligible(c->net, rp, sh.state_f32);
+    c->emu_f32 = c->is_mlp && c->mode_first == kF32 && c->mode_rest == kF32;
+    c->emu_chains = c->is_mlp && (c->emu_frag || c->emu_f32) && cfg->fused_chains != 0 &&
+                    emu_chains_eligible(c->net, rp, sh.state_f32, c->emu_f32);
     NS_INIT_HIP(launch_init_rows(n_live, d, cfg->seed, rp, sh.state_f32, b.u, rb.pts, rb.xin, rb.flag,
                                  c->stream));
     NS_INIT_TRY(eval_rows(c, n_live, nullptr));
@@ -960,7 +970,8 @@ ns_status ns_step_batch(ns_ctx* c, int m) {
     RoundsParams rp = c->rp;
     rp.m = m;
     TimeScope ts(c, NS_TIME_SLICE);
-    NS_TRY(launch_emu_chains(rp, c->net, c->mlp_data, c->mlp_isig, c->sh, c->b, &c->d_sc->emu_rows, c->stream));
+    NS_TRY(launch_emu_chains(rp, c->net, c->emu_f32, c->mlp_data, c->mlp_isig, c->sh, c->b, &c->d_sc->emu_rows,
+                             c->stream));
   } else if (c->batched) {
     ns_status r = run_rounds(c, m);
     if (r != NS_OK) return r;

@@ -56,6 +56,8 @@ struct NetDev {
   const __bf16* Wb[8];  // bfloat16 copies of Wt (layers >= 1) for the split-activation path
   const __bf16* Wf[8];  // the same in the fragment-major layout (emu_forward_logL); layer 0:
                         // hi, mid, lo planes of widths[1] x 32 (inputs padded with zeros)
+  const float* Wq[8];   // FP32 W^T in 16 x 16 blocks for the FP32 MFMA (k_emu_chains, FP32
+                        // layers); K padded with zeros to a multiple of 16
 };
 
 // Forward over M rows of X (M x widths[0]); H0/H1 ping-pong buffers of

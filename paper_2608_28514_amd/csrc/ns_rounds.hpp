@@ -68,12 +68,18 @@ hipError_t launch_rows_from_points(long n, int d, const double* u, const RoundsP
 hipError_t launch_init_rows(int N, int d, uint64_t seed, const RoundsParams& p, int state_f32, void* u,
                             void* pts, float* xin, int* flag, hipStream_t s);
 // A step's chains with a network likelihood in one persistent launch
-// (k_emu_chains.hip): same results as the rounds driver.  Eligible for FP32
-// state, split-bfloat16 fragment-major layers, P = 8 rows per chain and round,
-// hidden widths 256 or 512, output width a multiple of 512 up to 2048.
-bool emu_chains_eligible(const NetDev& net, const RoundsParams& p, int state_f32);
-hipError_t launch_emu_chains(const RoundsParams& p, const NetDev& net, const double* data, const double* isig,
-                             const Shape& sh, const DevBufs& b, unsigned long long* net_rows, hipStream_t s);
+// (k_emu_chains.hip): with split-bfloat16 layers the same results as the
+// rounds driver, with FP32 layers (f32: the FP32 MFMA) the same to FP32
+// rounding.  Eligible for FP32 state, P = 8 rows per chain and round, at most
+// 8 layers, input width <= 32, hidden widths 256 or 512, output width 256,
+// 512 or 1024, and the weights in the layout of the chosen arithmetic.
+bool emu_chains_eligible(const NetDev& net, const RoundsParams& p, int state_f32, bool f32);
+hipError_t launch_emu_chains(const RoundsParams& p, const NetDev& net, bool f32, const double* data,
+                             const double* isig, const Shape& sh, const DevBufs& b, unsigned long long* net_rows,
+                             hipStream_t s);
+// W^T (N x K row major) into the FP32 MFMA block layout of N x Kp (Kp a
+// multiple of 16, columns k >= K zero).
+void fragq_layout_host(const float* wt, int N, int K, int Kp, float* out);
 // analytic likelihood on rows (the batched driver with an analytic family)
 hipError_t launch_rows_loglike(const Shape& sh, const LikDev& lik, long n, const void* pts,
                                const int* flag, double* out, const int* gate, hipStream_t s);
