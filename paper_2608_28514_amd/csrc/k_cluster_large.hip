@@ -58,8 +58,18 @@ struct CLWork {
 
 size_t cluster_split_work_bytes() { return sizeof(CLWork); }
 
+// v summed over the wave by the butterfly with partners lane ^ 32, ^ 16, ^ 8,
+// ^ 4, ^ 2, ^ 1.  After the first two steps a lane's value depends only on
+// lane mod 16, and after each later step only on lane mod o, so the last four
+// partners are met by rotating each 16-lane row (DPP), which finds the same
+// values as the xor partners: the sums are the butterfly's, bit for bit.
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  v += __shfl_xor(v, 32);
+  v += __shfl_xor(v, 16);
+  v += dpp_row_ror<8>(v);
+  v += dpp_row_ror<4>(v);
+  v += dpp_row_ror<2>(v);
+  v += dpp_row_ror<1>(v);
   return v;
 }
 
@@ -719,8 +729,11 @@ hipError_t launch_cluster_split(const float* u, long N, int d, int iters, double
   } else {
     hipLaunchKernelGGL(k_cl_sum<32>, dim3(G), dim3(256), 0, s, u, N, d, w);
     hipLaunchKernelGGL(k_cl_red_mean, dim3(R), dim3(256), 0, s, N, d, G, mean, w);
-    hipLaunchKernelGGL(k_cl_cov, dim3(G), dim3(64), 0, s, u, N, d, mean, w);
-    hipLaunchKernelGGL(k_cl_red_cov, dim3(R), dim3(256), 0, s, N, d, G, cov, w);
+    // one wave per workgroup: a workgroup per 64 points (up to kCLGroups), so
+    // that small point sets still spread over many CUs
+    const int Gc = static_cast<int>(std::min<long>(kCLGroups, std::max<long>(1, (N + 63) / 64)));
+    hipLaunchKernelGGL(k_cl_cov, dim3(Gc), dim3(64), 0, s, u, N, d, mean, w);
+    hipLaunchKernelGGL(k_cl_red_cov, dim3((Gc + kCLFan - 1) / kCLFan), dim3(256), 0, s, N, d, Gc, cov, w);
   }
   for (int which = 0; which < 2; ++which) {
     NS_CL_DM(k_cl_far, u, N, d, which, mean, w)

@@ -434,15 +434,6 @@ __device__ __forceinline__ void emu_chain_round(const EmuArgs& A, EmuShared& sh,
 }
 
 // ---------------------------------------------------------------- network
-// v from the lane o places further on in the same 16-lane row (row_ror:o)
-template <int O>
-__device__ __forceinline__ double dpp_row_ror(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), 0x120 + O, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), 0x120 + O, 0xf, 0xf, false);
-  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-
 constexpr int kEStages = 4;   // K steps of weight fragments in registers (three loads in flight)
 
 // One pass of a wave over NCB column blocks (cb0 .. cb0 + NCB - 1, two 16-wide

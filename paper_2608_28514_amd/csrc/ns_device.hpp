@@ -308,6 +308,15 @@ __device__ __forceinline__ bool line_in_box(const T* x, const T* v, T t, int d) 
   return ok;
 }
 
+// v of the lane O places further on in the same 16-lane row (DPP row_ror:O).
+template <int O>
+__device__ __forceinline__ double dpp_row_ror(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), 0x120 + O, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), 0x120 + O, 0xf, 0xf, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
 // NaN likelihoods count as -inf (they can never satisfy a hard constraint).
 __device__ __forceinline__ double clean_logL(double v) { return isnan(v) ? -INFINITY : v; }
 
