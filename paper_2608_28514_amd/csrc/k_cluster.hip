@@ -647,9 +647,16 @@ hipError_t launch_cluster(const Shape& sh, const DevBufs& b, double p, int nmin,
     // a root beyond one workgroup's LDS: its passes spread over the device
     // instead of reloading the points chunk by chunk in one workgroup
     if (!b.root_work || !b.root_stats || !b.root_side) return hipErrorInvalidValue;
-    hipError_t e = launch_cluster_split(static_cast<const float*>(b.u), sh.N, sh.d, iters, b.root_stats,
-                                        b.root_stats + 32, b.root_stats + 32 + 32 * 32, b.root_side,
-                                        b.root_work, nullptr, s);
+    // one cooperative launch where the point set is small enough, else the
+    // streaming passes
+    hipError_t e = launch_cluster_split_coop(static_cast<const float*>(b.u), sh.N, sh.d, iters, b.root_stats,
+                                             b.root_stats + 32, b.root_stats + 32 + 32 * 32, b.root_side,
+                                             b.root_work, s);
+    if (e == hipErrorNotSupported) {
+      (void)hipGetLastError();
+      e = launch_cluster_split(static_cast<const float*>(b.u), sh.N, sh.d, iters, b.root_stats, b.root_stats + 32,
+                               b.root_stats + 32 + 32 * 32, b.root_side, b.root_work, nullptr, s);
+    }
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_cluster_root_take, dim3((sh.N + 255) / 256), dim3(256), 0, s, sh.N, sh.d,
                        b.root_stats, b.root_side, b.nodeof, b.count, b.centre, b.cov, b.st);

@@ -48,7 +48,7 @@ constexpr int kCLFirst = kCLGroups / kCLFan;
 struct CLWork {
   CLState st;
   unsigned int tt;                  // finished workgroups of a reduction kernel
-  unsigned int pad0;
+  unsigned int bar;                 // arrivals at the grid barriers of the one-launch split
   double pad[7];
   double part[kCLGroups][kCLPart];  // one partial per workgroup
   double gpart[kCLFirst][kCLPart];  // one partial per group
@@ -666,6 +666,7 @@ __global__ void k_cl_init(CLWork* __restrict__ w) {
   const int t = threadIdx.x;
   if (t == 0) {
     w->tt = 0u;
+    w->bar = 0u;
     w->st.done = 0;
     w->st.passes = 0;
     w->st.iters_used = 0;
@@ -674,6 +675,228 @@ __global__ void k_cl_init(CLWork* __restrict__ w) {
 
 __global__ void k_cl_finish(int* __restrict__ passes, CLWork* __restrict__ w) {
   if (threadIdx.x == 0 && passes) *passes = w->st.passes;
+}
+
+// ---------------------------------------------------------------- one launch
+// A point set of at most kCoopMaxG tiles takes the mean, the two farthest
+// points and the Lloyd passes in one cooperative launch: workgroup g keeps
+// tile g (256 points, the same tiles and the same thread-per-point sums as the
+// streaming passes) in LDS and registers for the whole split, and after each
+// phase the workgroups exchange one partial row each through the workspace
+// and a grid barrier.  Every workgroup adds the rows in workgroup order, so
+// all of them hold the same totals and take the same decisions.  Partial rows
+// alternate between two banks from one exchange to the next, so a row is
+// never rewritten while another workgroup may still read it.
+constexpr int kCoopMaxG = 64;
+constexpr long kCoopSpin = 1L << 24;   // barrier polls before giving up (never reached by a co-resident grid)
+
+// Grid barrier number k (1, 2, ...): the workgroup's writes before it are
+// visible to every workgroup after it.  False after a timeout (s_ok cleared).
+// One release (the arrival) and one acquire (after the wait) per workgroup;
+// the wait itself polls with relaxed loads.
+__device__ __forceinline__ bool coop_barrier(unsigned int* ctr, unsigned int G, unsigned int k, int* s_ok) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    long spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < G * k) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kCoopSpin) { *s_ok = 0; break; }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
+// The sum of column c over rows r0 .. r0 + G - 1 of the partials, in row
+// order, with sixteen loads in flight at a time.
+__device__ __forceinline__ double rows_sum(const CLWork* w, int r0, unsigned int G, int c) {
+  double a = 0.0;
+  for (unsigned int q0 = 0; q0 < G; q0 += 16) {
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = q0 + q < G ? w->part[r0 + q0 + q][c] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (q0 + q < G) a = (q0 + q == 0) ? v[q] : a + v[q];
+  }
+  return a;
+}
+
+// every lane of a 16-lane row ends with the row's sum (DPP rotations)
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_row_ror<8>(v);
+  v += dpp_row_ror<4>(v);
+  v += dpp_row_ror<2>(v);
+  v += dpp_row_ror<1>(v);
+  return v;
+}
+
+// the largest value, lowest index on ties, over the wave
+__device__ __forceinline__ void wave_argmax(double& bv, long& bi) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(bv, o);
+    const long oi = __shfl_xor(bi, o);
+    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+  }
+}
+
+template <int DM>
+__global__ void __launch_bounds__(256)
+k_cl_coop(const float* __restrict__ u, long N, int d, int iters, double* __restrict__ mean,
+          double* __restrict__ centres, unsigned char* __restrict__ side, CLWork* __restrict__ w) {
+  constexpr int QF = tile_quads<DM>();
+  __shared__ __align__(16) float xs[tile_floats<DM>()];
+  __shared__ double red[16][2 * DM + 2];   // one row per 16-lane row of the workgroup
+  __shared__ double cen[2][DM];
+  __shared__ double tot[2 * DM + 2];
+  __shared__ double sv[4];
+  __shared__ long si[4];
+  __shared__ long s_best;
+  __shared__ int s_ok;
+  const unsigned int G = gridDim.x;
+  const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6, ds = d | 1;
+  const int row = t >> 4;            // 16-lane row of the workgroup
+  const bool head = (t & 15) == 0;
+  // a workgroup's sum of column c: the 16 row sums in row order
+  auto wg_sum = [&](int c) {
+    double a = red[0][c];
+    for (int q = 1; q < 16; ++q) a += red[q][c];
+    return a;
+  };
+  const long lo = static_cast<long>(g) * kCLTile, hi = min(N, lo + kCLTile);
+  const int nt = static_cast<int>(hi - lo);
+  const bool mine = t < nt;
+  if (t == 0) s_ok = 1;
+  {
+    float4 r[QF];
+    tile_fetch<QF>(u, lo * d, nt * d, (reinterpret_cast<uintptr_t>(u) & 15) == 0, r);
+    tile_put<QF>(xs, nt * d, d, r);
+  }
+  __syncthreads();
+  double x[DM];
+#pragma unroll
+  for (int i = 0; i < DM; ++i) x[i] = (mine && i < d) ? static_cast<double>(xs[t * ds + i]) : 0.0;
+  unsigned int bk = 0;
+  // ---- mean (the row sums in workgroup order, then / N)
+#pragma unroll
+  for (int i = 0; i < DM; ++i)
+    if (i < d) {
+      const double v = row16_sum(x[i]);
+      if (head) red[row][i] = v;
+    }
+  __syncthreads();
+  if (t < d) w->part[g][t] = wg_sum(t);
+  if (!coop_barrier(&w->bar, G, ++bk, &s_ok)) return;
+  if (t < d) {
+    const double m = rows_sum(w, 0, G, t) / static_cast<double>(N);
+    cen[0][t] = m;
+    if (g == 0) mean[t] = m;
+  }
+  __syncthreads();
+  // ---- the point farthest from the mean, then the one farthest from it
+  // (the reference is cen[0] both times: the mean, then point ia)
+  for (int which = 0; which < 2; ++which) {
+    double bv = -1.0;
+    long bi = 0x7fffffffffffffffL;
+    if (mine) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int i = 0; i < DM; ++i)
+        if (i < d) {
+          const double q = x[i] - cen[0][i];
+          s2 += q * q;
+        }
+      bv = s2;
+      bi = lo + t;
+    }
+    wave_argmax(bv, bi);
+    if (lane == 0) { sv[wv] = bv; si[wv] = bi; }
+    __syncthreads();
+    if (t == 0) {
+      for (int q = 1; q < 4; ++q)
+        if (sv[q] > bv || (sv[q] == bv && si[q] < bi)) { bv = sv[q]; bi = si[q]; }
+      w->pv[which * G + g] = bv;
+      w->pi[which * G + g] = bi;
+    }
+    if (!coop_barrier(&w->bar, G, ++bk, &s_ok)) return;
+    if (t < 64) {
+      // lane q reads the partial of workgroup q (and q + 64 ...), then the
+      // wave takes the largest value, lowest index on ties
+      double v = -1.0;
+      long ix = 0x7fffffffffffffffL;
+      for (unsigned int q = t; q < G; q += 64) {
+        const double pv = w->pv[which * G + q];
+        const long pi = w->pi[which * G + q];
+        if (pv > v || (pv == v && pi < ix)) { v = pv; ix = pi; }
+      }
+      wave_argmax(v, ix);
+      if (t == 0) {
+        s_best = ix;
+        if (g == 0) { if (which == 0) w->st.ia = static_cast<int>(ix); else w->st.ib = static_cast<int>(ix); }
+      }
+    }
+    __syncthreads();
+    // the start centres: ca = point ia (replacing the mean), cb = point ib
+    if (t < d) cen[which][t] = static_cast<double>(u[s_best * d + t]);
+    __syncthreads();
+  }
+  // ---- Lloyd: assign with the current centres (a tie to the first), sum the
+  // sides; stop at a fixed point or after `iters` updates
+  int prev = 0, used = 0;
+  for (int r = 0; r <= iters; ++r) {
+    int sd = 0, ch = 0;
+    if (mine) {
+      double da = 0.0, db = 0.0;
+#pragma unroll
+      for (int i = 0; i < DM; ++i)
+        if (i < d) {
+          const double qa = x[i] - cen[0][i], qb = x[i] - cen[1][i];
+          da += qa * qa;
+          db += qb * qb;
+        }
+      sd = da <= db ? 0 : 1;
+      if (r > 0 && prev != sd) ch = 1;
+      prev = sd;
+    }
+#pragma unroll
+    for (int i = 0; i < DM; ++i)
+      if (i < d) {
+        const double ta = row16_sum(sd ? 0.0 : x[i]), tb = row16_sum(sd ? x[i] : 0.0);
+        if (head) { red[row][i] = ta; red[row][d + i] = tb; }
+      }
+    const double fn = row16_sum(static_cast<double>(sd)), fc = row16_sum(static_cast<double>(ch));
+    if (head) { red[row][2 * d] = fn; red[row][2 * d + 1] = fc; }
+    __syncthreads();
+    const int bank = (r & 1) * static_cast<int>(G);
+    if (t < 2 * d + 2) w->part[bank + g][t] = wg_sum(t);
+    if (!coop_barrier(&w->bar, G, ++bk, &s_ok)) return;
+    if (t < 2 * d + 2) tot[t] = rows_sum(w, bank, G, t);
+    __syncthreads();
+    const double n1v = tot[2 * d], n0v = static_cast<double>(N) - n1v;
+    const bool stop = (r > 0 && tot[2 * d + 1] == 0.0) || r == iters;
+    used = stop ? r : r + 1;
+    if (!stop && t < d) {
+      if (n0v > 0.0) cen[0][t] = tot[t] / n0v;
+      if (n1v > 0.0) cen[1][t] = tot[d + t] / n1v;
+    }
+    __syncthreads();
+    if (stop) {
+      if (g == 0 && t == 0) {
+        w->st.n1 = static_cast<int>(n1v);
+        w->st.n0 = static_cast<int>(n0v);
+        w->st.iters_used = used;
+        w->st.done = 1;
+      }
+      break;
+    }
+  }
+  if (mine) side[lo + t] = static_cast<unsigned char>(prev);
+  if (g == 0 && t < d) {
+    centres[t] = cen[0][t];
+    centres[kMaxD + t] = cen[1][t];
+  }
 }
 
 // Workgroups of 256 threads of kernel k resident at once on the current
@@ -695,6 +918,47 @@ static int lloyd_resident() {
     cache[dev].store(v, std::memory_order_relaxed);
   }
   return v;
+}
+
+// Co-resident workgroups of k_cl_coop<DM> on the current device (cached).
+template <int DM>
+static int coop_resident() {
+  static std::atomic<int> cache[16];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return 0;
+  int v = cache[dev].load(std::memory_order_relaxed);
+  if (v == 0) {
+    int cus = 0, nb = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_cl_coop<DM>), 256, 0) !=
+            hipSuccess)
+      return 0;
+    v = cus * nb;
+    cache[dev].store(v, std::memory_order_relaxed);
+  }
+  return v;
+}
+
+hipError_t launch_cluster_split_coop(const float* u, long N, int d, int iters, double* mean, double* cov,
+                                     double* centres, unsigned char* side, void* work, hipStream_t s) {
+  const long G = (N + kCLTile - 1) / kCLTile;
+  if (N < 2 || d <= 16 || d > kMaxD || iters < 0 || G > kCoopMaxG) return hipErrorNotSupported;
+  const int DM = d <= 24 ? 24 : 32;
+  if ((DM == 24 ? coop_resident<24>() : coop_resident<32>()) < G) return hipErrorNotSupported;
+  CLWork* w = static_cast<CLWork*>(work);
+  hipLaunchKernelGGL(k_cl_init, dim3(1), dim3(64), 0, s, w);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  void* args[] = {const_cast<float**>(&u), &N, &d, &iters, &mean, &centres, &side, &w};
+  e = hipLaunchCooperativeKernel(DM == 24 ? reinterpret_cast<const void*>(k_cl_coop<24>)
+                                          : reinterpret_cast<const void*>(k_cl_coop<32>),
+                                 dim3(static_cast<unsigned>(G)), dim3(256), args, 0, s);
+  if (e != hipSuccess) return e;
+  // the covariance about that mean: the streaming pass, a workgroup per 64 points
+  const int Gc = static_cast<int>(std::min<long>(kCLGroups, std::max<long>(1, (N + 63) / 64)));
+  hipLaunchKernelGGL(k_cl_cov, dim3(Gc), dim3(64), 0, s, u, N, d, mean, w);
+  hipLaunchKernelGGL(k_cl_red_cov, dim3((Gc + kCLFan - 1) / kCLFan), dim3(256), 0, s, N, d, Gc, cov, w);
+  return hipGetLastError();
 }
 
 hipError_t launch_cluster_split(const float* u, long N, int d, int iters, double* mean, double* cov,

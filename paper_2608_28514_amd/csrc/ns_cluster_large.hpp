@@ -12,5 +12,10 @@ size_t cluster_split_work_bytes();
 // streaming passes made over u
 hipError_t launch_cluster_split(const float* u, long N, int d, int iters, double* mean, double* cov,
                                 double* centres, unsigned char* side, void* work, int* passes, hipStream_t s);
+// The same quantities in one cooperative launch (mean, farthest points,
+// Lloyd passes; the covariance pass after it) for 16 < d <= 32 and at most 64
+// tiles of 256 points; hipErrorNotSupported otherwise (use the above).
+hipError_t launch_cluster_split_coop(const float* u, long N, int d, int iters, double* mean, double* cov,
+                                     double* centres, unsigned char* side, void* work, hipStream_t s);
 
 }  // namespace ns
