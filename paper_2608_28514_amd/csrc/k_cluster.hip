@@ -624,9 +624,9 @@ bool cluster_root_split(const Shape& sh) {
 // covariance in the tree's layout, and each point's child (the same
 // quantities the per-node kernel writes for the root).
 __global__ void __launch_bounds__(256)
-k_cluster_root_take(int N, int d, const double* __restrict__ stats, const unsigned char* __restrict__ side,
-                    int* __restrict__ nodeof, int* __restrict__ count, double* __restrict__ centre,
-                    double* __restrict__ cov, const RunState* __restrict__ st) {
+k_cluster_root_take(int N, int d, int children, const double* __restrict__ stats,
+                    const unsigned char* __restrict__ side, int* __restrict__ nodeof, int* __restrict__ count,
+                    double* __restrict__ centre, double* __restrict__ cov, const RunState* __restrict__ st) {
   if (st->done) return;
   const long k = static_cast<long>(blockIdx.x) * 256 + threadIdx.x;
   if (k < N) nodeof[k] = 1 + side[k];
@@ -637,6 +637,20 @@ k_cluster_root_take(int N, int d, const double* __restrict__ stats, const unsign
       const int i = q / d, j = q - i * d;
       cov[i * kMaxD + j] = stats[32 + q];
     }
+  }
+  if (children && blockIdx.x < 2) {
+    // node 1 + c: as the per-node kernel leaves a leaf (mean once it has a
+    // point, covariance once it has two)
+    const int c = blockIdx.x, node = 1 + c;
+    const double* cs = stats + kRootChild;
+    const int cnt = static_cast<int>(cs[c]);
+    if (threadIdx.x == 0) count[node] = cnt;
+    if (cnt > 0 && threadIdx.x < d) centre[node * kMaxD + threadIdx.x] = cs[2 + 32 * c + threadIdx.x];
+    if (cnt >= 2)
+      for (int q = threadIdx.x; q < d * d; q += 256) {
+        const int i = q / d, j = q - i * d;
+        cov[static_cast<long>(node) * kMaxD * kMaxD + i * kMaxD + j] = cs[66 + 1024 * c + q];
+      }
   }
 }
 
@@ -649,20 +663,24 @@ hipError_t launch_cluster(const Shape& sh, const DevBufs& b, double p, int nmin,
     if (!b.root_work || !b.root_stats || !b.root_side) return hipErrorInvalidValue;
     // one cooperative launch where the point set is small enough, else the
     // streaming passes
+    // (a depth-1 tree takes its leaves' statistics from the same launch)
+    const bool leaves = sh.depth == 1;
+    int children = 0;
     hipError_t e = launch_cluster_split_coop(static_cast<const float*>(b.u), sh.N, sh.d, iters, b.root_stats,
                                              b.root_stats + 32, b.root_stats + 32 + 32 * 32, b.root_side,
-                                             b.root_work, s);
+                                             leaves ? b.root_stats + kRootChild : nullptr, b.root_work, s);
+    if (e == hipSuccess && leaves) children = 1;
     if (e == hipErrorNotSupported) {
       (void)hipGetLastError();
       e = launch_cluster_split(static_cast<const float*>(b.u), sh.N, sh.d, iters, b.root_stats, b.root_stats + 32,
                                b.root_stats + 32 + 32 * 32, b.root_side, b.root_work, nullptr, s);
     }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cluster_root_take, dim3((sh.N + 255) / 256), dim3(256), 0, s, sh.N, sh.d,
-                       b.root_stats, b.root_side, b.nodeof, b.count, b.centre, b.cov, b.st);
+    hipLaunchKernelGGL(k_cluster_root_take, dim3(std::max(2, (sh.N + 255) / 256)), dim3(256), 0, s, sh.N, sh.d,
+                       children, b.root_stats, b.root_side, b.nodeof, b.count, b.centre, b.cov, b.st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    level0 = 1;
+    level0 = children ? 2 : 1;
   }
   for (int level = level0; level <= sh.depth; ++level) {
     const dim3 grid(1u << level), block(kCT);

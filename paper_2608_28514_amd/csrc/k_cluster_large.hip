@@ -745,7 +745,8 @@ __device__ __forceinline__ void wave_argmax(double& bv, long& bi) {
 template <int DM>
 __global__ void __launch_bounds__(256)
 k_cl_coop(const float* __restrict__ u, long N, int d, int iters, double* __restrict__ mean,
-          double* __restrict__ centres, unsigned char* __restrict__ side, CLWork* __restrict__ w) {
+          double* __restrict__ centres, unsigned char* __restrict__ side, double* __restrict__ cstats,
+          CLWork* __restrict__ w) {
   constexpr int QF = tile_quads<DM>();
   __shared__ __align__(16) float xs[tile_floats<DM>()];
   __shared__ double red[16][2 * DM + 2];   // one row per 16-lane row of the workgroup
@@ -755,6 +756,8 @@ k_cl_coop(const float* __restrict__ u, long N, int d, int iters, double* __restr
   __shared__ long si[4];
   __shared__ long s_best;
   __shared__ int s_ok;
+  __shared__ unsigned char sside[kCLTile];
+  __shared__ double cmu[2][DM];
   const unsigned int G = gridDim.x;
   const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6, ds = d | 1;
   const int row = t >> 4;            // 16-lane row of the workgroup
@@ -845,6 +848,7 @@ k_cl_coop(const float* __restrict__ u, long N, int d, int iters, double* __restr
   // ---- Lloyd: assign with the current centres (a tie to the first), sum the
   // sides; stop at a fixed point or after `iters` updates
   int prev = 0, used = 0;
+  double n0f = 0.0, n1f = 0.0;
   for (int r = 0; r <= iters; ++r) {
     int sd = 0, ch = 0;
     if (mine) {
@@ -877,6 +881,8 @@ k_cl_coop(const float* __restrict__ u, long N, int d, int iters, double* __restr
     const double n1v = tot[2 * d], n0v = static_cast<double>(N) - n1v;
     const bool stop = (r > 0 && tot[2 * d + 1] == 0.0) || r == iters;
     used = stop ? r : r + 1;
+    n0f = n0v;
+    n1f = n1v;
     if (!stop && t < d) {
       if (n0v > 0.0) cen[0][t] = tot[t] / n0v;
       if (n1v > 0.0) cen[1][t] = tot[d + t] / n1v;
@@ -896,6 +902,51 @@ k_cl_coop(const float* __restrict__ u, long N, int d, int iters, double* __restr
   if (g == 0 && t < d) {
     centres[t] = cen[0][t];
     centres[kMaxD + t] = cen[1][t];
+  }
+  if (cstats == nullptr) return;
+  // ---- the two children (the leaves of a depth-1 tree): count, mean (the
+  // side sums of the final assignment / count) and unbiased covariance about
+  // that mean.  Thread-per-pair sums over the workgroup's points, one partial
+  // row per child and workgroup, added in workgroup order by workgroup 0.
+  if (mine) sside[t] = static_cast<unsigned char>(prev);
+  if (t < d) {
+    cmu[0][t] = n0f > 0.0 ? tot[t] / n0f : 0.0;
+    cmu[1][t] = n1f > 0.0 ? tot[d + t] / n1f : 0.0;
+  }
+  __syncthreads();
+  const int np = d * (d + 1) / 2;
+  for (int p = t; p < 2 * np; p += 256) {
+    const int c = p >= np ? 1 : 0;
+    const int pc = p - c * np;
+    int i = 0, j = pc;
+    while (j > i) { j -= i + 1; ++i; }
+    double acc = 0.0;
+    for (int k = 0; k < nt; ++k)
+      if (sside[k] == c) {
+        const double a = static_cast<double>(xs[k * ds + i]) - cmu[c][i];
+        const double b = static_cast<double>(xs[k * ds + j]) - cmu[c][j];
+        acc += a * b;
+      }
+    w->part[(2 + c) * static_cast<int>(G) + g][pc] = acc;
+  }
+  if (!coop_barrier(&w->bar, G, ++bk, &s_ok)) return;
+  if (g != 0) return;
+  // cstats: counts [0..2), means [2 + 32 c ..), covariances [66 + 1024 c ..) (stride d)
+  if (t < 2) cstats[t] = t == 0 ? n0f : n1f;
+  if (t < d) {
+    cstats[2 + t] = cmu[0][t];
+    cstats[2 + 32 + t] = cmu[1][t];
+  }
+  for (int p = t; p < 2 * np; p += 256) {
+    const int c = p >= np ? 1 : 0;
+    const int pc = p - c * np;
+    int i = 0, j = pc;
+    while (j > i) { j -= i + 1; ++i; }
+    const double nc = c == 0 ? n0f : n1f;
+    const double v = nc >= 2.0 ? rows_sum(w, (2 + c) * static_cast<int>(G), G, pc) / (nc - 1.0) : 0.0;
+    double* C = cstats + 66 + 1024 * c;
+    C[i * d + j] = v;
+    C[j * d + i] = v;
   }
 }
 
@@ -940,7 +991,8 @@ static int coop_resident() {
 }
 
 hipError_t launch_cluster_split_coop(const float* u, long N, int d, int iters, double* mean, double* cov,
-                                     double* centres, unsigned char* side, void* work, hipStream_t s) {
+                                     double* centres, unsigned char* side, double* cstats, void* work,
+                                     hipStream_t s) {
   const long G = (N + kCLTile - 1) / kCLTile;
   if (N < 2 || d <= 16 || d > kMaxD || iters < 0 || G > kCoopMaxG) return hipErrorNotSupported;
   const int DM = d <= 24 ? 24 : 32;
@@ -949,7 +1001,7 @@ hipError_t launch_cluster_split_coop(const float* u, long N, int d, int iters, d
   hipLaunchKernelGGL(k_cl_init, dim3(1), dim3(64), 0, s, w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  void* args[] = {const_cast<float**>(&u), &N, &d, &iters, &mean, &centres, &side, &w};
+  void* args[] = {const_cast<float**>(&u), &N, &d, &iters, &mean, &centres, &side, &cstats, &w};
   e = hipLaunchCooperativeKernel(DM == 24 ? reinterpret_cast<const void*>(k_cl_coop<24>)
                                           : reinterpret_cast<const void*>(k_cl_coop<32>),
                                  dim3(static_cast<unsigned>(G)), dim3(256), args, 0, s);

@@ -15,7 +15,11 @@ hipError_t launch_cluster_split(const float* u, long N, int d, int iters, double
 // The same quantities in one cooperative launch (mean, farthest points,
 // Lloyd passes; the covariance pass after it) for 16 < d <= 32 and at most 64
 // tiles of 256 points; hipErrorNotSupported otherwise (use the above).
+// cstats (may be null): the two sides' statistics as children of the node:
+// counts [0..2), means [2 + 32 c ..), unbiased covariances [66 + 1024 c ..)
+// (d x d, stride d).
 hipError_t launch_cluster_split_coop(const float* u, long N, int d, int iters, double* mean, double* cov,
-                                     double* centres, unsigned char* side, void* work, hipStream_t s);
+                                     double* centres, unsigned char* side, double* cstats, void* work,
+                                     hipStream_t s);
 
 }  // namespace ns

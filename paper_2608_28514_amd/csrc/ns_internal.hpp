@@ -39,7 +39,8 @@ struct DevBufs {
   float* chol_f;        // nodes x 32 x 32
   // the root by the multi-workgroup split (cluster_root_split); null otherwise
   void* root_work;      // split workspace (cluster_split_work_bytes)
-  double* root_stats;   // mean (32), covariance (d x d, stride d; 32 x 32 room), centres (2 x 32)
+  double* root_stats;   // mean (32), covariance (d x d, stride d; 32 x 32 room), centres (2 x 32),
+                        // then the children's counts, means and covariances (kRootChild ..)
   unsigned char* root_side;  // N: side of each point at the root split
   // dead store
   double* dead_u;       // cap x d
@@ -98,7 +99,8 @@ hipError_t launch_cluster(const Shape& sh, const DevBufs& b, double p, int nmin,
 // (FP32 state, a split below the root, and more points than one workgroup
 // holds in LDS); the context then provides root_work, root_stats, root_side.
 bool cluster_root_split(const Shape& sh);
-constexpr int kRootStats = 32 + 32 * 32 + 2 * 32;
+constexpr int kRootChild = 32 + 32 * 32 + 2 * 32;
+constexpr int kRootStats = kRootChild + 2 + 2 * 32 + 2 * 32 * 32;
 // Regularise every node with at least two points (the tree as a whole).
 hipError_t launch_regularise_all(const Shape& sh, const DevBufs& b, int nmin, double eps, hipStream_t s);
 hipError_t launch_final_logZ(const Shape& sh, const DevBufs& b, double* out3, hipStream_t s);
