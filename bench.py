@@ -51,9 +51,9 @@ METRIC = "live-point updates/s at |dlogZ|<2sigma vs oracle, 1 GPU"
 # FETCH_SIZE is scaled by 2.0 and WRITE_SIZE by 1.0 (the factors a plain
 # 256 MiB device copy reads for the same counters); L1-to-L2 read requests
 # are 128-byte lines.  Valid only for the kernel source they were taken on.
-EMU_CHAINS_COUNTERS = {"source_sha256": "cea38a13fc4b306e66a7822605483949bef1aa0d27c4ba1397c1c42d820518fa",
-                       "fetch_kib": 11115.0, "write_kib": 21077.0, "tcp_tcc_read_req": 9.4342e8,
-                       "tcc_hit": 9.4673e8, "tcc_miss": 3.188e5}
+EMU_CHAINS_COUNTERS = {"source_sha256": "8a9168237a0a23a3da73c8632683b3513ae1c591404afa56d04dd9c588f26481",
+                       "fetch_kib": 12326.0, "write_kib": 24277.0, "tcp_tcc_read_req": 9.4506e8,
+                       "tcc_hit": 9.4917e8, "tcc_miss": 3.6046e5}
 L2_CU_PEAK = 64 * 256 * 2.4e9       # MI355X L2-to-CU fill bandwidth: 64 B per clock per CU, 256 CUs
 
 
