@@ -138,11 +138,16 @@ typedef struct {
   int shrink_spec;         /* batched rounds: shrink proposals per round; 8             */
   int fused_chains;        /* network likelihoods: 1 (default) runs a step's chains in
                               one persistent launch whose workgroups evaluate their own
-                              rows through the network (FP32 state, split-bfloat16
-                              layers, stepout_spec <= 4, shrink_spec <= 8, hidden
-                              widths 256 or 512; otherwise, and with the learned
-                              screen, the batched-rounds driver); 0: always the
-                              batched-rounds driver (the same results)              */
+                              rows through the network (FP32 state, split-bfloat16 or
+                              FP32 layers, stepout_spec <= 4, shrink_spec <= 8, hidden
+                              widths 256 or 512, output 256, 512 or 1024; otherwise,
+                              and with the learned screen, the batched-rounds driver);
+                              0: always the batched-rounds driver (the same results;
+                              with FP32 layers the same to FP32 rounding)           */
+  int wait_limit;          /* polls a device-side grid barrier (the one-launch split of
+                              a large tree root) makes before it gives up; 0 (default):
+                              2^24.  A wait that gives up stops the run, and the next
+                              call that synchronises returns NS_EDEVICE              */
 } ns_config;
 
 typedef struct {

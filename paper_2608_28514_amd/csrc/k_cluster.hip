@@ -626,8 +626,13 @@ bool cluster_root_split(const Shape& sh) {
 __global__ void __launch_bounds__(256)
 k_cluster_root_take(int N, int d, int children, const double* __restrict__ stats,
                     const unsigned char* __restrict__ side, int* __restrict__ nodeof, int* __restrict__ count,
-                    double* __restrict__ centre, double* __restrict__ cov, const RunState* __restrict__ st) {
+                    double* __restrict__ centre, double* __restrict__ cov, RunState* __restrict__ st) {
   if (st->done) return;
+  if (st->fault) {
+    // the split gave up waiting: nothing it left is used, the run stops
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 1;
+    return;
+  }
   const long k = static_cast<long>(blockIdx.x) * 256 + threadIdx.x;
   if (k < N) nodeof[k] = 1 + side[k];
   if (blockIdx.x == 0) {
@@ -655,7 +660,7 @@ k_cluster_root_take(int N, int d, int children, const double* __restrict__ stats
 }
 
 hipError_t launch_cluster(const Shape& sh, const DevBufs& b, double p, int nmin, int iters,
-                          double eps, hipStream_t s) {
+                          double eps, int wait_limit, hipStream_t s) {
   int level0 = 0;
   if (cluster_root_split(sh)) {
     // a root beyond one workgroup's LDS: its passes spread over the device
@@ -668,7 +673,8 @@ hipError_t launch_cluster(const Shape& sh, const DevBufs& b, double p, int nmin,
     int children = 0;
     hipError_t e = launch_cluster_split_coop(static_cast<const float*>(b.u), sh.N, sh.d, iters, b.root_stats,
                                              b.root_stats + 32, b.root_stats + 32 + 32 * 32, b.root_side,
-                                             leaves ? b.root_stats + kRootChild : nullptr, b.root_work, s);
+                                             leaves ? b.root_stats + kRootChild : nullptr, b.root_work,
+                                             &b.st->fault, wait_limit, s);
     if (e == hipSuccess && leaves) children = 1;
     if (e == hipErrorNotSupported) {
       (void)hipGetLastError();

@@ -688,20 +688,26 @@ __global__ void k_cl_finish(int* __restrict__ passes, CLWork* __restrict__ w) {
 // alternate between two banks from one exchange to the next, so a row is
 // never rewritten while another workgroup may still read it.
 constexpr int kCoopMaxG = 64;
-constexpr long kCoopSpin = 1L << 24;   // barrier polls before giving up (never reached by a co-resident grid)
+constexpr long kCoopSpin = 1L << 24;   // default barrier polls before giving up (never reached by a co-resident grid)
 
 // Grid barrier number k (1, 2, ...): the workgroup's writes before it are
-// visible to every workgroup after it.  False after a timeout (s_ok cleared).
+// visible to every workgroup after it.  False after `spin` polls without
+// every arrival (s_ok cleared, *fault set when given).
 // One release (the arrival) and one acquire (after the wait) per workgroup;
 // the wait itself polls with relaxed loads.
-__device__ __forceinline__ bool coop_barrier(unsigned int* ctr, unsigned int G, unsigned int k, int* s_ok) {
+__device__ __forceinline__ bool coop_barrier(unsigned int* ctr, unsigned int G, unsigned int k, long spin,
+                                             int* fault, int* s_ok) {
   __syncthreads();
   if (threadIdx.x == 0) {
     __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     long spins = 0;
     while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < G * k) {
       __builtin_amdgcn_s_sleep(1);
-      if (++spins > kCoopSpin) { *s_ok = 0; break; }
+      if (++spins > spin) {
+        *s_ok = 0;
+        if (fault) atomicOr(fault, 1);
+        break;
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
@@ -746,7 +752,7 @@ template <int DM>
 __global__ void __launch_bounds__(256)
 k_cl_coop(const float* __restrict__ u, long N, int d, int iters, double* __restrict__ mean,
           double* __restrict__ centres, unsigned char* __restrict__ side, double* __restrict__ cstats,
-          CLWork* __restrict__ w) {
+          int* __restrict__ fault, long spin, CLWork* __restrict__ w) {
   constexpr int QF = tile_quads<DM>();
   __shared__ __align__(16) float xs[tile_floats<DM>()];
   __shared__ double red[16][2 * DM + 2];   // one row per 16-lane row of the workgroup
@@ -791,7 +797,7 @@ k_cl_coop(const float* __restrict__ u, long N, int d, int iters, double* __restr
     }
   __syncthreads();
   if (t < d) w->part[g][t] = wg_sum(t);
-  if (!coop_barrier(&w->bar, G, ++bk, &s_ok)) return;
+  if (!coop_barrier(&w->bar, G, ++bk, spin, fault, &s_ok)) return;
   if (t < d) {
     const double m = rows_sum(w, 0, G, t) / static_cast<double>(N);
     cen[0][t] = m;
@@ -823,7 +829,7 @@ k_cl_coop(const float* __restrict__ u, long N, int d, int iters, double* __restr
       w->pv[which * G + g] = bv;
       w->pi[which * G + g] = bi;
     }
-    if (!coop_barrier(&w->bar, G, ++bk, &s_ok)) return;
+    if (!coop_barrier(&w->bar, G, ++bk, spin, fault, &s_ok)) return;
     if (t < 64) {
       // lane q reads the partial of workgroup q (and q + 64 ...), then the
       // wave takes the largest value, lowest index on ties
@@ -875,7 +881,7 @@ k_cl_coop(const float* __restrict__ u, long N, int d, int iters, double* __restr
     __syncthreads();
     const int bank = (r & 1) * static_cast<int>(G);
     if (t < 2 * d + 2) w->part[bank + g][t] = wg_sum(t);
-    if (!coop_barrier(&w->bar, G, ++bk, &s_ok)) return;
+    if (!coop_barrier(&w->bar, G, ++bk, spin, fault, &s_ok)) return;
     if (t < 2 * d + 2) tot[t] = rows_sum(w, bank, G, t);
     __syncthreads();
     const double n1v = tot[2 * d], n0v = static_cast<double>(N) - n1v;
@@ -929,7 +935,7 @@ k_cl_coop(const float* __restrict__ u, long N, int d, int iters, double* __restr
       }
     w->part[(2 + c) * static_cast<int>(G) + g][pc] = acc;
   }
-  if (!coop_barrier(&w->bar, G, ++bk, &s_ok)) return;
+  if (!coop_barrier(&w->bar, G, ++bk, spin, fault, &s_ok)) return;
   if (g != 0) return;
   // cstats: counts [0..2), means [2 + 32 c ..), covariances [66 + 1024 c ..) (stride d)
   if (t < 2) cstats[t] = t == 0 ? n0f : n1f;
@@ -992,7 +998,7 @@ static int coop_resident() {
 
 hipError_t launch_cluster_split_coop(const float* u, long N, int d, int iters, double* mean, double* cov,
                                      double* centres, unsigned char* side, double* cstats, void* work,
-                                     hipStream_t s) {
+                                     int* fault, int wait_limit, hipStream_t s) {
   const long G = (N + kCLTile - 1) / kCLTile;
   if (N < 2 || d <= 16 || d > kMaxD || iters < 0 || G > kCoopMaxG) return hipErrorNotSupported;
   const int DM = d <= 24 ? 24 : 32;
@@ -1001,7 +1007,8 @@ hipError_t launch_cluster_split_coop(const float* u, long N, int d, int iters, d
   hipLaunchKernelGGL(k_cl_init, dim3(1), dim3(64), 0, s, w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  void* args[] = {const_cast<float**>(&u), &N, &d, &iters, &mean, &centres, &side, &cstats, &w};
+  long spin = wait_limit > 0 ? wait_limit : kCoopSpin;
+  void* args[] = {const_cast<float**>(&u), &N, &d, &iters, &mean, &centres, &side, &cstats, &fault, &spin, &w};
   e = hipLaunchCooperativeKernel(DM == 24 ? reinterpret_cast<const void*>(k_cl_coop<24>)
                                           : reinterpret_cast<const void*>(k_cl_coop<32>),
                                  dim3(static_cast<unsigned>(G)), dim3(256), args, 0, s);

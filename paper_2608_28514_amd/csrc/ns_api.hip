@@ -280,7 +280,7 @@ static ns_status enqueue_cluster(ns_ctx* c) {
   TimeScope ts(c, NS_TIME_CLUSTER);
   const int nmin = c->nmin;
   NS_TRY(launch_cluster(c->sh, c->b, c->cfg.split_vol_frac, nmin, c->cfg.kmeans_iters,
-                        c->cfg.eig_floor, c->stream));
+                        c->cfg.eig_floor, c->cfg.wait_limit, c->stream));
   c->since_cluster = 0;
   c->tree_partial = true;
   return NS_OK;
@@ -595,6 +595,7 @@ ns_status ns_config_default(ns_config* cfg) {
   cfg->stepout_spec = 4;
   cfg->shrink_spec = 8;
   cfg->fused_chains = 1;
+  cfg->wait_limit = 0;
   return NS_OK;
 }
 
@@ -610,7 +611,7 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
   if (cfg->tree_depth < 0 || cfg->tree_depth > 6) return inval(nullptr, "ns_init: tree_depth in [0, 6]");
   if (cfg->hist_cap < 2 || cfg->hist_cap > 64) return inval(nullptr, "ns_init: hist_cap in [2, 64]");
   if (cfg->slice_steps_per_dim < 1 || cfg->max_shrink < 1 || cfg->max_stepout < 0 ||
-      !(cfg->step_width > 0) || cfg->recluster_every < 1 || cfg->kmeans_iters < 0 ||
+      !(cfg->step_width > 0) || cfg->recluster_every < 1 || cfg->kmeans_iters < 0 || cfg->wait_limit < 0 ||
       cfg->history_iters < 0 || !(cfg->stop_frac > 0) || !(cfg->split_vol_frac >= 0 && cfg->split_vol_frac < 1))
     return inval(nullptr, "ns_init: invalid sampler configuration");
   if (cfg->correction < NS_CORR_NONE || cfg->correction > NS_CORR_HISTORY)
@@ -1011,6 +1012,11 @@ ns_status ns_sync(ns_ctx* c) {
   drain_timing(c);
   NS_TRY(hipMemcpy(c->h_st, c->b.st, sizeof(RunState), hipMemcpyDeviceToHost));
   c->poll_pending = false;
+  if (c->h_st->fault) {
+    c->known_done = true;
+    set_err(c, "a device-side grid barrier gave up waiting (wait_limit); the run was stopped");
+    return NS_EDEVICE;
+  }
   c->issued = c->h_st->step;
   if (c->h_prog) {
     c->h_prog->step = c->h_st->step;

@@ -17,9 +17,11 @@ hipError_t launch_cluster_split(const float* u, long N, int d, int iters, double
 // tiles of 256 points; hipErrorNotSupported otherwise (use the above).
 // cstats (may be null): the two sides' statistics as children of the node:
 // counts [0..2), means [2 + 32 c ..), unbiased covariances [66 + 1024 c ..)
-// (d x d, stride d).
+// (d x d, stride d).  A grid barrier polls at most wait_limit times (0: 2^24);
+// if it gives up, the launch sets *fault (may be null) and its outputs are
+// not valid.
 hipError_t launch_cluster_split_coop(const float* u, long N, int d, int iters, double* mean, double* cov,
                                      double* centres, unsigned char* side, double* cstats, void* work,
-                                     hipStream_t s);
+                                     int* fault, int wait_limit, hipStream_t s);
 
 }  // namespace ns

@@ -353,7 +353,7 @@ struct RunState {
   double logZ;           // running log evidence of the dead points
   double A;              // Z-weighted mean of logL of the dead points
   int32_t done;
-  int32_t pad;
+  int32_t fault;         // nonzero: a bounded device-side wait gave up (the run stops, the host reports it)
   double lmax;           // best live logL after the last step
   // counters
   unsigned long long evals, oob, so_caps, sh_caps, nan_logL, clusterings, screened;

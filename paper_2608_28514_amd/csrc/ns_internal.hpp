@@ -93,8 +93,9 @@ hipError_t launch_correct_arrays(int m, int corr, int K, int T, const double* wl
                                  const double* nlogL, const double* P, const double* hist,
                                  const int* hist_n, int* acc_code, int* acc_hslot, double* acc_logL,
                                  int* rej_code, int* rej_hslot, double* rej_logL, hipStream_t s);
+// wait_limit: polls of a grid barrier before it gives up (0: the default)
 hipError_t launch_cluster(const Shape& sh, const DevBufs& b, double p, int nmin, int iters,
-                          double eps, hipStream_t s);
+                          double eps, int wait_limit, hipStream_t s);
 // True when the root of the tree is computed by the multi-workgroup split
 // (FP32 state, a split below the root, and more points than one workgroup
 // holds in LDS); the context then provides root_work, root_stats, root_side.

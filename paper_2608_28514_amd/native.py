@@ -47,7 +47,8 @@ class NsConfig(C.Structure):
                 ("history_iters", C.c_int), ("hist_cap", C.c_int), ("state_prec", C.c_int),
                 ("stop_frac", C.c_double), ("eig_floor", C.c_double), ("seed", C.c_uint64),
                 ("batch_rounds", C.c_int), ("stepout_spec", C.c_int), ("shrink_spec", C.c_int),
-                ("fused_chains", C.c_int)]
+                ("fused_chains", C.c_int),
+                ("wait_limit", C.c_int)]
 
 
 class NsStats(C.Structure):

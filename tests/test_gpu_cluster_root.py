@@ -64,3 +64,31 @@ def test_two_gaussians_trees_along_a_run_equal_oracle():
     print(f"two-gaussian trees compared: {compared}, with more than one cluster: {splits}")
     assert splits >= 2
     s.close()
+
+
+def test_grid_barrier_that_gives_up_stops_the_run_cleanly():
+    """The one-launch split waits at grid barriers with a bounded number of
+    polls (wait_limit).  With a limit of one poll some barrier usually gives
+    up: the run must then stop and report NS_EDEVICE, and the device must
+    stay usable; if no barrier gave up, the run is the default run."""
+    spec = W.likelihood(5, seed=0)
+    ref = native.Sampler(spec, 4000, prec="bf16x3", state="f32", tree_depth=1, seed=4)
+    ref.run(400, max_steps=2)
+    ref_dead = ref.dead()["logL"]
+    ref.close()
+    faulted = False
+    try:
+        s = native.Sampler(spec, 4000, prec="bf16x3", state="f32", tree_depth=1, seed=4, wait_limit=1)
+        try:
+            s.run(400, max_steps=2)
+            assert np.array_equal(s.dead()["logL"], ref_dead)
+        finally:
+            s.close()
+    except native.NsError as e:
+        assert "grid barrier" in str(e) or "NS_EDEVICE" in str(e)
+        faulted = True
+    print(f"wait_limit=1: a barrier gave up: {faulted}")
+    again = native.Sampler(spec, 4000, prec="bf16x3", state="f32", tree_depth=1, seed=4)
+    again.run(400, max_steps=2)
+    assert np.array_equal(again.dead()["logL"], ref_dead)
+    again.close()
