@@ -135,46 +135,44 @@ __device__ __forceinline__ void emu_direction(const RoundsParams& p, const float
                                               float* zsc, float* v, float* a0, float* us) {
   const int lane = threadIdx.x & 63, d = p.d;
   const uint32_t c3 = (kStreamSlice << 24) | static_cast<uint32_t>(it);
-  // us (may be null): the uniforms of the iteration's first kEP shrink proposals
-  if (us && lane < kEP) {
-    const Draw2 du = uniform2(p.seed, kSlotShrink0 + lane, static_cast<uint32_t>(j), step, c3);
-    us[lane] = static_cast<float>(du.a);
-  }
-  if (2 * lane < d) {
-    const Draw2 dr = uniform2(p.seed, kSlotDir0 + lane, static_cast<uint32_t>(j), step, c3);
+  // the iteration's draws in one pass, one per lane: lane k < 32 the pair of
+  // z_k (slot k / 2; both lanes of a pair draw it), lanes 32 .. the first kEP
+  // shrink uniforms (us, may be null), lane 32 + kEP the stepping-out offset
+  const bool ldir = lane < 32, lsh = lane >= 32 && lane < 32 + kEP;
+  const uint32_t slot = ldir ? kSlotDir0 + (lane >> 1) : (lsh ? kSlotShrink0 + (lane - 32) : kSlotStepout);
+  const Draw2 dr = uniform2(p.seed, slot, static_cast<uint32_t>(j), step, c3);
+  float zk = 0.f;   // z_k on lane k
+  if (ldir && lane < d) {
     const float r = DirMath<float>::r_of(static_cast<float>(dr.a));
     const float ang = static_cast<float>(6.283185307179586) * static_cast<float>(dr.b);
     float sn, csn;
     DirMath<float>::sc(ang, &sn, &csn);
-    zsc[2 * lane] = r * csn;
-    if (2 * lane + 1 < d) zsc[2 * lane + 1] = r * sn;
+    zk = (lane & 1) ? r * sn : r * csn;
   }
-  wave_sync();
-  float zr[kMaxD];
-#pragma unroll
-  for (int i = 0; i < kMaxD; ++i) zr[i] = i < d ? zsc[i] : 0.f;
+  if (us && lsh) us[lane - 32] = static_cast<float>(dr.a);
+  if (lane == 32 + kEP) *a0 = -static_cast<float>(p.w) * static_cast<float>(dr.a);
+  // |z| summed in coordinate order, every lane the same (z_i broadcast from lane i)
   float nrm = 0.f;
 #pragma unroll
   for (int i = 0; i < kMaxD; ++i)
-    if (i < d) nrm += zr[i] * zr[i];
+    if (i < d) {
+      const float zi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zk), i));
+      nrm += zi * zi;
+    }
   nrm = DirMath<float>::sq(nrm);
-  // z / |z|, one division per coordinate (lane i), shared through LDS
-  wave_sync();
-  if (lane < d) zsc[lane] = zsc[lane] / nrm;
-  wave_sync();
+  const float zn = zk / nrm;   // z_k / |z| on lane k
   if (lane < d) {
-    // row `lane` of the factor (conflict-free stride kMaxD + 1)
+    // row `lane` of the factor (LDS, conflict-free stride kMaxD + 1) times z / |z|
     const float* Lr = Lc + lane * (kMaxD + 1);
     float acc = 0.f;
 #pragma unroll
-    for (int k = 0; k < kMaxD; ++k)
-      if (k <= lane) acc += Lr[k] * zsc[k];
+    for (int k = 0; k < kMaxD; ++k) {
+      const float znk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zn), k));
+      if (k < d && k <= lane) acc += Lr[k] * znk;
+    }
     v[lane] = acc;
   }
-  if (lane == 0) {
-    const Draw2 d0 = uniform2(p.seed, kSlotStepout, static_cast<uint32_t>(j), step, c3);
-    *a0 = -static_cast<float>(p.w) * static_cast<float>(d0.a);
-  }
+  (void)zsc;
   wave_sync();
 }
 
