@@ -53,6 +53,7 @@ struct EmuNet {
   int widths[9];
   const __bf16* Wf[8];   // fragment-major W^T; layer 0: three planes of widths[1] x 32
   const float* Wq[8];    // FP32 layers: W^T in 16 x 16 blocks (fragq_index)
+  int w0_planes;         // first-layer weight planes with non-zero values (1 or 3)
   const float* b[8];
   const double* data;
   const double* isig;
@@ -565,7 +566,8 @@ __device__ __forceinline__ void emu_layer(EmuShared& sh, const EmuNet& net, int 
   const int N = net.widths[l + 1];
   const int cb0 = wave * NCB;
   f32x4 acc[kERB][NCB][2];
-  if (FIRST) emu_pass<NCB, 3, 1>(sh.xin, kER * 32, net.Wf[0], static_cast<long>(N) * 32, cb0, acc);
+  if (FIRST && net.w0_planes == 1) emu_pass<NCB, 1, 1>(sh.xin, kER * 32, net.Wf[0], 0L, cb0, acc);
+  else if (FIRST) emu_pass<NCB, 3, 1>(sh.xin, kER * 32, net.Wf[0], static_cast<long>(N) * 32, cb0, acc);
   else emu_pass<NCB, 1, S>(sh.act[(l + 1) & 1], kER * S * 32, net.Wf[l], 0L, cb0, acc);
   if (OUT) {
     emu_store_chi2<NCB>(sh, cb0, sh.bias + boff, acc);
@@ -813,6 +815,7 @@ hipError_t launch_emu_chains(const RoundsParams& p, const NetDev& net, bool f32,
   A.p = p;
   A.net.n_layers = net.n_layers;
   A.net.act = net.act;
+  A.net.w0_planes = net.w0_planes;
   for (int l = 0; l <= net.n_layers; ++l) A.net.widths[l] = net.widths[l];
   for (int l = 0; l < net.n_layers; ++l) {
     A.net.Wf[l] = net.Wf[l];

@@ -771,7 +771,11 @@ hipError_t emu_forward_logL(const NetDev& net, int M, const __bf16* Xf, long xpl
   for (int l = 0; l < L; ++l) {
     const int K = l == 0 ? 32 : net.widths[l], N = net.widths[l + 1];
     const dim3 grid(static_cast<unsigned>(rbs * (N / 32)));
-    if (l == 0) {
+    if (l == 0 && net.w0_planes == 1) {
+      // bfloat16 first-layer weights: the mid and lo weight planes are zero
+      hipLaunchKernelGGL((k_dense_frag<false, 1>), grid, dim3(64), 0, s, M, N, K, in, inplane, net.Wf[0], 0L,
+                         net.b[0], net.act, out, plane, nullptr, nullptr, nullptr, 0L, gate, dM);
+    } else if (l == 0) {
       hipLaunchKernelGGL((k_dense_frag<false, 3>), grid, dim3(64), 0, s, M, N, K, in, inplane, net.Wf[0],
                          static_cast<long>(N) * 32, net.b[0], net.act, out, plane, nullptr, nullptr, nullptr, 0L,
                          gate, dM);

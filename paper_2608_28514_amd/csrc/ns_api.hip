@@ -730,6 +730,9 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
         std::vector<__bf16> wf(static_cast<size_t>(3) * Nn * 32);
         frag_split_host(wt.data(), Nn, K, wf.data());
         NS_INIT_TRY(upload(c, wf.data(), wf.size(), &net.Wf[0]));
+        net.w0_planes = 1;
+        for (size_t q = static_cast<size_t>(Nn) * 32; q < wf.size(); ++q)
+          if (static_cast<float>(wf[q]) != 0.f) { net.w0_planes = 3; break; }
       }
       NS_INIT_TRY(upload(c, bb.data(), bb.size(), &net.b[l]));
       if (lik->prec == NS_FP32 && Nn % 32 == 0 && (l > 0 || K <= 32)) {

@@ -58,6 +58,8 @@ struct NetDev {
                         // hi, mid, lo planes of widths[1] x 32 (inputs padded with zeros)
   const float* Wq[8];   // FP32 W^T in 16 x 16 blocks for the FP32 MFMA (k_emu_chains, FP32
                         // layers); K padded with zeros to a multiple of 16
+  int w0_planes;        // 1 when the first layer's weights are bfloat16 values (mid and lo
+                        // planes zero: their products add exact zeros and are skipped), else 3
 };
 
 // Forward over M rows of X (M x widths[0]); H0/H1 ping-pong buffers of
