@@ -41,9 +41,11 @@ FP64_PEAK = 78.6e12                 # MI355X FP64 vector FLOP/s
 FP32_PEAK = 157.3e12                # MI355X FP32 vector FLOP/s
 BF16_PEAK = 2.5e15                  # MI355X dense BF16 MFMA FLOP/s
 EMU_FLOPS = 2 * (27 * 512 + 512 * 512 * 2 + 512 * 1024)   # one emulator evaluation: 2,124,800
-# MFMA work issued per row by the split-bfloat16 path: nine products of 32
-# (padded) inputs in the first layer, three activation terms afterwards
-EMU_MFMA_ISSUED = 2 * (9 * 32 * 512 + 3 * (512 * 512 * 2 + 512 * 1024))
+# MFMA work issued per row by the split-bfloat16 path: three activation terms
+# against the bfloat16 weights in every layer (the first layer's 32 padded
+# inputs; its weights are bfloat16 values, so their zero split planes are
+# skipped)
+EMU_MFMA_ISSUED = 2 * (3 * 32 * 512 + 3 * (512 * 512 * 2 + 512 * 1024))
 METRIC = "live-point updates/s at |dlogZ|<2sigma vs oracle, 1 GPU"
 # Counters of the persistent chain kernel at N = 4000, m = 400, BF16x3 (the
 # default workload), per launch over its first 12 steps, from
@@ -233,14 +235,14 @@ def bench_emulator(args, np, torch, native, workloads):
     log(f"timed {args.steps} steps: {t_steps:.3f} s, {dead / t_steps:.0f} updates/s, "
         f"{rows} network rows, dominant kernel {k_ms:.1f} ms over {k_launches} launches")
     useful = rows * EMU_FLOPS / (k_ms * 1e-3)
-    # split-bfloat16 layers issue three MFMA per product (nine in the first layer); FP32 layers one
+    # split-bfloat16 layers issue three MFMA per product; FP32 layers one
     issued = rows * (EMU_MFMA_ISSUED if prec == "bf16x3" else EMU_FLOPS) / (k_ms * 1e-3)
     peak = BF16_PEAK if prec.startswith("bf16") else FP32_PEAK
     if fused and prec != "f32":
         kname = ("k_emu_chains: a step's chains in one persistent launch, each workgroup evaluating its "
                  "chains' rows through the four layers (27-512, 512-512, 512-512, 512-1024 + chi^2)")
         note = ("one launch per step, timed by HIP events on the context's stream; useful work 2,124,800 "
-                "FLOP per network row (the split activations issue 3x that on MFMA, 9x in the first layer); "
+                "FLOP per network row (the split activations issue 3x that on MFMA); "
                 "the chain logic runs inside the same launch")
     elif fused:
         kname = ("k_emu_chains<FP32>: a step's chains in one persistent launch, the four layers on the FP32 "
