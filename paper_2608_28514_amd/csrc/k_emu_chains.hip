@@ -152,27 +152,30 @@ __device__ __forceinline__ void emu_direction(const RoundsParams& p, const float
   }
   if (us && lsh) us[lane - 32] = static_cast<float>(dr.a);
   if (lane == 32 + kEP) *a0 = -static_cast<float>(p.w) * static_cast<float>(dr.a);
-  // |z| summed in coordinate order, every lane the same (z_i broadcast from lane i)
+  // |z| summed in coordinate order, every lane the same (z_i broadcast from
+  // lane i).  Lanes d .. 31 hold z = +0, whose squares leave the sum exactly
+  // as it is, so the loop runs over all 32 lanes: no bound test, no branch.
   float nrm = 0.f;
 #pragma unroll
-  for (int i = 0; i < kMaxD; ++i)
-    if (i < d) {
-      const float zi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zk), i));
-      nrm += zi * zi;
-    }
-  nrm = DirMath<float>::sq(nrm);
-  const float zn = zk / nrm;   // z_k / |z| on lane k
-  if (lane < d) {
-    // row `lane` of the factor (LDS, conflict-free stride kMaxD + 1) times z / |z|
-    const float* Lr = Lc + lane * (kMaxD + 1);
-    float acc = 0.f;
-#pragma unroll
-    for (int k = 0; k < kMaxD; ++k) {
-      const float znk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zn), k));
-      if (k < d && k <= lane) acc += Lr[k] * znk;
-    }
-    v[lane] = acc;
+  for (int i = 0; i < kMaxD; ++i) {
+    const float zi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zk), i));
+    nrm += zi * zi;
   }
+  nrm = DirMath<float>::sq(nrm);
+  const float zn = zk / nrm;   // z_k / |z| on lane k (+0 beyond d)
+  // row `lane` of the factor (LDS, conflict-free stride kMaxD + 1) times
+  // z / |z|.  The row holds zeros above the diagonal and beyond d, and a sum
+  // that starts at +0 is unchanged by adding the products +-0 of those zeros,
+  // so all 32 terms are taken: the same value as the triangular sum, with no
+  // branch per term.
+  const float* Lr = Lc + min(lane, kMaxD - 1) * (kMaxD + 1);
+  float acc = 0.f;
+#pragma unroll
+  for (int k = 0; k < kMaxD; ++k) {
+    const float znk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zn), k));
+    acc += Lr[k] * znk;
+  }
+  if (lane < d) v[lane] = acc;
   (void)zsc;
   wave_sync();
 }
