@@ -194,11 +194,13 @@ __device__ __forceinline__ void emu_chain_round(const EmuArgs& A, EmuShared& sh,
   const int fl = round > 0 ? sh.rflag[myrow] : 0;
   double rl = -INFINITY;
   if (round > 0) {
-    // the row's chi^2 partials summed in column-block order
-    const int nbo = A.net.widths[A.net.n_layers] >> 5;
+    // the row's chi^2 partials summed in column-block order.  Blocks past the
+    // output width hold +0 (cleared at the start) and the partials are sums
+    // of squares, so all kEMaxOutB terms give the same sum: a fixed trip
+    // count, every load issued at once.
     double t = 0.0;
-#pragma unroll 8
-    for (int q = 0; q < nbo; ++q) t += sh.part[myrow * kEMaxOutB + q];
+#pragma unroll
+    for (int q = 0; q < kEMaxOutB; ++q) t += sh.part[myrow * kEMaxOutB + q];
     const double v = -0.5 * t;
     rl = (fl == 0 || isnan(v)) ? -INFINITY : v;
   }
@@ -717,6 +719,7 @@ k_emu_chains(EmuArgs A) {
   // inputs beyond the first d columns stay zero; rows of absent chains never
   // reach an output
   for (int q = threadIdx.x; q < 3 * kER * 32; q += 64 * kEW) sh.xin[q] = static_cast<__bf16>(0.f);
+  for (int q = threadIdx.x; q < kER * kEMaxOutB; q += 64 * kEW) sh.part[q] = 0.0;
   if (threadIdx.x < kER) sh.rflag[threadIdx.x] = 0;
   if (threadIdx.x < kEC) sh.us0it[threadIdx.x] = -1;
   if (threadIdx.x < kEC) sh.done[threadIdx.x] = threadIdx.x < nchain ? 0 : 1;
