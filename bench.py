@@ -53,9 +53,9 @@ METRIC = "live-point updates/s at |dlogZ|<2sigma vs oracle, 1 GPU"
 # FETCH_SIZE is scaled by 2.0 and WRITE_SIZE by 1.0 (the factors a plain
 # 256 MiB device copy reads for the same counters); L1-to-L2 read requests
 # are 128-byte lines.  Valid only for the kernel source they were taken on.
-EMU_CHAINS_COUNTERS = {"source_sha256": "8a9168237a0a23a3da73c8632683b3513ae1c591404afa56d04dd9c588f26481",
-                       "fetch_kib": 12326.0, "write_kib": 24277.0, "tcp_tcc_read_req": 9.4506e8,
-                       "tcc_hit": 9.4917e8, "tcc_miss": 3.6046e5}
+EMU_CHAINS_COUNTERS = {"source_sha256": "32cb8e0fea3d760e32d4b95f1c88baf6b6e100929c85599d2b62ac8cdd27fbd9",
+                       "fetch_kib": 10784.9, "write_kib": 19877.4, "tcp_tcc_read_req": 9.1290e8,
+                       "tcc_hit": 9.1744e8, "tcc_miss": 3.1675e5}
 L2_CU_PEAK = 64 * 256 * 2.4e9       # MI355X L2-to-CU fill bandwidth: 64 B per clock per CU, 256 CUs
 
 
