@@ -174,7 +174,11 @@ ns_status ns_config_default(ns_config* cfg);
  * (Sec. 1), their likelihoods, and the first cluster tree (Sec. 2.1).
  * lo, hi: host arrays of d doubles.  hip_stream: a hipStream_t, or NULL for
  * the default (null) stream.
- * On success *out owns all device memory of the context (freed by ns_free). */
+ * On success *out owns all device memory of the context (freed by ns_free).
+ * Debugging aid: with the environment variable NS_FILL_ALLOC=<byte> set, every
+ * device buffer the context allocates (here and in later calls) is filled
+ * with that byte before first use; results do not change, since no call reads
+ * device memory it has not written. */
 ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n_live,
                   const ns_config* cfg, const ns_likelihood* lik, void* hip_stream);
 

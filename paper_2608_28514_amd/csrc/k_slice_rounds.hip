@@ -390,18 +390,21 @@ hipError_t launch_fill_int(int* p, long n, int v, hipStream_t s) {
 
 hipError_t launch_rounds_advance(int round, const RoundsParams& p, const Shape& sh, const DevBufs& b,
                                  const RoundBufs& r, hipStream_t s) {
+  // screen flags exist only where the screen pass writes them every round (a
+  // direct round has no screen pass)
+  const int* sflag = r.xf_direct ? nullptr : r.sflag;
   if (sh.state_f32)
     hipLaunchKernelGGL(k_rounds_advance<float>, dim3(p.m), dim3(64), 0, s, round, p,
                        static_cast<const float*>(b.u), b.logL, b.label, b.chol_f, b.seeds, b.tau, b.LW,
                        static_cast<ChainState<float>*>(r.cs), static_cast<float*>(r.pts), r.xin, r.flag,
-                       r.rlogL, r.rthr, r.sflag, r.gate, static_cast<float*>(b.new_u), b.new_logL, b.chain_stat,
+                       r.rlogL, r.rthr, sflag, r.gate, static_cast<float*>(b.new_u), b.new_logL, b.chain_stat,
                        b.hist_logL, static_cast<float*>(b.hist_u), b.hist_n, b.st, r.xf_direct, r.xf_plane,
                        r.crows, r.cmap, r.cbase, r.xf_direct ? r.xpart : nullptr, r.xpstride, r.xnb, r.xnet_rows);
   else
     hipLaunchKernelGGL(k_rounds_advance<double>, dim3(p.m), dim3(64), 0, s, round, p,
                        static_cast<const double*>(b.u), b.logL, b.label, b.chol, b.seeds, b.tau, b.LW,
                        static_cast<ChainState<double>*>(r.cs), static_cast<double*>(r.pts), r.xin,
-                       r.flag, r.rlogL, r.rthr, r.sflag, r.gate, static_cast<double*>(b.new_u), b.new_logL,
+                       r.flag, r.rlogL, r.rthr, sflag, r.gate, static_cast<double*>(b.new_u), b.new_logL,
                        b.chain_stat,
                        b.hist_logL, static_cast<double*>(b.hist_u), b.hist_n, b.st, r.xf_direct,
                        r.xf_plane, r.crows, r.cmap, r.cbase, r.xf_direct ? r.xpart : nullptr, r.xpstride, r.xnb,

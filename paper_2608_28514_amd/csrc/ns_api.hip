@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <algorithm>
 #include <string>
@@ -177,9 +178,24 @@ static ns_status inval(ns_ctx* c, const std::string& s) {
   return NS_EINVAL;
 }
 
+// Every device buffer of a context comes from here.  NS_FILL_ALLOC=<byte>
+// (a debugging aid) fills each one with that byte before first use, so that
+// a read of memory the library has not written shows up as a changed result
+// instead of depending on what earlier work left there.
+static hipError_t dmalloc(void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) return e;
+  const char* f = std::getenv("NS_FILL_ALLOC");
+  if (f && *f) {
+    e = hipMemset(*p, std::atoi(f) & 0xFF, bytes);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+  }
+  return e;
+}
+
 template <typename T>
 static hipError_t dalloc(T** p, size_t n) {
-  return hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T) + 16);
+  return dmalloc(reinterpret_cast<void**>(p), n * sizeof(T) + 16);
 }
 
 static size_t state_bytes(const ns_ctx* c) { return c->sh.state_f32 ? 4 : 8; }
@@ -202,15 +218,15 @@ static ns_status alloc_batch(ns_ctx* c, int M) {
   NS_TRY(dalloc(&b.tau2, M));
   NS_TRY(dalloc(&b.LW2, M));
   c->sel_ready_m = 0;
-  NS_TRY(hipMalloc(&b.new_u, sb * M * d));
+  NS_TRY(dmalloc(reinterpret_cast<void**>(&b.new_u), sb * M * d));
   NS_TRY(dalloc(&b.new_logL, M));
   NS_TRY(dalloc(&b.chain_stat, kStatW * M));
   NS_TRY(dalloc(&b.hist_logL, static_cast<size_t>(T) * M));
-  NS_TRY(hipMalloc(&b.hist_u, sb * static_cast<size_t>(M) * T * d));
+  NS_TRY(dmalloc(reinterpret_cast<void**>(&b.hist_u), sb * static_cast<size_t>(M) * T * d));
   NS_TRY(dalloc(&b.hist_n, M));
   // draw blocks of the fused slice kernel: M chains x n_iter iterations x (d + kDrawExtra)
   const size_t n_iter = static_cast<size_t>(c->cfg.slice_steps_per_dim) * d;
-  NS_TRY(hipMalloc(&b.draws, sb * static_cast<size_t>(M) * n_iter * (d + kDrawExtra)));
+  NS_TRY(dmalloc(reinterpret_cast<void**>(&b.draws), sb * static_cast<size_t>(M) * n_iter * (d + kDrawExtra)));
   c->M = M;
   return NS_OK;
 }
@@ -771,7 +787,7 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
   DevBufs& b = c->b;
   const size_t sb = sh.state_f32 ? 4 : 8;
   const size_t N = n_live;
-  NS_INIT_HIP(hipMalloc(&b.u, sb * N * d));
+  NS_INIT_HIP(dmalloc(reinterpret_cast<void**>(&b.u), sb * N * d));
   NS_INIT_HIP(dalloc(&b.logL, N));
   NS_INIT_HIP(dalloc(&b.label, N));
   NS_INIT_HIP(dalloc(&b.order, N));
@@ -786,7 +802,7 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
   NS_INIT_HIP(dalloc(&b.chol, static_cast<size_t>(sh.nodes) * kMaxD * kMaxD));
   NS_INIT_HIP(dalloc(&b.chol_f, static_cast<size_t>(sh.nodes) * kMaxD * kMaxD));
   if (cluster_root_split(sh)) {
-    NS_INIT_HIP(hipMalloc(&b.root_work, cluster_split_work_bytes()));
+    NS_INIT_HIP(dmalloc(reinterpret_cast<void**>(&b.root_work), cluster_split_work_bytes()));
     NS_INIT_HIP(dalloc(&b.root_stats, kRootStats));
     NS_INIT_HIP(dalloc(&b.root_side, N));
   }
@@ -840,8 +856,8 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
                          (cfg->max_shrink + rp.sh_spec - 1) / rp.sh_spec + 1;
     rb.gate_cap = rp.n_iter * per_iter + 4;
     const size_t csz = sh.state_f32 ? sizeof(ChainState<float>) : sizeof(ChainState<double>);
-    NS_INIT_HIP(hipMalloc(&rb.cs, csz * 1024));
-    NS_INIT_HIP(hipMalloc(&rb.pts, sb * rb.rows_cap * d));
+    NS_INIT_HIP(dmalloc(reinterpret_cast<void**>(&rb.cs), csz * 1024));
+    NS_INIT_HIP(dmalloc(reinterpret_cast<void**>(&rb.pts), sb * rb.rows_cap * d));
     NS_INIT_HIP(dalloc(&rb.xin, static_cast<size_t>(rb.rows_cap) * d));
     NS_INIT_HIP(dalloc(&rb.flag, rb.rows_cap));
     NS_INIT_HIP(dalloc(&rb.rlogL, rb.rows_cap));
@@ -884,6 +900,7 @@ ns_status ns_init(ns_ctx** out, const double* lo, const double* hi, int d, int n
       NS_INIT_HIP(dalloc(&c->s_norm, kNormLen));
       NS_INIT_HIP(hipMemsetAsync(c->d_sc, 0, sizeof(SurrCounters), c->stream));
       NS_INIT_HIP(hipMemsetAsync(rb.rthr, 0, sizeof(double) * rb.rows_cap, c->stream));
+      NS_INIT_HIP(hipMemsetAsync(rb.sflag, 0, sizeof(int) * rb.rows_cap, c->stream));
       NS_INIT_HIP(hipMemsetAsync(c->s_norm, 0, sizeof(float) * kNormLen, c->stream));
     }
     c->emu_f32 = c->is_mlp && c->mode_first == kF32 && c->mode_rest == kF32;

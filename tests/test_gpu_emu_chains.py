@@ -47,6 +47,21 @@ def test_emulator_chains_identical_to_rounds(N, m, steps):
     _same(*_pair(spec, N, m, steps))
 
 
+def test_runs_do_not_read_stale_device_memory(monkeypatch):
+    """Device memory that earlier work released keeps its bytes, and the
+    library's allocations may receive it: no run may read a buffer it has not
+    written (the plain rounds once read screen flags that only a screen pass
+    writes, and rejected rows wherever a stale word was nonzero).  With
+    NS_FILL_ALLOC every buffer starts as 0xFF bytes (NaN, -1): both drivers
+    must still give the runs they give on zeroed memory."""
+    spec = W.likelihood(4, seed=0)
+    clean = _pair(spec, 200, 40, 30)
+    monkeypatch.setenv("NS_FILL_ALLOC", "255")
+    filled = _pair(spec, 200, 40, 30)
+    _same(*filled)
+    _same(clean[0], filled[0])
+
+
 def test_emulator_chains_256_wide_hidden_layers():
     spec = W.emulator(seed=5, widths=(12, 256, 256, 512), noise_frac=0.02)
     _same(*_pair(spec, 300, 30, 40, seed=2))
