@@ -112,6 +112,9 @@ def main():
     ap.add_argument("--suite", action="store_true",
                     help="Sec. 4 workloads: Gaussians d = 2..32, 2-d Rosenbrock and the 49-mode array vs N_live")
     ap.add_argument("--seeds", type=int, default=0, help="study modes: runs per setting (0: the paper's count)")
+    ap.add_argument("--seed-study", type=int, default=0,
+                    help="emulator (--workload 4/5): this many complete runs, seeds 0 .., one after another; "
+                         "log Z of each against the reference and the spread over seeds")
     ap.add_argument("--concurrent", type=int, default=16, help="study modes: runs at once (ns_run_many)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
@@ -156,6 +159,8 @@ def main():
         return study_clustering(args, np, torch, native, workloads)
     if args.suite:
         return study_suite(args, np, torch, native, workloads)
+    if args.workload in (4, 5) and args.seed_study:
+        return study_emulator_seeds(args, np, torch, native, workloads)
     if args.workload in (4, 5):
         return bench_emulator(args, np, torch, native, workloads)
     if args.workload == 2:
@@ -323,6 +328,38 @@ def bench_emulator(args, np, torch, native, workloads):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_emulator(np, spec, N)
     print(json.dumps(out, default=float))
+
+
+def study_emulator_seeds(args, np, torch, native, workloads):
+    """Complete runs of the emulator workload over seeds 0 .. K-1: each run's
+    log Z against the oracle's reference, the mean's offset in standard errors
+    of the mean, and the run-to-run spread against the single-run sqrt(H/N)."""
+    wl = args.workload
+    prec = args.prec or "bf16x3"
+    N, m = (2000, 200) if wl == 4 else (4000, 400)
+    m = args.m or m
+    spec = workloads.likelihood(wl, seed=0)
+    ref = json.load(open(os.path.join(GOLDEN, "emulator27d_reference.json")))
+    runs = []
+    for sd in range(args.seed_study):
+        s = _emu_sampler(native, spec, N, prec, sd, args, screen=False)
+        native.ns_sync(s.ctx)
+        t0 = time.perf_counter()
+        _finish_run(native, s, m, t0, f"seed {sd}")
+        lz, sig, H = s.logZ()
+        s.close()
+        runs.append({"seed": sd, "logZ": lz, "sigma": sig, "H": H, "wall_s": time.perf_counter() - t0})
+        log(f"seed {sd}: log Z {lz:.4f} +- {sig:.4f} ({(lz - ref['logZ']) / sig:+.2f} sigma)")
+    z = np.array([r["logZ"] for r in runs])
+    sg = np.array([r["sigma"] for r in runs])
+    d = z - ref["logZ"]
+    sd_runs = float(z.std(ddof=1)) if z.size > 1 else float("nan")
+    sem = sd_runs / math.sqrt(z.size) if z.size > 1 else float("nan")
+    print(json.dumps({"study": "emulator evidence over seeds", "workload": wl, "n_live": N, "m": m, "prec": prec,
+                      "reference_logZ": ref["logZ"], "runs": runs, "mean_minus_reference": float(d.mean()),
+                      "sem": sem, "mean_over_sem": float(d.mean()) / sem if z.size > 1 else None,
+                      "run_std": sd_runs, "mean_sqrt_H_over_N": float(sg.mean()),
+                      "within_2sigma": int(np.sum(np.abs(d) < 2 * sg))}, default=float))
 
 
 def cpu_baseline_emulator(np, spec, N):
